@@ -1,0 +1,176 @@
+/*
+ * hcc.h -- C ABI of the hierarchy-cut-code ray-reordering library for MI355X (gfx950).
+ *
+ * The library implements the data-parallel path of Xiang et al., "Faster Ray Tracing
+ * through Hierarchy Cut Code" (2023): build a BVH, choose a cut of it, encode each ray
+ * as a sorting key, sort the rays by key, and trace the reordered rays.
+ *
+ * Conventions for every call
+ *   - Pointers prefixed d_ are device pointers (hipMalloc'd or from a caching allocator)
+ *     owned by the caller; pointers prefixed h_ are host pointers owned by the caller.
+ *   - Handles (hcc_bvh, hcc_cut) are owned by the library and freed with *_destroy.
+ *   - Calls taking a stream enqueue their device work on it and return without waiting,
+ *     unless stated as blocking.  A NULL stream is the default stream.
+ *   - Arguments are validated before any work is queued; on an error nothing is written
+ *     to the out-parameters and hcc_last_error() (per thread) describes the failure.
+ *   - A device fault surfaces as HCC_ERR_DEVICE from the next call that synchronises.
+ *   - hcc_encode, hcc_sort and hcc_trace never allocate memory.
+ *
+ * Data layouts
+ *   triangles : n x 9 float32, [v0.xyz v1.xyz v2.xyz] (36 bytes each)
+ *   rays      : hcc_ray, 32 bytes: origin, tmin, direction, tmax.  The ray is the segment
+ *               o + t d for tmin <= t <= tmax (tmax may be +inf); d need not be unit length.
+ *   keys      : uint32 per ray when key_bits <= 32, else uint64.  Bits >= key_bits are 0.
+ *   hits      : hcc_hit per ray (closest hit), or one uint8 per ray (any hit), both indexed
+ *               by the ORIGINAL ray index whatever permutation the rays were traced in.
+ *   node ids  : internal node i -> i (0 <= i < n-1), leaf j (j-th triangle in Morton
+ *               order) -> n-1+j.  The root is id 0 (also when n == 1: then it is leaf 0).
+ */
+#ifndef HCC_H
+#define HCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HCC_OK = 0,
+    HCC_ERR_INVALID = 1,      /* bad argument (null pointer, size out of range, wrong handle) */
+    HCC_ERR_OOM = 2,          /* device or host allocation failed */
+    HCC_ERR_DEVICE = 3,       /* HIP runtime error or device fault */
+    HCC_ERR_UNSUPPORTED = 4,  /* option not implemented */
+    HCC_ERR_BUDGET = 5        /* request refused by an admission budget */
+} hcc_status;
+
+typedef enum {
+    HCC_KEY_NONE = 0,         /* no key: rays traced in generation order ("NoSort") */
+    HCC_KEY_HCC = 1,          /* hierarchy cut code (Section 4.2, Algorithm 1) */
+    HCC_KEY_TWOPOINT = 2      /* origin + estimated end point 6-D Morton code (Section 3.2) */
+} hcc_key_mode;
+
+typedef enum { HCC_TRACE_CLOSEST = 0, HCC_TRACE_ANY = 1 } hcc_trace_mode;
+
+typedef enum {
+    HCC_STACK_LDS = 0,        /* per-lane traversal stack in LDS (64 entries) */
+    HCC_STACK_SCRATCH = 1,    /* per-lane traversal stack in private (scratch) memory */
+    HCC_STACK_SHORT = 2       /* short stack in registers, spilling to an LDS stack */
+} hcc_stack_mode;
+
+typedef struct hcc_bvh_s* hcc_bvh;
+typedef struct hcc_cut_s* hcc_cut;
+typedef void* hcc_stream;     /* a hipStream_t */
+
+typedef struct hcc_ray { float ox, oy, oz, tmin, dx, dy, dz, tmax; } hcc_ray;
+typedef struct hcc_hit { float t; uint32_t prim; float u, v; } hcc_hit;   /* miss: t = +inf, prim = 0xFFFFFFFF */
+
+/* Launch options of the trace kernel (the autotuner's knobs).  Zero-initialised = defaults. */
+typedef struct hcc_trace_opts {
+    uint32_t block;           /* threads per block: 64, 128 or 256 (0 = 128) */
+    uint32_t stack;           /* hcc_stack_mode */
+    uint32_t xcd_remap;       /* 1 = give each XCD a contiguous range of rays (0 = hardware order) */
+    uint32_t reserved;
+} hcc_trace_opts;
+
+/* ---------------------------------------------------------------------------------------
+ * hcc_build_bvh -- linear BVH over n_tris triangles (Section 3.1: the acceleration structure
+ * the code is defined on; the builder is the Morton-code LBVH, one triangle per leaf).
+ * Steps on the device: scene box; 30-bit Morton code of each triangle's AABB centre
+ * (10 bits per axis, x most significant); stable sort by code; binary radix tree over
+ * (code << 32 | position) (Karras 2012 numbering); bottom-up boxes; HAD with lambda 0.125.
+ * d_tris: device, n_tris x 9 float32, read only during the call.  Blocking: returns when the
+ * BVH is complete.  n_tris must be in [1, 2^28].  *out receives a new handle.
+ */
+hcc_status hcc_build_bvh(const float* d_tris, uint32_t n_tris, hcc_stream stream, hcc_bvh* out);
+
+/* Sizes of a BVH: triangles, nodes (2n-1), scene box (6 floats lo.xyz hi.xyz) and device bytes
+ * held.  Any out pointer may be NULL. */
+hcc_status hcc_bvh_info(hcc_bvh bvh, uint32_t* n_tris, uint32_t* n_nodes, float* h_scene_box6,
+                        size_t* device_bytes);
+
+/* Copy the BVH to host memory (parity checks, inspection).  Blocking.  Any pointer may be NULL.
+ * h_child: (n-1) x 2 uint32 unified ids; h_leaf_prim: n uint32 (triangle index of leaf j);
+ * h_boxes: (2n-1) x 6 float32 by unified id; h_had: (2n-1) float64 HAD (Eq. 1) with the
+ * lambda of the most recent hcc_select_cut (0.125 before the first). */
+hcc_status hcc_bvh_export(hcc_bvh bvh, uint32_t* h_child, uint32_t* h_leaf_prim, float* h_boxes, double* h_had);
+
+void hcc_bvh_destroy(hcc_bvh bvh);
+
+/* ---------------------------------------------------------------------------------------
+ * hcc_select_cut -- choose cut_size nodes of the BVH by Algorithm 2 (Section 4.2.2): a priority
+ * queue keyed by HAD (Eq. 1 with the given lambda; the paper uses 0.125) starts at the root;
+ * while it holds fewer nodes than the target, the largest-HAD node (ties: smaller id) is
+ * removed and replaced by its children, or, if it is a leaf, moved to the cut while the target
+ * shrinks by one.  The cut is ordered by HAD descending (ties: id ascending): cut node 0 owns
+ * the most significant key bit.  A target above the leaf count yields all leaves.
+ * HAD is recomputed on the device when lambda changes; the search runs on the host; the cut's
+ * boxes are uploaded on the stream.  Blocking.  cut_size in [1, 2^20], lambda >= 0 and finite.
+ */
+hcc_status hcc_select_cut(hcc_bvh bvh, uint32_t cut_size, double lambda, hcc_stream stream, hcc_cut* out);
+
+/* Number of nodes in the cut (min(cut_size, n_tris)). */
+hcc_status hcc_cut_info(hcc_cut cut, uint32_t* c_eff);
+
+/* Copy the cut to host memory, in bit order: h_ids (c_eff uint32 unified ids), h_had
+ * (c_eff float64), h_boxes (c_eff x 6 float32).  Any pointer may be NULL.  Blocking. */
+hcc_status hcc_cut_export(hcc_cut cut, uint32_t* h_ids, double* h_had, float* h_boxes);
+
+void hcc_cut_destroy(hcc_cut cut);
+
+/* ---------------------------------------------------------------------------------------
+ * hcc_encode -- one sorting key per ray.
+ *   HCC_KEY_HCC (Algorithm 1, Section 4.2.1): bit (key_bits-1-i) is set iff the ray's segment
+ *     meets the box of cut node i, for i < min(c_eff, key_bits); the cut's boxes are staged in
+ *     LDS once per block.  Requires cut (from this bvh).
+ *   HCC_KEY_TWOPOINT (Section 3.2 / Section 5): 6-D Morton code of the origin and the point at
+ *     distance 0.25 x (largest scene extent) along the normalised direction (clipped to the
+ *     segment); dimension d of (ox,oy,oz,ex,ey,ez) gets key_bits/6 bits plus one if
+ *     d < key_bits % 6, interleaved from the top level down.  cut is ignored.
+ * key_bits in [1, 64]; d_keys: uint32[n] if key_bits <= 32 else uint64[n].  n may be 0.
+ */
+hcc_status hcc_encode(hcc_bvh bvh, hcc_cut cut, hcc_key_mode mode, uint32_t key_bits, const hcc_ray* d_rays,
+                      uint32_t n, void* d_keys, hcc_stream stream);
+
+/* ---------------------------------------------------------------------------------------
+ * hcc_sort -- stable ascending sort of the keys as unsigned integers (Section 4.2.3), output
+ * as the permutation of ray indices (Section 5: the trace kernel fetches rays through it):
+ * d_perm[k] = index of the k-th smallest key, equal keys in input order.  LSD radix sort,
+ * ceil(key_bits/8) passes of 8 bits.  d_sorted_keys (nullable) receives the sorted keys.
+ * d_ws must hold hcc_sort_workspace(n, key_bits) bytes, 256-byte aligned.  n < 2^30.
+ */
+hcc_status hcc_sort_workspace(uint32_t n, uint32_t key_bits, size_t* bytes);
+hcc_status hcc_sort(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm, void* d_sorted_keys,
+                    void* d_ws, size_t ws_bytes, hcc_stream stream);
+
+/* ---------------------------------------------------------------------------------------
+ * hcc_trace -- BVH traversal of n rays taken in the order d_perm (NULL = 0..n-1), Section 5.
+ *   HCC_TRACE_CLOSEST: d_hits[r] = the hit with the smallest (t, triangle index) among all
+ *     triangles met with tmin < t < tmax (Moller-Trumbore, double sided); miss: t = +inf,
+ *     prim = 0xFFFFFFFF, u = v = 0.
+ *   HCC_TRACE_ANY: d_occluded[r] = 1 iff some triangle is met with tmin < t < tmax.
+ * Results are written at the original ray index r = d_perm[k].  opts may be NULL (defaults).
+ */
+hcc_status hcc_trace(hcc_bvh bvh, const hcc_ray* d_rays, const uint32_t* d_perm, uint32_t n, hcc_trace_mode mode,
+                     hcc_hit* d_hits, uint8_t* d_occluded, hcc_stream stream);
+hcc_status hcc_trace_ex(hcc_bvh bvh, const hcc_ray* d_rays, const uint32_t* d_perm, uint32_t n, hcc_trace_mode mode,
+                        hcc_hit* d_hits, uint8_t* d_occluded, const hcc_trace_opts* opts, hcc_stream stream);
+
+/* Measurement variant of hcc_trace (same results, slower): also counts, per ray, the BVH nodes
+ * fetched (d_nodes, nullable) and triangles tested (d_tris, nullable), and per wavefront of 64
+ * consecutive rays in trace order the distinct node and triangle fetches summed over its
+ * lockstep iterations (d_wave_nodes, d_wave_tris: ceil(n/64) uint32 each, required; cleared by
+ * the call).  Always uses 64-lane blocks with the scratch stack and hardware block order. */
+hcc_status hcc_trace_stats(hcc_bvh bvh, const hcc_ray* d_rays, const uint32_t* d_perm, uint32_t n,
+                           hcc_trace_mode mode, hcc_hit* d_hits, uint8_t* d_occluded, uint32_t* d_nodes,
+                           uint32_t* d_tris, uint32_t* d_wave_nodes, uint32_t* d_wave_tris, hcc_stream stream);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char* hcc_last_error(void);
+const char* hcc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HCC_H */

@@ -1,0 +1,251 @@
+"""Python binding of the gfx950 hierarchy-cut-code library (``libhcc.so``).
+
+Argument marshalling only: every step of the path runs in the library's HIP kernels;
+PyTorch provides device memory and the stream.  The C declarations and their
+documentation are in ``include/hcc.h``.  If the library has not been built this
+module raises on import -- there is no fallback.
+
+Tensor conventions (all on the current CUDA/HIP device):
+  triangles: (N, 9) float32          rays: (R, 8) float32 [ox oy oz tmin dx dy dz tmax]
+  keys: int32 (key_bits <= 32) or int64 tensors holding the unsigned key bits
+  perm: int32 tensor holding uint32 ray indices
+  closest hits: (R, 4) float32 = (t, prim bits, u, v); ``hits_prim`` views the prim ids
+  any hits: (R,) uint8
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+__all__ = [
+    "lib", "HCCError", "BVH", "Cut", "build_bvh", "select_cut", "encode", "sort", "sort_workspace_bytes",
+    "trace", "trace_stats", "hits_prim", "KEY_HCC", "KEY_TWOPOINT", "STACK_LDS", "STACK_SCRATCH",
+    "STACK_SHORT", "TraceOpts", "LIB_PATH",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhcc.so")
+
+KEY_NONE, KEY_HCC, KEY_TWOPOINT = 0, 1, 2
+CLOSEST, ANY = 0, 1
+STACK_LDS, STACK_SCRATCH, STACK_SHORT = 0, 1, 2
+_STATUS = {0: "HCC_OK", 1: "HCC_ERR_INVALID", 2: "HCC_ERR_OOM", 3: "HCC_ERR_DEVICE", 4: "HCC_ERR_UNSUPPORTED",
+           5: "HCC_ERR_BUDGET"}
+
+
+class HCCError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class TraceOpts(C.Structure):
+    _fields_ = [("block", C.c_uint32), ("stack", C.c_uint32), ("xcd_remap", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2305_16652_amd/build.py "
+                      "(or __graft_entry__.build()); there is no fallback path")
+lib = C.CDLL(LIB_PATH)
+
+_P = C.c_void_p
+_U32 = C.c_uint32
+_H = C.c_void_p
+_SIGS = {
+    "hcc_build_bvh": [_P, _U32, _P, C.POINTER(_H)],
+    "hcc_bvh_info": [_H, C.POINTER(_U32), C.POINTER(_U32), _P, C.POINTER(C.c_size_t)],
+    "hcc_bvh_export": [_H, _P, _P, _P, _P],
+    "hcc_select_cut": [_H, _U32, C.c_double, _P, C.POINTER(_H)],
+    "hcc_cut_info": [_H, C.POINTER(_U32)],
+    "hcc_cut_export": [_H, _P, _P, _P],
+    "hcc_encode": [_H, _H, C.c_int, _U32, _P, _U32, _P, _P],
+    "hcc_sort_workspace": [_U32, _U32, C.POINTER(C.c_size_t)],
+    "hcc_sort": [_P, _U32, _U32, _P, _P, _P, C.c_size_t, _P],
+    "hcc_trace": [_H, _P, _P, _U32, C.c_int, _P, _P, _P],
+    "hcc_trace_ex": [_H, _P, _P, _U32, C.c_int, _P, _P, C.POINTER(TraceOpts), _P],
+    "hcc_trace_stats": [_H, _P, _P, _U32, C.c_int, _P, _P, _P, _P, _P, _P, _P],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+lib.hcc_bvh_destroy.argtypes = [_H]
+lib.hcc_bvh_destroy.restype = None
+lib.hcc_cut_destroy.argtypes = [_H]
+lib.hcc_cut_destroy.restype = None
+lib.hcc_last_error.restype = C.c_char_p
+lib.hcc_version.restype = C.c_char_p
+
+
+def _check(status: int):
+    if status != 0:
+        raise HCCError(status, lib.hcc_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _key_dtype(key_bits: int):
+    return torch.int32 if key_bits <= 32 else torch.int64
+
+
+class BVH:
+    """Library-owned BVH handle (immutable after the build)."""
+
+    def __init__(self, handle: int, tris: torch.Tensor):
+        self._h = C.c_void_p(handle)
+        self.tris = tris                      # kept alive only for callers' convenience
+        n, nodes, size = _U32(), _U32(), C.c_size_t()
+        box = (C.c_float * 6)()
+        _check(lib.hcc_bvh_info(self._h, C.byref(n), C.byref(nodes), box, C.byref(size)))
+        self.n = n.value
+        self.n_nodes = nodes.value
+        self.scene_box = list(box)
+        self.device_bytes = size.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self):
+        """(child (n-1,2) u32, leaf_prim (n,) u32, boxes (2n-1,6) f32, had (2n-1,) f64) as numpy."""
+        import numpy as np
+        n = self.n
+        child = np.zeros((max(n - 1, 0), 2), np.uint32)
+        leaf = np.empty(n, np.uint32)
+        boxes = np.empty((2 * n - 1, 6), np.float32)
+        had = np.empty(2 * n - 1, np.float64)
+        _check(lib.hcc_bvh_export(self._h, child.ctypes.data_as(_P), leaf.ctypes.data_as(_P),
+                                  boxes.ctypes.data_as(_P), had.ctypes.data_as(_P)))
+        return child, leaf, boxes, had
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.hcc_bvh_destroy(h)
+            self._h = C.c_void_p(0)
+
+
+class Cut:
+    def __init__(self, handle: int, bvh: BVH):
+        self._h = C.c_void_p(handle)
+        self.bvh = bvh
+        c = _U32()
+        _check(lib.hcc_cut_info(self._h, C.byref(c)))
+        self.c_eff = c.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self):
+        import numpy as np
+        ids = np.empty(self.c_eff, np.uint32)
+        had = np.empty(self.c_eff, np.float64)
+        boxes = np.empty((self.c_eff, 6), np.float32)
+        _check(lib.hcc_cut_export(self._h, ids.ctypes.data_as(_P), had.ctypes.data_as(_P),
+                                  boxes.ctypes.data_as(_P)))
+        return ids, had, boxes
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.hcc_cut_destroy(h)
+            self._h = C.c_void_p(0)
+
+
+def build_bvh(tris: torch.Tensor, stream=None) -> BVH:
+    if tris.dtype != torch.float32 or tris.dim() != 2 or tris.shape[1] != 9:
+        raise ValueError("triangles must be an (N, 9) float32 tensor")
+    h = _H()
+    _check(lib.hcc_build_bvh(_dptr(tris), tris.shape[0], _stream(stream), C.byref(h)))
+    return BVH(h.value, tris)
+
+
+def select_cut(bvh: BVH, cut_size: int, lam: float = 0.125, stream=None) -> Cut:
+    h = _H()
+    _check(lib.hcc_select_cut(bvh.handle, cut_size, float(lam), _stream(stream), C.byref(h)))
+    return Cut(h.value, bvh)
+
+
+def _check_rays(rays: torch.Tensor):
+    if rays.dtype != torch.float32 or rays.dim() != 2 or rays.shape[1] != 8:
+        raise ValueError("rays must be an (R, 8) float32 tensor")
+
+
+def encode(bvh: BVH, cut: Cut | None, mode: int, key_bits: int, rays: torch.Tensor, out=None,
+           stream=None) -> torch.Tensor:
+    _check_rays(rays)
+    n = rays.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=_key_dtype(key_bits), device=rays.device)
+    _check(lib.hcc_encode(bvh.handle, cut.handle if cut is not None else None, mode, key_bits, _dptr(rays), n,
+                          _dptr(out), _stream(stream)))
+    return out
+
+
+def sort_workspace_bytes(n: int, key_bits: int) -> int:
+    b = C.c_size_t()
+    _check(lib.hcc_sort_workspace(n, key_bits, C.byref(b)))
+    return b.value
+
+
+def sort(keys: torch.Tensor, key_bits: int, perm=None, sorted_keys=None, ws=None, stream=None) -> torch.Tensor:
+    n = keys.shape[0]
+    if perm is None:
+        perm = torch.empty(n, dtype=torch.int32, device=keys.device)
+    need = sort_workspace_bytes(n, key_bits)
+    if ws is None:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=keys.device)
+    _check(lib.hcc_sort(_dptr(keys), key_bits, n, _dptr(perm), _dptr(sorted_keys), _dptr(ws), ws.numel(),
+                        _stream(stream)))
+    return perm
+
+
+def trace(bvh: BVH, rays: torch.Tensor, perm=None, closest: bool = True, out=None, opts: TraceOpts | None = None,
+          stream=None) -> torch.Tensor:
+    _check_rays(rays)
+    n = rays.shape[0]
+    if out is None:
+        out = (torch.empty((n, 4), dtype=torch.float32, device=rays.device) if closest
+               else torch.empty(n, dtype=torch.uint8, device=rays.device))
+    hits, occ = (out, None) if closest else (None, out)
+    _check(lib.hcc_trace_ex(bvh.handle, _dptr(rays), _dptr(perm), n, CLOSEST if closest else ANY, _dptr(hits),
+                            _dptr(occ), C.byref(opts) if opts is not None else None, _stream(stream)))
+    return out
+
+
+def trace_stats(bvh: BVH, rays: torch.Tensor, perm=None, closest: bool = True, stream=None):
+    """Trace with per-ray and per-wavefront fetch counters (measurement only)."""
+    _check_rays(rays)
+    n = rays.shape[0]
+    dev = rays.device
+    out = (torch.empty((n, 4), dtype=torch.float32, device=dev) if closest
+           else torch.empty(n, dtype=torch.uint8, device=dev))
+    hits, occ = (out, None) if closest else (None, out)
+    nodes = torch.empty(n, dtype=torch.int32, device=dev)
+    tris = torch.empty(n, dtype=torch.int32, device=dev)
+    waves = (n + 63) // 64
+    wn = torch.empty(max(waves, 1), dtype=torch.int32, device=dev)
+    wt = torch.empty(max(waves, 1), dtype=torch.int32, device=dev)
+    _check(lib.hcc_trace_stats(bvh.handle, _dptr(rays), _dptr(perm), n, CLOSEST if closest else ANY, _dptr(hits),
+                               _dptr(occ), _dptr(nodes), _dptr(tris), _dptr(wn), _dptr(wt), _stream(stream)))
+    return out, nodes, tris, wn[:waves], wt[:waves]
+
+
+def hits_prim(hits: torch.Tensor) -> torch.Tensor:
+    """The prim-id column of closest-hit results as int32 (0xFFFFFFFF shows as -1)."""
+    return hits[:, 1].contiguous().view(torch.int32)

@@ -1,0 +1,300 @@
+// C ABI entry points: argument validation, handle management, the host-side cut search
+// (Algorithm 2), and dispatch to the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "hcc_internal.h"
+
+namespace hcc {
+
+// defined in the kernel translation units
+hcc_status build_bvh(const float* d_tris, uint32_t n, hipStream_t stream, hcc_bvh_s** out);
+void free_bvh(hcc_bvh_s* b);
+hcc_status recompute_had(hcc_bvh_s* b, double lambda, hipStream_t stream);
+hcc_status encode_hcc(const hcc_cut_s* cut, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
+                      hipStream_t stream);
+hcc_status encode_twopoint(const hcc_bvh_s* bvh, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n,
+                           void* d_keys, hipStream_t stream);
+hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
+                 hcc_hit* hits, uint8_t* occ, const hcc_trace_opts& o, hipStream_t s);
+hcc_status trace_stats(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
+                       hcc_hit* hits, uint8_t* occ, uint32_t* cn, uint32_t* ct, uint32_t* wn, uint32_t* wt,
+                       hipStream_t s);
+hcc_status fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+
+namespace {
+thread_local std::string g_error;
+}
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+hcc_status fail(hcc_status st, const std::string& msg) {
+    g_error = msg;
+    return st;
+}
+
+hcc_status hip_fail(hipError_t e, const char* what) {
+    g_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? HCC_ERR_OOM : HCC_ERR_DEVICE;
+}
+
+namespace {
+
+bool valid_bvh(const hcc_bvh_s* b) { return b && b->magic == 0x6863636276680001ull; }
+bool valid_cut(const hcc_cut_s* c) { return c && c->magic == 0x6863636375740001ull; }
+
+hcc_status ensure_host_mirror(hcc_bvh_s* b, hipStream_t stream) {
+    if (b->h_had_lambda == b->had_lambda && b->h_had.size() == 2 * (size_t)b->n - 1) return HCC_OK;
+    b->h_child.resize(2 * (size_t)b->n_int);
+    b->h_had.resize(2 * (size_t)b->n - 1);
+    if (b->n_int)
+        HCC_HIP(hipMemcpyAsync(b->h_child.data(), b->child, sizeof(uint32_t) * b->h_child.size(),
+                               hipMemcpyDeviceToHost, stream));
+    HCC_HIP(hipMemcpyAsync(b->h_had.data(), b->had, sizeof(double) * b->h_had.size(), hipMemcpyDeviceToHost, stream));
+    HCC_HIP(hipStreamSynchronize(stream));
+    b->h_had_lambda = b->had_lambda;
+    return HCC_OK;
+}
+
+// Algorithm 2 with a binary heap ordered by (HAD descending, id ascending).
+std::vector<uint32_t> cut_search(const hcc_bvh_s* b, uint32_t cut_size) {
+    const std::vector<double>& had = b->h_had;
+    auto lower = [&](uint32_t x, uint32_t y) {   // true if x has lower priority than y
+        if (had[x] != had[y]) return had[x] < had[y];
+        return x > y;
+    };
+    std::priority_queue<uint32_t, std::vector<uint32_t>, decltype(lower)> q(lower);
+    std::vector<uint32_t> cut;
+    int64_t max_q = cut_size;
+    q.push(0);
+    while ((int64_t)q.size() < max_q && !q.empty()) {
+        const uint32_t node = q.top();
+        q.pop();
+        if (b->n_int == 0 || node >= b->n_int) {
+            cut.push_back(node);
+            --max_q;
+        } else {
+            q.push(b->h_child[2 * (size_t)node]);
+            q.push(b->h_child[2 * (size_t)node + 1]);
+        }
+    }
+    while (!q.empty()) {
+        cut.push_back(q.top());
+        q.pop();
+    }
+    std::sort(cut.begin(), cut.end(), [&](uint32_t x, uint32_t y) {
+        if (had[x] != had[y]) return had[x] > had[y];
+        return x < y;
+    });
+    return cut;
+}
+
+inline hipStream_t S(hcc_stream s) { return (hipStream_t)s; }
+
+}  // namespace
+}  // namespace hcc
+
+using namespace hcc;
+
+extern "C" {
+
+__attribute__((visibility("default"))) const char* hcc_last_error(void) { return g_error.c_str(); }
+
+__attribute__((visibility("default"))) const char* hcc_version(void) { return "hcc-gfx950 0.1"; }
+
+__attribute__((visibility("default"))) hcc_status hcc_build_bvh(const float* d_tris, uint32_t n_tris,
+                                                                hcc_stream stream, hcc_bvh* out) {
+    if (!d_tris || !out) return fail(HCC_ERR_INVALID, "hcc_build_bvh: null pointer");
+    if (n_tris == 0 || n_tris > (1u << 28)) return fail(HCC_ERR_INVALID, "hcc_build_bvh: n_tris must be in [1, 2^28]");
+    hcc_bvh_s* b = nullptr;
+    hcc_status st = build_bvh(d_tris, n_tris, S(stream), &b);
+    if (st != HCC_OK) return st;
+    *out = b;
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_bvh_info(hcc_bvh bvh, uint32_t* n_tris, uint32_t* n_nodes,
+                                                               float* h_scene_box6, size_t* device_bytes) {
+    if (!valid_bvh(bvh)) return fail(HCC_ERR_INVALID, "hcc_bvh_info: invalid handle");
+    if (n_tris) *n_tris = bvh->n;
+    if (n_nodes) *n_nodes = 2 * bvh->n - 1;
+    if (h_scene_box6) std::memcpy(h_scene_box6, bvh->scene_box, sizeof(bvh->scene_box));
+    if (device_bytes) *device_bytes = bvh->bytes;
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_bvh_export(hcc_bvh bvh, uint32_t* h_child, uint32_t* h_leaf_prim,
+                                                                 float* h_boxes, double* h_had) {
+    if (!valid_bvh(bvh)) return fail(HCC_ERR_INVALID, "hcc_bvh_export: invalid handle");
+    const size_t nn = 2 * (size_t)bvh->n - 1;
+    if (h_child && bvh->n_int)
+        HCC_HIP(hipMemcpy(h_child, bvh->child, sizeof(uint32_t) * 2 * bvh->n_int, hipMemcpyDeviceToHost));
+    if (h_leaf_prim) HCC_HIP(hipMemcpy(h_leaf_prim, bvh->leaf_prim, sizeof(uint32_t) * bvh->n, hipMemcpyDeviceToHost));
+    if (h_boxes) HCC_HIP(hipMemcpy(h_boxes, bvh->boxes, sizeof(float) * 6 * nn, hipMemcpyDeviceToHost));
+    if (h_had) HCC_HIP(hipMemcpy(h_had, bvh->had, sizeof(double) * nn, hipMemcpyDeviceToHost));
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) void hcc_bvh_destroy(hcc_bvh bvh) {
+    if (valid_bvh(bvh)) free_bvh(bvh);
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_select_cut(hcc_bvh bvh, uint32_t cut_size, double lambda,
+                                                                 hcc_stream stream, hcc_cut* out) {
+    if (!valid_bvh(bvh) || !out) return fail(HCC_ERR_INVALID, "hcc_select_cut: invalid handle or null out");
+    if (cut_size == 0 || cut_size > (1u << 20)) return fail(HCC_ERR_INVALID, "hcc_select_cut: cut_size must be in [1, 2^20]");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(HCC_ERR_INVALID, "hcc_select_cut: lambda must be finite and >= 0");
+    hcc_status st;
+    if (lambda != bvh->had_lambda) {
+        st = recompute_had(bvh, lambda, S(stream));
+        if (st != HCC_OK) return st;
+    }
+    st = ensure_host_mirror(bvh, S(stream));
+    if (st != HCC_OK) return st;
+    std::vector<uint32_t> ids = cut_search(bvh, cut_size);
+    hcc_cut_s* c = new hcc_cut_s();
+    c->bvh = bvh;
+    c->c_eff = (uint32_t)ids.size();
+    c->ids = ids;
+    c->had.resize(ids.size());
+    c->boxes.resize(ids.size() * 6);
+    std::vector<float> all(6 * (2 * (size_t)bvh->n - 1));
+    hipError_t e = hipMemcpy(all.data(), bvh->boxes, sizeof(float) * all.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hcc_select_cut: box copy");
+    }
+    std::vector<CutBox> up(ids.size());
+    for (size_t i = 0; i < ids.size(); ++i) {
+        c->had[i] = bvh->h_had[ids[i]];
+        const float* bx = &all[6 * (size_t)ids[i]];
+        std::memcpy(&c->boxes[6 * i], bx, 6 * sizeof(float));
+        up[i].lo = make_float4(bx[0], bx[1], bx[2], 0.0f);
+        up[i].hi = make_float4(bx[3], bx[4], bx[5], 0.0f);
+    }
+    e = hipMalloc((void**)&c->d_boxes, sizeof(CutBox) * std::max<size_t>(1, up.size()));
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hcc_select_cut: hipMalloc");
+    }
+    e = hipMemcpyAsync(c->d_boxes, up.data(), sizeof(CutBox) * up.size(), hipMemcpyHostToDevice, S(stream));
+    if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
+    if (e != hipSuccess) {
+        (void)hipFree(c->d_boxes);
+        delete c;
+        return hip_fail(e, "hcc_select_cut: upload");
+    }
+    *out = c;
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_cut_info(hcc_cut cut, uint32_t* c_eff) {
+    if (!valid_cut(cut) || !c_eff) return fail(HCC_ERR_INVALID, "hcc_cut_info: invalid handle");
+    *c_eff = cut->c_eff;
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_cut_export(hcc_cut cut, uint32_t* h_ids, double* h_had,
+                                                                 float* h_boxes) {
+    if (!valid_cut(cut)) return fail(HCC_ERR_INVALID, "hcc_cut_export: invalid handle");
+    if (h_ids) std::memcpy(h_ids, cut->ids.data(), sizeof(uint32_t) * cut->c_eff);
+    if (h_had) std::memcpy(h_had, cut->had.data(), sizeof(double) * cut->c_eff);
+    if (h_boxes) std::memcpy(h_boxes, cut->boxes.data(), sizeof(float) * 6 * cut->c_eff);
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) void hcc_cut_destroy(hcc_cut cut) {
+    if (!valid_cut(cut)) return;
+    (void)hipFree(cut->d_boxes);
+    cut->magic = 0;
+    delete cut;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_encode(hcc_bvh bvh, hcc_cut cut, hcc_key_mode mode,
+                                                             uint32_t key_bits, const hcc_ray* d_rays, uint32_t n,
+                                                             void* d_keys, hcc_stream stream) {
+    if (!valid_bvh(bvh)) return fail(HCC_ERR_INVALID, "hcc_encode: invalid bvh handle");
+    if (key_bits < 1 || key_bits > 64) return fail(HCC_ERR_INVALID, "hcc_encode: key_bits must be in [1, 64]");
+    if (n == 0) return HCC_OK;
+    if (!d_rays || !d_keys) return fail(HCC_ERR_INVALID, "hcc_encode: null pointer");
+    switch (mode) {
+        case HCC_KEY_HCC:
+            if (!valid_cut(cut)) return fail(HCC_ERR_INVALID, "hcc_encode: HCC needs a cut");
+            if (cut->bvh != bvh) return fail(HCC_ERR_INVALID, "hcc_encode: cut belongs to another BVH");
+            return encode_hcc(cut, key_bits, d_rays, n, d_keys, S(stream));
+        case HCC_KEY_TWOPOINT:
+            return encode_twopoint(bvh, key_bits, d_rays, n, d_keys, S(stream));
+        default:
+            return fail(HCC_ERR_INVALID, "hcc_encode: mode must be HCC_KEY_HCC or HCC_KEY_TWOPOINT");
+    }
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_sort_workspace(uint32_t n, uint32_t key_bits, size_t* bytes) {
+    if (!bytes) return fail(HCC_ERR_INVALID, "hcc_sort_workspace: null pointer");
+    if (key_bits < 1 || key_bits > 64) return fail(HCC_ERR_INVALID, "hcc_sort_workspace: key_bits must be in [1, 64]");
+    if (n >= (1u << 30)) return fail(HCC_ERR_INVALID, "hcc_sort_workspace: n must be below 2^30");
+    *bytes = sort_workspace_bytes(n, key_bits);
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_sort(const void* d_keys, uint32_t key_bits, uint32_t n,
+                                                           uint32_t* d_perm, void* d_sorted_keys, void* d_ws,
+                                                           size_t ws_bytes, hcc_stream stream) {
+    return radix_sort(d_keys, key_bits, n, d_perm, d_sorted_keys, nullptr, d_ws, ws_bytes, S(stream));
+}
+
+static hcc_status check_trace(hcc_bvh bvh, const hcc_ray* d_rays, uint32_t n, hcc_trace_mode mode, hcc_hit* d_hits,
+                              uint8_t* d_occluded) {
+    if (!valid_bvh(bvh)) return fail(HCC_ERR_INVALID, "hcc_trace: invalid bvh handle");
+    if (mode != HCC_TRACE_CLOSEST && mode != HCC_TRACE_ANY) return fail(HCC_ERR_INVALID, "hcc_trace: bad mode");
+    if (n == 0) return HCC_OK;
+    if (!d_rays) return fail(HCC_ERR_INVALID, "hcc_trace: null rays");
+    if (mode == HCC_TRACE_CLOSEST && !d_hits) return fail(HCC_ERR_INVALID, "hcc_trace: closest hit needs d_hits");
+    if (mode == HCC_TRACE_ANY && !d_occluded) return fail(HCC_ERR_INVALID, "hcc_trace: any hit needs d_occluded");
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_trace_ex(hcc_bvh bvh, const hcc_ray* d_rays,
+                                                               const uint32_t* d_perm, uint32_t n, hcc_trace_mode mode,
+                                                               hcc_hit* d_hits, uint8_t* d_occluded,
+                                                               const hcc_trace_opts* opts, hcc_stream stream) {
+    hcc_status st = check_trace(bvh, d_rays, n, mode, d_hits, d_occluded);
+    if (st != HCC_OK || n == 0) return st;
+    hcc_trace_opts o{};
+    if (opts) o = *opts;
+    return trace(bvh, d_rays, d_perm, n, mode == HCC_TRACE_CLOSEST, d_hits, d_occluded, o, S(stream));
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_trace(hcc_bvh bvh, const hcc_ray* d_rays, const uint32_t* d_perm,
+                                                            uint32_t n, hcc_trace_mode mode, hcc_hit* d_hits,
+                                                            uint8_t* d_occluded, hcc_stream stream) {
+    return hcc_trace_ex(bvh, d_rays, d_perm, n, mode, d_hits, d_occluded, nullptr, stream);
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_trace_stats(hcc_bvh bvh, const hcc_ray* d_rays,
+                                                                  const uint32_t* d_perm, uint32_t n,
+                                                                  hcc_trace_mode mode, hcc_hit* d_hits,
+                                                                  uint8_t* d_occluded, uint32_t* d_nodes,
+                                                                  uint32_t* d_tris, uint32_t* d_wave_nodes,
+                                                                  uint32_t* d_wave_tris, hcc_stream stream) {
+    hcc_status st = check_trace(bvh, d_rays, n, mode, d_hits, d_occluded);
+    if (st != HCC_OK || n == 0) return st;
+    if (!d_wave_nodes || !d_wave_tris)
+        return fail(HCC_ERR_INVALID, "hcc_trace_stats: d_wave_nodes and d_wave_tris are required");
+    const size_t waves = ((size_t)n + 63) / 64;
+    // the per-wave counters are accumulated with atomics: clear them first
+    st = fill_u32(d_wave_nodes, waves, 0u, S(stream));
+    if (st == HCC_OK) st = fill_u32(d_wave_tris, waves, 0u, S(stream));
+    if (st != HCC_OK) return st;
+    return trace_stats(bvh, d_rays, d_perm, n, mode == HCC_TRACE_CLOSEST, d_hits, d_occluded, d_nodes, d_tris,
+                       d_wave_nodes, d_wave_tris, S(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,401 @@
+// LBVH construction and HAD on gfx950 (the acceleration structure of Section 3.1 and
+// the hierarchically accumulated density of Eq. 1, Section 4.2.2).
+//
+//   scene box (two-level min/max reduction, exact)
+//   -> 30-bit Morton code of each triangle's AABB centre (10 bits per axis, x on top)
+//   -> stable radix sort of (code, triangle index)
+//   -> Karras (2012) radix tree: every internal node finds its range and split on its own
+//   -> leaves: triangles re-laid in Morton order as (v0, e1, e2, index), leaf boxes, leaf HAD
+//   -> bottom-up pass with one arrival counter per internal node: the second child to
+//      arrive unions the two boxes, fills the parent's 64-byte node and its HAD.
+// Everything is exact or rounds in a fixed operation order, so the tree, boxes and HAD
+// are identical from run to run and to a plain sequential build.
+#include "hcc_internal.h"
+
+namespace hcc {
+namespace {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+__global__ __launch_bounds__(256) void k_bounds_partial(const float* __restrict__ tris, uint32_t n,
+                                                        float* __restrict__ partial) {
+    __shared__ float s[6][256];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const size_t nv = (size_t)n * 3;
+    for (size_t v = (size_t)blockIdx.x * 256 + threadIdx.x; v < nv; v += (size_t)gridDim.x * 256) {
+        const float* p = tris + 3 * v;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], p[a]);
+            hi[a] = fmaxf(hi[a], p[a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s[a][threadIdx.x] = lo[a];
+        s[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (uint32_t off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                s[a][threadIdx.x] = fminf(s[a][threadIdx.x], s[a][threadIdx.x + off]);
+                s[3 + a][threadIdx.x] = fmaxf(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + off]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partial[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_bounds_final(const float* __restrict__ partial, uint32_t nblocks,
+                                                      float* __restrict__ box) {
+    __shared__ float s[6][256];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t b = threadIdx.x; b < nblocks; b += 256) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], partial[b * 6 + a]);
+            hi[a] = fmaxf(hi[a], partial[b * 6 + 3 + a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s[a][threadIdx.x] = lo[a];
+        s[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (uint32_t off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                s[a][threadIdx.x] = fminf(s[a][threadIdx.x], s[a][threadIdx.x + off]);
+                s[3 + a][threadIdx.x] = fmaxf(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + off]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) box[threadIdx.x] = s[threadIdx.x][0];
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t x) {   // 10 bits -> every third bit
+    x &= 0x3FFu;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t quant10(float c, float lo, float hi) {
+    const float ext = hi - lo;
+    const float u = ext > 0.0f ? (c - lo) / ext : 0.0f;
+    float q = floorf(u * 1024.0f);
+    q = fminf(fmaxf(q, 0.0f), 1023.0f);
+    return (uint32_t)q;
+}
+
+__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ tris, uint32_t n,
+                                                const float* __restrict__ box, uint32_t* __restrict__ codes) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float* t = tris + 9 * (size_t)i;
+    uint32_t q[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float mn = fminf(fminf(t[a], t[3 + a]), t[6 + a]);
+        const float mx = fmaxf(fmaxf(t[a], t[3 + a]), t[6 + a]);
+        const float c = 0.5f * (mn + mx);
+        q[a] = quant10(c, box[a], box[3 + a]);
+    }
+    codes[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+}
+
+// Common-prefix length of the augmented keys (code << 32 | position); -1 out of range.
+__device__ __forceinline__ int delta(const uint32_t* __restrict__ codes, int64_t n, int64_t i, int64_t j) {
+    if (j < 0 || j >= n) return -1;
+    const uint64_t a = ((uint64_t)codes[i] << 32) | (uint64_t)i;
+    const uint64_t b = ((uint64_t)codes[j] << 32) | (uint64_t)j;
+    return __clzll((long long)(a ^ b));
+}
+
+__global__ __launch_bounds__(256) void k_karras(const uint32_t* __restrict__ codes, uint32_t n,
+                                                uint32_t* __restrict__ child, uint32_t* __restrict__ parent) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n_int = (int64_t)n - 1;
+    if (i >= n_int) return;
+    const int64_t d = (delta(codes, n, i, i + 1) - delta(codes, n, i, i - 1)) > 0 ? 1 : -1;
+    const int dmin = delta(codes, n, i, i - d);
+    int64_t lmax = 2;
+    while (delta(codes, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int64_t l = 0;
+    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (delta(codes, n, i, i + (l + t) * d) > dmin) l += t;
+    const int64_t j = i + l * d;
+    const int dnode = delta(codes, n, i, j);
+    int64_t s = 0;
+    for (int64_t div = 2;; div <<= 1) {
+        const int64_t t = (l + div - 1) / div;
+        if (delta(codes, n, i, i + (s + t) * d) > dnode) s += t;
+        if (t == 1) break;
+    }
+    const int64_t g = i + s * d + (d < 0 ? -1 : 0);
+    const int64_t first = i < j ? i : j, last = i < j ? j : i;
+    const uint32_t left = (uint32_t)(first == g ? n_int + g : g);
+    const uint32_t right = (uint32_t)(last == g + 1 ? n_int + g + 1 : g + 1);
+    child[2 * i] = left;
+    child[2 * i + 1] = right;
+    parent[left] = (uint32_t)i;
+    parent[right] = (uint32_t)i;
+}
+
+__device__ __forceinline__ double box_sa(float lx, float ly, float lz, float hx, float hy, float hz) {
+    const double dx = (double)hx - (double)lx, dy = (double)hy - (double)ly, dz = (double)hz - (double)lz;
+    return 2.0 * ((dx * dy + dy * dz) + dz * dx);
+}
+
+__global__ __launch_bounds__(256) void k_leaves(const float* __restrict__ tris, uint32_t n,
+                                                const uint32_t* __restrict__ leaf_prim, Tri* __restrict__ out,
+                                                float* __restrict__ boxes, double* __restrict__ had) {
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t prim = leaf_prim[j];
+    const float* t = tris + 9 * (size_t)prim;
+    const float v0x = t[0], v0y = t[1], v0z = t[2];
+    const float e1x = t[3] - v0x, e1y = t[4] - v0y, e1z = t[5] - v0z;
+    const float e2x = t[6] - v0x, e2y = t[7] - v0y, e2z = t[8] - v0z;
+    Tri tr;
+    tr.p = make_float4(v0x, v0y, v0z, e1x);
+    tr.q = make_float4(e1y, e1z, e2x, e2y);
+    tr.r = make_float4(e2z, __uint_as_float(prim), 0.0f, 0.0f);
+    out[j] = tr;
+    float b[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        b[a] = fminf(fminf(t[a], t[3 + a]), t[6 + a]);
+        b[3 + a] = fmaxf(fmaxf(t[a], t[3 + a]), t[6 + a]);
+    }
+    const size_t id = (size_t)(n - 1) + j;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) boxes[6 * id + a] = b[a];
+    had[id] = 1.0 * box_sa(b[0], b[1], b[2], b[3], b[4], b[5]);
+}
+
+// Loads of values another thread published before its arrival on the counter; agent
+// scope so that a copy cached for another XCD is never used.
+__device__ __forceinline__ float load_agent(const float* p) {
+    return __uint_as_float(__hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ double load_agent(const double* p) {
+    return __longlong_as_double(
+        (long long)__hip_atomic_load((const uint64_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Bottom-up pass.  kBoxes: union boxes and fill nodes; always: HAD with 'lambda'.
+template <bool kBoxes>
+__global__ __launch_bounds__(256) void k_refit(uint32_t n, const uint32_t* __restrict__ child,
+                                               const uint32_t* __restrict__ parent, uint32_t* flags,
+                                               float* boxes, double* had, Node* __restrict__ nodes, double lambda) {
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t n_int = n - 1;
+    uint32_t node = parent[n_int + j];
+    while (node != kNone) {
+        __threadfence();                                  // publish this child's results
+        if (atomicAdd(&flags[node], 1u) == 0) return;     // sibling not done: it continues
+        __threadfence();                                  // see the sibling's results
+        const uint32_t c0 = child[2 * node], c1 = child[2 * node + 1];
+        const float* b0 = boxes + 6 * (size_t)c0;
+        const float* b1 = boxes + 6 * (size_t)c1;
+        float b[6];
+        if (kBoxes) {
+            float x0[6], x1[6];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                x0[a] = load_agent(b0 + a);
+                x1[a] = load_agent(b1 + a);
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                b[a] = fminf(x0[a], x1[a]);
+                b[3 + a] = fmaxf(x0[3 + a], x1[3 + a]);
+            }
+#pragma unroll
+            for (int a = 0; a < 6; ++a) boxes[6 * (size_t)node + a] = b[a];
+            Node nd;
+            nd.a = make_float4(x0[0], x0[1], x0[2], x0[3]);
+            nd.b = make_float4(x0[4], x0[5], x1[0], x1[1]);
+            nd.c = make_float4(x1[2], x1[3], x1[4], x1[5]);
+            nd.d = make_uint4(c0, c1, 0u, 0u);
+            nodes[node] = nd;
+        } else {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) b[a] = boxes[6 * (size_t)node + a];
+        }
+        const double h0 = load_agent(had + c0);
+        const double h1 = load_agent(had + c1);
+        had[node] = (h0 + h1) + lambda * box_sa(b[0], b[1], b[2], b[3], b[4], b[5]);
+        node = parent[node];
+    }
+}
+
+__global__ void k_fill(uint32_t* p, size_t n, uint32_t v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_leaf_had(const float* __restrict__ boxes, uint32_t n, double* __restrict__ had) {
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const size_t id = (size_t)(n - 1) + j;
+    const float* b = boxes + 6 * id;
+    had[id] = 1.0 * box_sa(b[0], b[1], b[2], b[3], b[4], b[5]);
+}
+
+template <typename T>
+hcc_status dalloc(T** p, size_t count, size_t& bytes) {
+    const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc((void**)p, b);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(HCC_ERR_OOM, "hipMalloc failed in hcc_build_bvh");
+    }
+    bytes += b;
+    return HCC_OK;
+}
+
+inline unsigned blocks_for(size_t n, unsigned per = 256) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+void free_bvh(hcc_bvh_s* b) {
+    if (!b) return;
+    (void)hipFree(b->nodes);
+    (void)hipFree(b->tris);
+    (void)hipFree(b->boxes);
+    (void)hipFree(b->had);
+    (void)hipFree(b->child);
+    (void)hipFree(b->leaf_prim);
+    (void)hipFree(b->parent);
+    b->magic = 0;
+    delete b;
+}
+
+hcc_status build_bvh(const float* d_tris, uint32_t n, hipStream_t stream, hcc_bvh_s** out) {
+    hcc_bvh_s* b = new hcc_bvh_s();
+    b->n = n;
+    b->n_int = n - 1;
+    (void)hipGetDevice(&b->device);
+    size_t bytes = 0;
+    const size_t nn = 2 * (size_t)n - 1;
+    hcc_status st;
+#define TRY(x)                      \
+    do {                            \
+        st = (x);                   \
+        if (st != HCC_OK) {         \
+            free_bvh(b);            \
+            return st;              \
+        }                           \
+    } while (0)
+    TRY(dalloc(&b->nodes, b->n_int, bytes));
+    TRY(dalloc(&b->tris, n, bytes));
+    TRY(dalloc(&b->boxes, nn * 6, bytes));
+    TRY(dalloc(&b->had, nn, bytes));
+    TRY(dalloc(&b->child, 2 * (size_t)b->n_int, bytes));
+    TRY(dalloc(&b->leaf_prim, n, bytes));
+    TRY(dalloc(&b->parent, nn, bytes));
+    b->bytes = bytes;
+
+    // temporaries
+    size_t tmp_bytes = 0;
+    const unsigned nb_bounds = std::min<unsigned>(1024u, std::max(1u, blocks_for((size_t)n * 3)));
+    float* partial = nullptr;
+    float* d_box = nullptr;
+    uint32_t* codes = nullptr;
+    uint32_t* codes_sorted = nullptr;
+    uint32_t* flags = nullptr;
+    void* ws = nullptr;
+    const size_t ws_bytes = sort_workspace_bytes(n, 30);
+    auto cleanup = [&]() {
+        (void)hipFree(partial);
+        (void)hipFree(d_box);
+        (void)hipFree(codes);
+        (void)hipFree(codes_sorted);
+        (void)hipFree(flags);
+        (void)hipFree(ws);
+    };
+#define TRYT(x)                     \
+    do {                            \
+        st = (x);                   \
+        if (st != HCC_OK) {         \
+            cleanup();              \
+            free_bvh(b);            \
+            return st;              \
+        }                           \
+    } while (0)
+    TRYT(dalloc(&partial, (size_t)nb_bounds * 6, tmp_bytes));
+    TRYT(dalloc(&d_box, 6, tmp_bytes));
+    TRYT(dalloc(&codes, n, tmp_bytes));
+    TRYT(dalloc(&codes_sorted, n, tmp_bytes));
+    TRYT(dalloc(&flags, std::max<size_t>(b->n_int, 1), tmp_bytes));
+    if (hipMalloc(&ws, ws_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        free_bvh(b);
+        return fail(HCC_ERR_OOM, "hipMalloc failed in hcc_build_bvh (sort workspace)");
+    }
+
+    k_bounds_partial<<<nb_bounds, 256, 0, stream>>>(d_tris, n, partial);
+    k_bounds_final<<<1, 256, 0, stream>>>(partial, nb_bounds, d_box);
+    k_morton<<<blocks_for(n), 256, 0, stream>>>(d_tris, n, d_box, codes);
+    TRYT(radix_sort(codes, 30, n, b->leaf_prim, codes_sorted, nullptr, ws, ws_bytes, stream));
+    k_fill<<<blocks_for(nn), 256, 0, stream>>>(b->parent, nn, kNone);
+    if (b->n_int > 0) {
+        k_karras<<<blocks_for(b->n_int), 256, 0, stream>>>(codes_sorted, n, b->child, b->parent);
+        k_fill<<<blocks_for(b->n_int), 256, 0, stream>>>(flags, b->n_int, 0u);
+    }
+    k_leaves<<<blocks_for(n), 256, 0, stream>>>(d_tris, n, b->leaf_prim, b->tris, b->boxes, b->had);
+    if (b->n_int > 0)
+        k_refit<true><<<blocks_for(n), 256, 0, stream>>>(n, b->child, b->parent, flags, b->boxes, b->had, b->nodes,
+                                                        0.125);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(b->scene_box, d_box, 6 * sizeof(float), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    cleanup();
+    if (e != hipSuccess) {
+        free_bvh(b);
+        return hip_fail(e, "hcc_build_bvh");
+    }
+    b->had_lambda = 0.125;
+    *out = b;
+    return HCC_OK;
+#undef TRY
+#undef TRYT
+}
+
+// Recompute HAD for another lambda (boxes unchanged).  Blocking.
+hcc_status recompute_had(hcc_bvh_s* b, double lambda, hipStream_t stream) {
+    if (b->n == 1) {
+        b->had_lambda = lambda;   // a single leaf: HAD = TC * SA regardless of lambda
+        return HCC_OK;
+    }
+    uint32_t* flags = nullptr;
+    if (hipMalloc(&flags, sizeof(uint32_t) * b->n_int) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HCC_ERR_OOM, "hipMalloc failed in hcc_select_cut");
+    }
+    k_fill<<<blocks_for(b->n_int), 256, 0, stream>>>(flags, b->n_int, 0u);
+    k_leaf_had<<<blocks_for(b->n), 256, 0, stream>>>(b->boxes, b->n, b->had);
+    k_refit<false><<<blocks_for(b->n), 256, 0, stream>>>(b->n, b->child, b->parent, flags, b->boxes, b->had,
+                                                         b->nodes, lambda);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(flags);
+    if (e != hipSuccess) return hip_fail(e, "hcc_select_cut (HAD)");
+    b->had_lambda = lambda;
+    return HCC_OK;
+}
+
+}  // namespace hcc

@@ -1,0 +1,127 @@
+// Sorting-key kernels for gfx950.
+//
+// HCC (Algorithm 1, Section 4.2.1): the first min(C, K) cut boxes (HAD order) are
+// copied into LDS once per block; every ray of the block's share is tested against all
+// of them and bit K-1-i records cut node i.  All lanes of a wavefront read the same box
+// at the same time, so the LDS reads are broadcasts.
+//
+// TwoPoint (Section 3.2; fixed-length end point of Section 5): 6-D Morton code of
+// (origin, origin + 0.25 L * d/|d|), L the largest scene extent.
+//
+// Rays are 32-byte records read as two 16-byte loads per lane (fully coalesced).
+#include "hcc_internal.h"
+
+namespace hcc {
+namespace {
+
+constexpr uint32_t kBlock = 256;
+constexpr uint32_t kMaxCut = 64;
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_encode_hcc(const float4* __restrict__ rays, uint32_t n,
+                                                       const CutBox* __restrict__ cut, uint32_t m,
+                                                       uint32_t key_bits, K* __restrict__ keys) {
+    __shared__ CutBox s_cut[kMaxCut];
+    for (uint32_t i = threadIdx.x; i < m; i += kBlock) s_cut[i] = cut[i];
+    __syncthreads();
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+        const float4 a = rays[2 * (size_t)r];
+        const float4 b = rays[2 * (size_t)r + 1];
+        const float ix = 1.0f / b.x, iy = 1.0f / b.y, iz = 1.0f / b.z;
+        K key = 0;
+        const uint32_t top = key_bits - 1;
+        for (uint32_t i = 0; i < m; ++i) {
+            const CutBox c = s_cut[i];
+            float tn;
+            const bool hit = slab(a.x, a.y, a.z, ix, iy, iz, a.w, b.w, c.lo.x, c.lo.y, c.lo.z, c.hi.x, c.hi.y,
+                                  c.hi.z, tn);
+            key |= (K)hit << (top - i);
+        }
+        keys[r] = key;
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_encode_twopoint(const float4* __restrict__ rays, uint32_t n, float lox,
+                                                            float loy, float loz, float hix, float hiy, float hiz,
+                                                            uint32_t key_bits, K* __restrict__ keys) {
+    const float lo[3] = {lox, loy, loz};
+    const float ext[3] = {hix - lox, hiy - loy, hiz - loz};
+    const float L = fmaxf(fmaxf(ext[0], ext[1]), ext[2]);
+    const float t_est = 0.25f * L;
+    uint32_t bits[6];
+#pragma unroll
+    for (uint32_t d = 0; d < 6; ++d) bits[d] = key_bits / 6 + (d < key_bits % 6 ? 1u : 0u);
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+        const float4 a = rays[2 * (size_t)r];
+        const float4 b = rays[2 * (size_t)r + 1];
+        const float len = sqrtf((b.x * b.x + b.y * b.y) + b.z * b.z);
+        const float dist = fminf(t_est, b.w * len);
+        const float dir[3] = {b.x, b.y, b.z};
+        const float org[3] = {a.x, a.y, a.z};
+        float p[6];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float dn = dir[k] / len;
+            p[k] = org[k];
+            p[3 + k] = org[k] + dn * dist;
+        }
+        uint32_t q[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const int ax = d % 3;
+            float u = ext[ax] > 0.0f ? (p[d] - lo[ax]) / ext[ax] : 0.0f;
+            u = fminf(fmaxf(u, 0.0f), 1.0f);
+            const float qf = floorf(u * (float)(1u << bits[d]));
+            const uint32_t qmax = (1u << bits[d]) - 1u;
+            const uint32_t qi = (uint32_t)qf;
+            q[d] = qi > qmax ? qmax : qi;
+        }
+        K key = 0;
+        for (uint32_t level = 0; level < bits[0]; ++level) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                if (level < bits[d]) key = (key << 1) | (K)((q[d] >> (bits[d] - 1 - level)) & 1u);
+            }
+        }
+        keys[r] = key;
+    }
+}
+
+inline unsigned grid_for(uint32_t n) {
+    // enough blocks to fill 256 CUs several times over; a grid-stride loop covers the rest
+    const uint32_t want = (n + kBlock - 1) / kBlock;
+    return std::max(1u, std::min(want, 256u * 32u));
+}
+
+}  // namespace
+
+hcc_status encode_hcc(const hcc_cut_s* cut, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
+                      hipStream_t stream) {
+    const uint32_t m = std::min(cut->c_eff, key_bits);
+    if (key_bits <= 32)
+        k_encode_hcc<uint32_t><<<grid_for(n), kBlock, 0, stream>>>((const float4*)d_rays, n, cut->d_boxes, m,
+                                                                   key_bits, (uint32_t*)d_keys);
+    else
+        k_encode_hcc<uint64_t><<<grid_for(n), kBlock, 0, stream>>>((const float4*)d_rays, n, cut->d_boxes, m,
+                                                                   key_bits, (uint64_t*)d_keys);
+    HCC_HIP(hipGetLastError());
+    return HCC_OK;
+}
+
+hcc_status encode_twopoint(const hcc_bvh_s* bvh, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
+                           hipStream_t stream) {
+    const float* s = bvh->scene_box;
+    if (key_bits <= 32)
+        k_encode_twopoint<uint32_t><<<grid_for(n), kBlock, 0, stream>>>((const float4*)d_rays, n, s[0], s[1], s[2],
+                                                                        s[3], s[4], s[5], key_bits,
+                                                                        (uint32_t*)d_keys);
+    else
+        k_encode_twopoint<uint64_t><<<grid_for(n), kBlock, 0, stream>>>((const float4*)d_rays, n, s[0], s[1], s[2],
+                                                                        s[3], s[4], s[5], key_bits,
+                                                                        (uint64_t*)d_keys);
+    HCC_HIP(hipGetLastError());
+    return HCC_OK;
+}
+
+}  // namespace hcc

@@ -1,0 +1,118 @@
+// Internal declarations of the gfx950 library: device data layouts, shared device
+// helpers, error plumbing.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hcc.h"
+
+namespace hcc {
+
+// ------------------------------------------------------------------------- layouts
+
+// BVH2 node, 64 bytes = one aligned fetch.  The node stores the boxes of its two
+// children so that one load gives everything a traversal step tests.
+//   a = (lo0.x, lo0.y, lo0.z, hi0.x)   b = (hi0.y, hi0.z, lo1.x, lo1.y)
+//   c = (lo1.z, hi1.x, hi1.y, hi1.z)   d = (child0, child1, 0, 0) as uint bits
+// child ids are unified: < n_internal -> internal node, else leaf (id - n_internal).
+struct alignas(64) Node {
+    float4 a, b, c;
+    uint4 d;
+};
+
+// Triangle in Morton order, 48 bytes: v0, e1 = v1 - v0, e2 = v2 - v0 (float32,
+// rounded exactly as the Moller-Trumbore test computes them), original index.
+//   p = (v0.x, v0.y, v0.z, e1.x)  q = (e1.y, e1.z, e2.x, e2.y)  r = (e2.z, prim bits, 0, 0)
+struct alignas(16) Tri {
+    float4 p, q, r;
+};
+
+// Cut box in LDS / global: lo.xyz, pad, hi.xyz, pad (32 bytes, two 16-byte loads).
+struct alignas(16) CutBox {
+    float4 lo, hi;
+};
+
+constexpr uint32_t kMissPrim = 0xFFFFFFFFu;
+constexpr int kStackDepth = 64;   // >= depth of a radix tree over 62-bit keys
+
+// ------------------------------------------------------------------------- device math
+// Slab test of a ray against a box over [tmin, tmax] (IEEE 1/d precomputed, minNum /
+// maxNum, far distance scaled by 1 + 3*2^-23).  Compiled without FMA contraction so
+// it rounds exactly like the reference definition.
+__device__ __forceinline__ bool slab(float ox, float oy, float oz, float ix, float iy, float iz, float tmin,
+                                     float tmax, float lx, float ly, float lz, float hx, float hy, float hz,
+                                     float& tnear) {
+    float t0x = (lx - ox) * ix, t1x = (hx - ox) * ix;
+    float t0y = (ly - oy) * iy, t1y = (hy - oy) * iy;
+    float t0z = (lz - oz) * iz, t1z = (hz - oz) * iz;
+    float nx = fminf(t0x, t1x), fx = fmaxf(t0x, t1x) * 0x1.000006p+0f;
+    float ny = fminf(t0y, t1y), fy = fmaxf(t0y, t1y) * 0x1.000006p+0f;
+    float nz = fminf(t0z, t1z), fz = fmaxf(t0z, t1z) * 0x1.000006p+0f;
+    tnear = fmaxf(fmaxf(fmaxf(nx, ny), nz), tmin);
+    float tfar = fminf(fminf(fminf(fx, fy), fz), tmax);
+    return tnear <= tfar;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Host-side error helpers ---------------------------------------------------------------
+void set_error(const std::string& msg);
+hcc_status fail(hcc_status st, const std::string& msg);
+hcc_status hip_fail(hipError_t e, const char* what);
+
+#define HCC_HIP(call)                                                  \
+    do {                                                               \
+        hipError_t _e = (call);                                        \
+        if (_e != hipSuccess) return ::hcc::hip_fail(_e, #call);       \
+    } while (0)
+
+// Radix sort used by the BVH build and by hcc_sort.
+size_t sort_workspace_bytes(uint32_t n, uint32_t key_bits);
+hcc_status radix_sort(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm, void* d_sorted_keys,
+                      const uint32_t* d_vals_in, void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+// XCD-aware block index: the hardware deals workgroups to the 8 XCDs round robin;
+// this maps them so that each XCD runs a contiguous range of logical blocks.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t g) {
+    uint32_t per = g >> 3, rem = g & 7u;
+    uint32_t x = b & 7u, k = b >> 3;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+}  // namespace hcc
+
+// Library-owned handle layouts.
+struct hcc_bvh_s {
+    uint32_t n = 0;                 // triangles
+    uint32_t n_int = 0;             // internal nodes = n - 1
+    hcc::Node* nodes = nullptr;     // n_int
+    hcc::Tri* tris = nullptr;       // n (Morton order)
+    float* boxes = nullptr;         // (2n-1) x 6
+    double* had = nullptr;          // 2n-1
+    uint32_t* child = nullptr;      // n_int x 2 (unified ids)
+    uint32_t* leaf_prim = nullptr;  // n
+    uint32_t* parent = nullptr;     // 2n-1 (root: 0xFFFFFFFF)
+    float scene_box[6] = {0, 0, 0, 0, 0, 0};
+    double had_lambda = 0.125;
+    size_t bytes = 0;
+    int device = 0;
+    // host mirror for the cut search
+    std::vector<uint32_t> h_child;
+    std::vector<double> h_had;
+    double h_had_lambda = -1.0;
+    uint64_t magic = 0x6863636276680001ull;
+};
+
+struct hcc_cut_s {
+    const hcc_bvh_s* bvh = nullptr;
+    uint32_t c_eff = 0;
+    std::vector<uint32_t> ids;
+    std::vector<double> had;
+    std::vector<float> boxes;       // c_eff x 6
+    hcc::CutBox* d_boxes = nullptr; // c_eff
+    uint64_t magic = 0x6863636375740001ull;
+};

@@ -1,0 +1,301 @@
+// Stable LSD radix sort of (key, index) pairs for gfx950, 8-bit digits.
+//
+// Sorting the ray keys "as natural numbers" and handing the trace kernel the sorted
+// ray indices is the reorder step of the method (Sections 4.2.3 and 5).  Design:
+//   1. one read of the keys builds the digit histograms of every pass at once;
+//   2. per pass, one kernel ranks a tile of 4096 keys (4 wavefronts x 16 keys per lane)
+//      with wavefront ballots: the lanes holding the same digit are found from one
+//      ballot per digit bit, and their count below a lane gives its stable rank;
+//      the tile's per-digit totals are combined with earlier tiles by a decoupled
+//      look-back (tiles are numbered in the order blocks start, so every tile waited
+//      on is already running); the tile is reordered in LDS and written out so that
+//      equal digits land on consecutive addresses.
+// Keys: uint32 (key_bits <= 32) or uint64.  Only bits [0, key_bits) take part.
+#include "hcc_internal.h"
+
+namespace hcc {
+namespace {
+
+constexpr uint32_t kBlock = 256;          // 4 wavefronts
+constexpr uint32_t kItems = 16;
+constexpr uint32_t kTile = kBlock * kItems;
+constexpr uint32_t kRadix = 256;
+constexpr uint32_t kMaxPasses = 8;
+constexpr uint32_t kFlagAgg = 1u << 30, kFlagIncl = 2u << 30, kCountMask = (1u << 30) - 1u;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.  s must hold 4 words
+// not used by any other concurrent scan.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s) {
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    uint32_t incl = wave_incl_scan(x);
+    if (lane == 63) s[w] = incl;
+    __syncthreads();
+    uint32_t pre = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) pre += (j < w) ? s[j] : 0u;
+    return pre + incl - x;
+}
+
+// Lanes of the wavefront (among 'alive') whose low 'nbits' bits of d equal this lane's.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint32_t nbits, bool alive) {
+    uint64_t m = __ballot(alive);
+    for (uint32_t b = 0; b < nbits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64u - lane));
+}
+
+__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint32_t n, uint32_t key_bits,
+                                                 uint32_t passes, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t s_h[kMaxPasses * kRadix];
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i = t; i < passes * kRadix; i += kBlock) s_h[i] = 0;
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        const uint32_t idx = base + t;
+        const bool valid = idx < n;
+        const K k = valid ? keys[idx] : K(0);
+        for (uint32_t p = 0; p < passes; ++p) {
+            const uint32_t nb = min(8u, key_bits - 8u * p);
+            const uint32_t d = (uint32_t)(k >> (8u * p)) & ((1u << nb) - 1u);
+            const uint64_t m = match_digit(d, nb, valid);
+            if (valid && (m & lt) == 0) atomicAdd(&s_h[p * kRadix + d], (uint32_t)__popcll(m));
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < passes * kRadix; i += kBlock)
+        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
+template <typename K, bool kIota, bool kWriteKeys>
+__global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                    K* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
+                                                    uint32_t shift, uint32_t nbits,
+                                                    const uint32_t* __restrict__ hist, uint32_t* lookback,
+                                                    uint32_t* counter) {
+    __shared__ uint32_t s_whist[4 * kRadix];
+    __shared__ uint32_t s_dexcl[kRadix];
+    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_scan[8];
+    __shared__ uint32_t s_tile;
+    __shared__ K s_keys[kTile];
+    __shared__ uint32_t s_vals[kTile];
+
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    if (t == 0) s_tile = atomicAdd(counter, 1u);
+    for (uint32_t i = t; i < 4 * kRadix; i += kBlock) s_whist[i] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t base = tile * kTile + w * (64u * kItems) + lane;
+    const uint32_t mask = (1u << nbits) - 1u;
+    const uint64_t lt = lanemask_lt();
+    uint32_t* wh = s_whist + w * kRadix;
+
+    K k[kItems];
+    uint32_t v[kItems];
+    uint32_t r[kItems];
+#pragma unroll
+    for (uint32_t i = 0; i < kItems; ++i) {
+        const uint32_t idx = base + i * 64u;
+        const bool valid = idx < n;
+        k[i] = valid ? kin[idx] : K(0);
+        v[i] = kIota ? idx : (valid ? vin[idx] : 0u);
+    }
+    // stable rank of every key among the keys of its wavefront with the same digit
+#pragma unroll
+    for (uint32_t i = 0; i < kItems; ++i) {
+        const bool valid = base + i * 64u < n;
+        const uint32_t d = (uint32_t)(k[i] >> shift) & mask;
+        const uint64_t m = match_digit(d, nbits, valid);
+        const uint32_t below = (uint32_t)__popcll(m & lt);
+        const uint32_t prev = valid ? wh[d] : 0u;
+        r[i] = prev + below;
+        // every lane of the group has read wh[d] before the group's lowest lane writes it:
+        // a wavefront's LDS operations complete in issue order
+        if (valid && below == 0) wh[d] = prev + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+
+    // thread t owns digit t: tile total, per-wavefront exclusive offsets
+    const uint32_t d = t;
+    const uint32_t c0 = s_whist[d], c1 = s_whist[kRadix + d], c2 = s_whist[2 * kRadix + d],
+                   c3 = s_whist[3 * kRadix + d];
+    const uint32_t cnt = c0 + c1 + c2 + c3;
+    s_whist[d] = 0;
+    s_whist[kRadix + d] = c0;
+    s_whist[2 * kRadix + d] = c0 + c1;
+    s_whist[3 * kRadix + d] = c0 + c1 + c2;
+
+    // decoupled look-back over earlier tiles for digit d
+    uint32_t excl = 0;
+    uint32_t* mine = lookback + (size_t)tile * kRadix + d;
+    if (tile == 0) {
+        __hip_atomic_store(mine, kFlagIncl | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(mine, kFlagAgg | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t j = (int64_t)tile - 1;
+        while (true) {
+            const uint32_t x = __hip_atomic_load(lookback + (size_t)j * kRadix + d, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t f = x & ~kCountMask;
+            if (f == 0) {
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            excl += x & kCountMask;
+            if (f == kFlagIncl) break;
+            --j;
+        }
+        __hip_atomic_store(mine, kFlagIncl | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t hexcl = block_excl_scan256(hist[d], s_scan);
+    const uint32_t dexcl = block_excl_scan256(cnt, s_scan + 4);
+    s_gbase[d] = hexcl + excl;
+    s_dexcl[d] = dexcl;
+    __syncthreads();
+
+#pragma unroll
+    for (uint32_t i = 0; i < kItems; ++i) {
+        if (base + i * 64u < n) {
+            const uint32_t dd = (uint32_t)(k[i] >> shift) & mask;
+            const uint32_t pos = s_dexcl[dd] + wh[dd] + r[i];
+            s_keys[pos] = k[i];
+            s_vals[pos] = v[i];
+        }
+    }
+    __syncthreads();
+    const uint32_t count = min(kTile, n - tile * kTile);
+    for (uint32_t j = t; j < count; j += kBlock) {
+        const K key = s_keys[j];
+        const uint32_t dd = (uint32_t)(key >> shift) & mask;
+        const uint32_t g = s_gbase[dd] + (j - s_dexcl[dd]);
+        if (kWriteKeys) kout[g] = key;
+        vout[g] = s_vals[j];
+    }
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t keys_a, keys_b, vals, hist, counters, lookback, total;
+};
+
+Layout layout(uint32_t n, uint32_t key_bits) {
+    const size_t ks = key_bits <= 32 ? 4 : 8;
+    const uint32_t passes = (key_bits + 7) / 8;
+    const size_t tiles = ((size_t)n + kTile - 1) / kTile;
+    Layout L{};
+    size_t off = 0;
+    L.keys_a = off; off += align256((size_t)n * ks);
+    L.keys_b = off; off += align256((size_t)n * ks);
+    L.vals = off; off += align256((size_t)n * 4);
+    L.hist = off; off += align256((size_t)kMaxPasses * kRadix * 4);
+    L.counters = off; off += align256(kMaxPasses * 4);
+    L.lookback = off; off += align256((size_t)passes * tiles * kRadix * 4);
+    L.total = off;
+    return L;
+}
+
+template <typename K>
+hcc_status run_sort(const K* keys, uint32_t key_bits, uint32_t n, uint32_t* perm, K* sorted_keys, char* ws,
+                    hipStream_t stream) {
+    const uint32_t passes = (key_bits + 7) / 8;
+    const Layout L = layout(n, key_bits);
+    const uint32_t tiles = (n + kTile - 1) / kTile;
+    uint32_t* hist = (uint32_t*)(ws + L.hist);
+    uint32_t* counters = (uint32_t*)(ws + L.counters);
+    uint32_t* lookback = (uint32_t*)(ws + L.lookback);
+    // zero histogram, counters and look-back state (hist, counters and lookback are contiguous)
+    const size_t zero_words = (L.total - L.hist) / 4;
+    k_fill_u32<<<dim3((unsigned)std::min<size_t>(1024, (zero_words + 255) / 256)), dim3(256), 0, stream>>>(
+        hist, zero_words, 0u);
+    const uint32_t hist_blocks = std::min<uint32_t>(2048u, (n + kBlock - 1) / kBlock);
+    k_hist<K><<<dim3(hist_blocks), dim3(kBlock), 0, stream>>>(keys, n, key_bits, passes, hist);
+
+    K* final_keys = sorted_keys ? sorted_keys : (K*)(ws + L.keys_a);
+    K* other_keys = (K*)(ws + L.keys_b);
+    uint32_t* vals_tmp = (uint32_t*)(ws + L.vals);
+    const K* kin = keys;
+    const uint32_t* vin = nullptr;
+    for (uint32_t p = 0; p < passes; ++p) {
+        const bool to_final = ((passes - 1 - p) % 2) == 0;
+        K* kout = to_final ? final_keys : other_keys;
+        uint32_t* vout = to_final ? perm : vals_tmp;
+        const bool last = p + 1 == passes;
+        const uint32_t nb = std::min<uint32_t>(8u, key_bits - 8u * p);
+        const uint32_t* h = hist + p * kRadix;
+        uint32_t* lb = lookback + (size_t)p * tiles * kRadix;
+        uint32_t* ctr = counters + p;
+        dim3 grid(tiles), block(kBlock);
+        if (p == 0) {
+            if (last && !sorted_keys)
+                k_scatter<K, true, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, 0, nb, h, lb, ctr);
+            else
+                k_scatter<K, true, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, 0, nb, h, lb, ctr);
+        } else {
+            if (last && !sorted_keys)
+                k_scatter<K, false, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, 8u * p, nb, h, lb, ctr);
+            else
+                k_scatter<K, false, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, 8u * p, nb, h, lb, ctr);
+        }
+        kin = kout;
+        vin = vout;
+    }
+    HCC_HIP(hipGetLastError());
+    return HCC_OK;
+}
+
+}  // namespace
+
+size_t sort_workspace_bytes(uint32_t n, uint32_t key_bits) { return layout(n, key_bits).total; }
+
+hcc_status fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+    if (n == 0) return HCC_OK;
+    const unsigned grid = (unsigned)std::min<size_t>(1024, (n + 255) / 256);
+    k_fill_u32<<<grid, 256, 0, s>>>(p, n, v);
+    HCC_HIP(hipGetLastError());
+    return HCC_OK;
+}
+
+hcc_status radix_sort(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm, void* d_sorted_keys,
+                      const uint32_t* /*d_vals_in*/, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+    if (key_bits < 1 || key_bits > 64) return fail(HCC_ERR_INVALID, "hcc_sort: key_bits must be in [1, 64]");
+    if (n >= (1u << 30)) return fail(HCC_ERR_INVALID, "hcc_sort: n must be below 2^30");
+    if (n == 0) return HCC_OK;
+    if (!d_keys || !d_perm || !d_ws) return fail(HCC_ERR_INVALID, "hcc_sort: null pointer");
+    if (((uintptr_t)d_ws & 255u) != 0) return fail(HCC_ERR_INVALID, "hcc_sort: workspace must be 256-byte aligned");
+    if (ws_bytes < sort_workspace_bytes(n, key_bits))
+        return fail(HCC_ERR_INVALID, "hcc_sort: workspace too small (see hcc_sort_workspace)");
+    if (key_bits <= 32)
+        return run_sort<uint32_t>((const uint32_t*)d_keys, key_bits, n, d_perm, (uint32_t*)d_sorted_keys,
+                                  (char*)d_ws, stream);
+    return run_sort<uint64_t>((const uint64_t*)d_keys, key_bits, n, d_perm, (uint64_t*)d_sorted_keys, (char*)d_ws,
+                              stream);
+}
+
+}  // namespace hcc

@@ -1,0 +1,246 @@
+// BVH traversal for gfx950 (the trace kernel of Section 5: it fetches the rays through
+// the sorted indices, so reordered rays of one wavefront walk similar paths).
+//
+// One lane per ray, wavefront of 64 lanes.  Loop per lane: fetch the current internal
+// node (one 64-byte load holding both child boxes), slab-test both children against
+// [tmin, best t], test leaf children's triangles at once (one triangle per leaf),
+// descend into the nearer hit child and push the farther one, pop when nothing is hit.
+// Stack placement is a template parameter (LDS, private scratch, or LDS for the first
+// entries and scratch beyond).  Results are written at the original ray index.
+//
+// Closest hit keeps the smallest (t, triangle index) pair, which makes the answer
+// independent of traversal order; any hit stops at the first triangle in the segment.
+#include "hcc_internal.h"
+
+namespace hcc {
+namespace {
+
+constexpr int kShortDepth = 16;
+
+// Moller-Trumbore, double sided, float32, fixed operation order, no FMA contraction.
+__device__ __forceinline__ bool tri_test(const Tri& tr, float ox, float oy, float oz, float dx, float dy, float dz,
+                                         float tmin, float tmax, float& t, float& u, float& v) {
+    const float v0x = tr.p.x, v0y = tr.p.y, v0z = tr.p.z;
+    const float e1x = tr.p.w, e1y = tr.q.x, e1z = tr.q.y;
+    const float e2x = tr.q.z, e2y = tr.q.w, e2z = tr.r.x;
+    const float px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    const float det = (e1x * px + e1y * py) + e1z * pz;
+    if (det == 0.0f) return false;
+    const float inv = 1.0f / det;
+    const float sx = ox - v0x, sy = oy - v0y, sz = oz - v0z;
+    u = ((sx * px + sy * py) + sz * pz) * inv;
+    if (!(u >= 0.0f && u <= 1.0f)) return false;
+    const float qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+    v = ((dx * qx + dy * qy) + dz * qz) * inv;
+    if (!(v >= 0.0f && u + v <= 1.0f)) return false;
+    t = ((e2x * qx + e2y * qy) + e2z * qz) * inv;
+    return t > tmin && t < tmax;
+}
+
+template <int kStack, int kBlock>
+struct Stack;
+
+template <int kBlock>
+struct Stack<HCC_STACK_LDS, kBlock> {
+    uint32_t* s;
+    __device__ void init(uint32_t* lds) { s = lds + threadIdx.x; }
+    __device__ void push(uint32_t sp, uint32_t x) { s[sp * kBlock] = x; }
+    __device__ uint32_t pop(uint32_t sp) { return s[sp * kBlock]; }
+};
+
+template <int kBlock>
+struct Stack<HCC_STACK_SCRATCH, kBlock> {
+    uint32_t s[kStackDepth];
+    __device__ void init(uint32_t*) {}
+    __device__ void push(uint32_t sp, uint32_t x) { s[sp] = x; }
+    __device__ uint32_t pop(uint32_t sp) { return s[sp]; }
+};
+
+template <int kBlock>
+struct Stack<HCC_STACK_SHORT, kBlock> {
+    uint32_t* s;
+    uint32_t deep[kStackDepth - kShortDepth];
+    __device__ void init(uint32_t* lds) { s = lds + threadIdx.x; }
+    __device__ void push(uint32_t sp, uint32_t x) {
+        if (sp < kShortDepth) s[sp * kBlock] = x;
+        else deep[sp - kShortDepth] = x;
+    }
+    __device__ uint32_t pop(uint32_t sp) { return sp < kShortDepth ? s[sp * kBlock] : deep[sp - kShortDepth]; }
+};
+
+template <int kStack>
+constexpr int lds_entries() {
+    return kStack == HCC_STACK_LDS ? kStackDepth : (kStack == HCC_STACK_SHORT ? kShortDepth : 1);
+}
+
+// Number of distinct values of x among the active lanes (measurement only).
+__device__ __forceinline__ uint32_t wave_distinct(uint32_t x) {
+    uint64_t rem = __ballot(1);
+    uint32_t count = 0;
+    while (rem) {
+        const int src = __ffsll((unsigned long long)rem) - 1;
+        const uint32_t id = __shfl(x, src, 64);
+        rem &= ~__ballot(x == id);
+        ++count;
+    }
+    return count;
+}
+
+__device__ __forceinline__ bool first_active_lane() {
+    const uint64_t act = __ballot(1);
+    return (int)__lane_id() == __ffsll((unsigned long long)act) - 1;
+}
+
+template <bool kClosest, int kStack, int kBlock, bool kStats>
+__global__ __launch_bounds__(kBlock) void k_trace(const Node* __restrict__ nodes, const Tri* __restrict__ tris,
+                                                  uint32_t n_int, const float4* __restrict__ rays,
+                                                  const uint32_t* __restrict__ perm, uint32_t n,
+                                                  float4* __restrict__ hits, uint8_t* __restrict__ occ,
+                                                  uint32_t remap, uint32_t* __restrict__ cnt_nodes,
+                                                  uint32_t* __restrict__ cnt_tris, uint32_t* wave_nodes,
+                                                  uint32_t* wave_tris) {
+    __shared__ uint32_t s_stack[lds_entries<kStack>() * kBlock];
+    const uint32_t blk = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t k = blk * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t rid = perm ? perm[k] : k;
+    if (rid >= n) return;   // a permutation entry out of range is skipped, never dereferenced
+    const float4 ra = rays[2 * (size_t)rid];
+    const float4 rb = rays[2 * (size_t)rid + 1];
+    const float ox = ra.x, oy = ra.y, oz = ra.z, tmin = ra.w;
+    const float dx = rb.x, dy = rb.y, dz = rb.z, tmax = rb.w;
+    const float ix = 1.0f / dx, iy = 1.0f / dy, iz = 1.0f / dz;
+    float best_t = tmax, best_u = 0.0f, best_v = 0.0f;
+    uint32_t best_prim = kMissPrim;
+    bool found = false;
+    uint32_t n_nodes = 0, n_tris = 0;
+    const uint32_t wave = k >> 6;
+
+    auto test_leaf = [&](uint32_t leaf) {
+        const Tri tr = tris[leaf];
+        const uint32_t prim = __float_as_uint(tr.r.y);
+        float t, u, v;
+        if (kStats) ++n_tris;
+        if (tri_test(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v)) {
+            if (!kClosest) {
+                found = true;
+            } else if (t < best_t || (t == best_t && prim < best_prim)) {
+                best_t = t;
+                best_u = u;
+                best_v = v;
+                best_prim = prim;
+                found = true;
+            }
+        }
+    };
+
+    if (n_int == 0) {
+        test_leaf(0);
+    } else {
+        Stack<kStack, kBlock> st;
+        st.init(s_stack);
+        uint32_t sp = 0;
+        uint32_t node = 0;
+        while (true) {
+            if (kStats) {
+                ++n_nodes;
+                const uint32_t dn = wave_distinct(node);
+                if (first_active_lane()) atomicAdd(wave_nodes + wave, dn);
+            }
+            const Node nd = nodes[node];
+            const float lim = kClosest ? best_t : tmax;
+            float tn0, tn1;
+            bool h0 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, tn0);
+            bool h1 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, tn1);
+            const uint32_t c0 = nd.d.x, c1 = nd.d.y;
+            const bool leaf0 = h0 && c0 >= n_int;
+            const bool leaf1 = h1 && c1 >= n_int;
+            if (kStats) {
+                const uint32_t t0 = wave_distinct(leaf0 ? c0 : 0xFFFFFFFFu) - (__ballot(!leaf0) != 0 ? 1u : 0u);
+                const uint32_t t1 = wave_distinct(leaf1 ? c1 : 0xFFFFFFFFu) - (__ballot(!leaf1) != 0 ? 1u : 0u);
+                if (first_active_lane()) atomicAdd(wave_tris + wave, t0 + t1);
+            }
+            if (leaf0) test_leaf(c0 - n_int);
+            if (leaf1) test_leaf(c1 - n_int);
+            if (!kClosest && found) break;
+            h0 = h0 && !leaf0;
+            h1 = h1 && !leaf1;
+            if (h0 && h1) {
+                const bool near1 = tn1 < tn0;
+                st.push(sp, near1 ? c0 : c1);
+                ++sp;
+                node = near1 ? c1 : c0;
+            } else if (h0) {
+                node = c0;
+            } else if (h1) {
+                node = c1;
+            } else {
+                if (sp == 0) break;
+                --sp;
+                node = st.pop(sp);
+            }
+        }
+    }
+    if (kClosest) {
+        hits[rid] = make_float4(found ? best_t : INFINITY, __uint_as_float(found ? best_prim : kMissPrim),
+                                found ? best_u : 0.0f, found ? best_v : 0.0f);
+    } else {
+        occ[rid] = found ? 1 : 0;
+    }
+    if (kStats) {
+        if (cnt_nodes) cnt_nodes[rid] = n_nodes;
+        if (cnt_tris) cnt_tris[rid] = n_tris;
+    }
+}
+
+template <bool kClosest, int kStack, int kBlock, bool kStats>
+void launch(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, hcc_hit* hits, uint8_t* occ,
+            uint32_t remap, uint32_t* cn, uint32_t* ct, uint32_t* wn, uint32_t* wt, hipStream_t stream) {
+    const unsigned grid = (n + kBlock - 1) / kBlock;
+    k_trace<kClosest, kStack, kBlock, kStats><<<grid, kBlock, 0, stream>>>(
+        b->nodes, b->tris, b->n_int, (const float4*)rays, perm, n, (float4*)hits, occ, remap, cn, ct, wn, wt);
+}
+
+template <bool kClosest, bool kStats>
+hcc_status dispatch_stack(uint32_t stack, uint32_t block, const hcc_bvh_s* b, const hcc_ray* rays,
+                          const uint32_t* perm, uint32_t n, hcc_hit* hits, uint8_t* occ, uint32_t remap, uint32_t* cn,
+                          uint32_t* ct, uint32_t* wn, uint32_t* wt, hipStream_t s) {
+#define HCC_BLOCKS(STK)                                                                       \
+    switch (block) {                                                                          \
+        case 64: launch<kClosest, STK, 64, kStats>(b, rays, perm, n, hits, occ, remap, cn, ct, wn, wt, s); break;   \
+        case 128: launch<kClosest, STK, 128, kStats>(b, rays, perm, n, hits, occ, remap, cn, ct, wn, wt, s); break; \
+        case 256: launch<kClosest, STK, 256, kStats>(b, rays, perm, n, hits, occ, remap, cn, ct, wn, wt, s); break; \
+        default: return fail(HCC_ERR_INVALID, "hcc_trace: block must be 64, 128 or 256");    \
+    }
+    switch (stack) {
+        case HCC_STACK_LDS: HCC_BLOCKS(HCC_STACK_LDS); break;
+        case HCC_STACK_SCRATCH: HCC_BLOCKS(HCC_STACK_SCRATCH); break;
+        case HCC_STACK_SHORT: HCC_BLOCKS(HCC_STACK_SHORT); break;
+        default: return fail(HCC_ERR_INVALID, "hcc_trace: unknown stack mode");
+    }
+#undef HCC_BLOCKS
+    HCC_HIP(hipGetLastError());
+    return HCC_OK;
+}
+
+}  // namespace
+
+hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
+                 hcc_hit* hits, uint8_t* occ, const hcc_trace_opts& o, hipStream_t s) {
+    const uint32_t block = o.block ? o.block : 128;
+    if (closest)
+        return dispatch_stack<true, false>(o.stack, block, b, rays, perm, n, hits, occ, o.xcd_remap, nullptr, nullptr,
+                                           nullptr, nullptr, s);
+    return dispatch_stack<false, false>(o.stack, block, b, rays, perm, n, hits, occ, o.xcd_remap, nullptr, nullptr,
+                                        nullptr, nullptr, s);
+}
+
+hcc_status trace_stats(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
+                       hcc_hit* hits, uint8_t* occ, uint32_t* cn, uint32_t* ct, uint32_t* wn, uint32_t* wt,
+                       hipStream_t s) {
+    if (closest)
+        return dispatch_stack<true, true>(HCC_STACK_SCRATCH, 64, b, rays, perm, n, hits, occ, 0, cn, ct, wn, wt, s);
+    return dispatch_stack<false, true>(HCC_STACK_SCRATCH, 64, b, rays, perm, n, hits, occ, 0, cn, ct, wn, wt, s);
+}
+
+}  // namespace hcc
