@@ -1,0 +1,331 @@
+#!/usr/bin/env python3
+"""Benchmark of the hierarchy-cut-code path on one MI355X.
+
+Workload (paper-shaped frame): a 1,012,012-triangle room holding 100 icospheres and 100
+tori, a 1920x1080 camera at 8 samples per pixel; the bounce-1 cosine-weighted diffuse
+secondary rays (one per primary hit, 16.6M) are the measured batch, and the two shadow
+rays per primary hit (33.2M) give the any-hit numbers.  Rays are generated once (primary
+hits come from the library's own trace) and stay resident in HBM.
+
+A step = HCC encode (cut of 32 nodes, 32-bit keys) + stable radix sort + closest-hit trace
+through the sorted permutation over the whole batch.  The same batch is also timed for
+NoSort (trace in generation order) and TwoPoint (32-bit 6-D Morton key) for comparison.
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "secondary Mrays/s incl. encode+sort vs NoSort; serve p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+NODE_BYTES, TRI_BYTES = 64, 48
+RAY_BYTES, PERM_BYTES, HIT_BYTES = 32, 4, 16
+
+
+def log(msg: str):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--spp", type=int, default=8)
+    ap.add_argument("--width", type=int, default=1920)
+    ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--cut", type=int, default=32)
+    ap.add_argument("--key-bits", type=int, default=32)
+    ap.add_argument("--block", type=int, default=64)
+    ap.add_argument("--stack", type=int, default=1, help="0 LDS, 1 scratch, 2 LDS+scratch")
+    ap.add_argument("--remap", type=int, default=0, help="1 = XCD-contiguous block order")
+    ap.add_argument("--methods", default="nosort,twopoint,hcc")
+    ap.add_argument("--no-stats", action="store_true", help="skip the fetch-counting trace (roofline bytes)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-stride", type=int, default=8, help="oracle sample: every k-th secondary ray")
+    ap.add_argument("--no-shadow", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(rays would be sharded by contiguous ranges with a BVH replica per GPU); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2305_16652_amd as H
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    methods = [m for m in args.methods.split(",") if m]
+    if args.copy_probe_mib > 0:
+        src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
+
+    # ------------------------------------------------------------------ workload
+    t0 = time.time()
+    spec = W.frame_scene()
+    tris_h = spec.tris
+    tris = torch.from_numpy(tris_h).to(dev)
+    log(f"scene {tris_h.shape[0]} triangles ({time.time() - t0:.1f}s)")
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    e0, e1 = ev(), ev()
+    e0.record()
+    bvh = H.build_bvh(tris)
+    e1.record()
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1)
+    e0.record()
+    cut = H.select_cut(bvh, args.cut)
+    e1.record()
+    torch.cuda.synchronize()
+    cut_ms = e0.elapsed_time(e1)
+    log(f"BVH built in {build_ms:.1f} ms, cut of {cut.c_eff} in {cut_ms:.1f} ms")
+
+    t0 = time.time()
+    prim = W.pinhole_rays(spec, args.width, args.height, args.spp, seed=2)
+    prim_d = torch.from_numpy(prim).to(dev)
+    ph = H.trace(bvh, prim_d, opts=H.TraceOpts(args.block, args.stack, args.remap, 0)).cpu().numpy()
+    del prim_d
+    p_t = ph[:, 0].copy()
+    p_prim = ph[:, 1].copy().view(np.uint32)
+    sec, _ = W.spawn_diffuse(prim, p_t, p_prim, tris_h, seed=7, bounce=0)
+    rays = torch.from_numpy(sec).to(dev)
+    R = rays.shape[0]
+    log(f"{prim.shape[0]} primary rays, {R} secondary rays ({time.time() - t0:.1f}s)")
+    shadow = None
+    if not args.no_shadow:
+        shd, _ = W.spawn_shadow(prim, p_t, p_prim, tris_h, spec.lights)
+        shadow = torch.from_numpy(shd).to(dev)
+        log(f"{shadow.shape[0]} shadow rays")
+    del prim, ph
+
+    K = args.key_bits
+    kdt = torch.int32 if K <= 32 else torch.int64
+    keys = torch.empty(R, dtype=kdt, device=dev)
+    perm = torch.empty(R, dtype=torch.int32, device=dev)
+    ws = torch.empty(H.sort_workspace_bytes(R, K), dtype=torch.uint8, device=dev)
+    hits = torch.empty((R, 4), dtype=torch.float32, device=dev)
+    opts = H.TraceOpts(args.block, args.stack, args.remap, 0)
+
+    def run(method: str, stage_events=None):
+        if method == "nosort":
+            if stage_events:
+                stage_events[0].record()
+            H.trace(bvh, rays, None, out=hits, opts=opts)
+            if stage_events:
+                stage_events[3].record()
+            return
+        if stage_events:
+            stage_events[0].record()
+        if method == "hcc":
+            H.encode(bvh, cut, H.KEY_HCC, K, rays, out=keys)
+        else:
+            H.encode(bvh, None, H.KEY_TWOPOINT, K, rays, out=keys)
+        if stage_events:
+            stage_events[1].record()
+        H.sort(keys, K, perm=perm, ws=ws)
+        if stage_events:
+            stage_events[2].record()
+        H.trace(bvh, rays, perm, out=hits, opts=opts)
+        if stage_events:
+            stage_events[3].record()
+
+    def timed(method: str):
+        for _ in range(args.warmup):
+            run(method)
+        torch.cuda.synchronize()
+        evs = [[ev() for _ in range(4)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        start, stop = ev(), ev()
+        t_wall = time.time()
+        start.record()
+        for s in range(args.steps):
+            run(method, evs[s])
+        stop.record()
+        torch.cuda.synchronize()
+        wall = time.time() - t_wall
+        total_ms = start.elapsed_time(stop)
+        enc = [e[0].elapsed_time(e[1]) for e in evs] if method != "nosort" else [0.0]
+        srt = [e[1].elapsed_time(e[2]) for e in evs] if method != "nosort" else [0.0]
+        trc = [(e[2] if method != "nosort" else e[0]).elapsed_time(e[3]) for e in evs]
+        ms = total_ms / args.steps
+        res = dict(ms_per_step=ms, mrays_s=R / (ms * 1e-3) / 1e6, encode_ms=float(np.median(enc)),
+                   sort_ms=float(np.median(srt)), trace_ms=float(np.median(trc)),
+                   trace_ms_mean=float(np.mean(trc)), trace_only_mrays_s=R / (np.median(trc) * 1e-3) / 1e6,
+                   wall_s=wall)
+        log(f"{method}: {ms:.3f} ms/step ({res['mrays_s']:.1f} Mrays/s), encode {res['encode_ms']:.3f} "
+            f"sort {res['sort_ms']:.3f} trace {res['trace_ms']:.3f} ms")
+        return res
+
+    results = {}
+    for m in ("nosort", "twopoint", "hcc"):
+        if m in methods:
+            results[m] = timed(m)
+    hcc_hits = hits.clone()
+
+    # any-hit (shadow) rays: NoSort vs HCC incl. encode+sort, median of the steps
+    shadow_res = None
+    if shadow is not None:
+        S = shadow.shape[0]
+        occ = torch.empty(S, dtype=torch.uint8, device=dev)
+        skeys = torch.empty(S, dtype=kdt, device=dev)
+        sperm = torch.empty(S, dtype=torch.int32, device=dev)
+        sws = torch.empty(H.sort_workspace_bytes(S, K), dtype=torch.uint8, device=dev)
+        shadow_res = {}
+        for m in [x for x in ("nosort", "twopoint", "hcc") if x in methods]:
+            times = []
+            for s in range(args.warmup + args.steps):
+                a, b = ev(), ev()
+                a.record()
+                if m != "nosort":
+                    if m == "hcc":
+                        H.encode(bvh, cut, H.KEY_HCC, K, shadow, out=skeys)
+                    else:
+                        H.encode(bvh, None, H.KEY_TWOPOINT, K, shadow, out=skeys)
+                    H.sort(skeys, K, perm=sperm, ws=sws)
+                    H.trace(bvh, shadow, sperm, closest=False, out=occ, opts=opts)
+                else:
+                    H.trace(bvh, shadow, None, closest=False, out=occ, opts=opts)
+                b.record()
+                torch.cuda.synchronize()
+                if s >= args.warmup:
+                    times.append(a.elapsed_time(b))
+            ms = float(np.median(times))
+            shadow_res[m] = dict(ms=ms, mrays_s=S / (ms * 1e-3) / 1e6)
+        shadow_res["rays"] = S
+        log("shadow: " + ", ".join(f"{m} {v['mrays_s']:.0f}" for m, v in shadow_res.items() if m != "rays"))
+
+    # ------------------------------------------------------------------ roofline of the trace kernel
+    # algorithmic bytes: per wavefront and lockstep iteration, every distinct node (64 B) and
+    # triangle (48 B) fetched, plus each ray's record, permutation entry and hit record
+    if args.no_stats or "hcc" not in results:
+        roofline = None
+    else:
+        roofline = roofline_of(H, bvh, rays, perm, R, results["hcc"]["trace_ms_mean"])
+
+    # ------------------------------------------------------------------ CPU oracle baseline
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(tris_h, sec, args, hcc_hits.cpu().numpy())
+
+    hcc = results.get("hcc") or next(iter(results.values()))
+    nos, tpt = results.get("nosort"), results.get("twopoint")
+    line = {
+        "metric": METRIC,
+        "value": round(hcc["mrays_s"], 2),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(hcc["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"frame: {tris_h.shape[0]:,}-triangle room with 100 icospheres + 100 tori, "
+                         f"{args.width}x{args.height}x{args.spp} spp, bounce-1 diffuse secondary rays; "
+                         f"HCC cut {cut.c_eff} nodes, {K}-bit keys"),
+            "triangles": int(tris_h.shape[0]), "rays": int(R), "cut": int(cut.c_eff), "key_bits": K,
+            "trace_block": args.block, "stack": args.stack, "xcd_remap": args.remap,
+        },
+        "methods": {m: {k: round(v, 4) for k, v in r.items()} for m, r in results.items()},
+        "speedup_vs_nosort": round(hcc["mrays_s"] / nos["mrays_s"], 3) if nos else None,
+        "speedup_vs_twopoint": round(hcc["mrays_s"] / tpt["mrays_s"], 3) if tpt else None,
+        "shadow": shadow_res,
+        "build_ms": round(build_ms, 2),
+        "select_cut_ms": round(cut_ms, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per trace launch from the committed PMC summary, if it still describes the
+    current trace kernel sources (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "trace_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    src = b"".join(open(os.path.join(ROOT, "paper_2305_16652_amd", "csrc", f), "rb").read()
+                   for f in ("trace.hip", "hcc_internal.h"))
+    if hashlib.sha256(src).hexdigest()[:16] != kv.get("kernel_sha256_16"):
+        return None
+    return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+
+
+def roofline_of(H, bvh, rays, perm, R, trace_ms_mean):
+    import torch
+    _, _, _, wn, wt = H.trace_stats(bvh, rays, perm)
+    wn_sum = int(wn.to(torch.int64).sum().item())
+    wt_sum = int(wt.to(torch.int64).sum().item())
+    _, nn, nt, wn0, wt0 = H.trace_stats(bvh, rays, None)
+    fetch_nosort = int(wn0.to(torch.int64).sum().item())
+    bytes_per_launch = NODE_BYTES * wn_sum + TRI_BYTES * wt_sum + R * (RAY_BYTES + PERM_BYTES + HIT_BYTES)
+    trace_s = trace_ms_mean * 1e-3
+    achieved = bytes_per_launch / trace_s / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
+                    kernel="k_trace<closest> on HCC-sorted rays",
+                    bytes_per_ray=round(bytes_per_launch / R, 1),
+                    node_fetches_per_ray=round(wn_sum / R, 3), tri_fetches_per_ray=round(wt_sum / R, 3),
+                    node_fetches_per_ray_nosort=round(fetch_nosort / R, 3),
+                    lane_node_visits_per_ray=round(float(nn.to(torch.float64).mean().item()), 2),
+                    lane_tri_tests_per_ray=round(float(nt.to(torch.float64).mean().item()), 2))
+    log(f"roofline: {achieved:.0f} GB/s of algorithmic traffic ({roofline['frac']:.3f} of HBM peak), "
+        f"wave node fetches/ray {roofline['node_fetches_per_ray']} vs NoSort {roofline['node_fetches_per_ray_nosort']}")
+    return roofline
+
+
+def cpu_baseline(tris_h, sec, args, gpu_hits):
+    """The oracle's encode + sort + trace on a strided sample of the same secondary rays."""
+    import oracle as O
+    cores = len(os.sched_getaffinity(0))
+    sample = np.ascontiguousarray(sec[:: args.cpu_stride])
+    n = sample.shape[0]
+    log(f"CPU oracle on {n} rays with {cores} threads")
+    ob = O.build_bvh(tris_h)
+    ids = O.select_cut(ob, O.had(ob), args.cut)
+    cb = O.cut_boxes(ob, ids)
+    t0 = time.time()
+    keys = O.encode_hcc(sample, cb, args.key_bits, threads=cores)
+    perm = O.sort(keys)
+    h = O.trace(ob, sample, perm=perm, threads=cores)
+    dt = time.time() - t0
+    g = gpu_hits[:: args.cpu_stride]
+    agree = float(np.mean(g[:, 1].copy().view(np.uint32) == h.prim))
+    log(f"CPU oracle: {dt:.1f}s, {n / dt / 1e6:.3f} Mrays/s; prim agreement with GPU {agree:.6f}")
+    return dict(value=round(n / dt / 1e6, 4), unit="Mrays/s", cores=cores, kind="oracle",
+                sample=f"every {args.cpu_stride}th bounce-1 secondary ray ({n} rays): HCC encode + stable sort + "
+                       f"closest-hit trace, {dt:.1f} s wall",
+                prim_agreement_with_gpu=agree)
+
+
+if __name__ == "__main__":
+    main()

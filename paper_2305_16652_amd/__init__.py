@@ -134,7 +134,7 @@ class BVH:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:
             lib.hcc_bvh_destroy(h)
             self._h = C.c_void_p(0)
 
@@ -162,7 +162,7 @@ class Cut:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:
             lib.hcc_cut_destroy(h)
             self._h = C.c_void_p(0)
 
