@@ -7,14 +7,16 @@ secondary rays (one per primary hit, 16.6M) are the measured batch, and the two 
 rays per primary hit (33.2M) give the any-hit numbers.  Rays are generated once (primary
 hits come from the library's own trace) and stay resident in HBM.
 
-A step = HCC encode (cut of 32 nodes, 32-bit keys) + stable radix sort + closest-hit trace
-through the sorted permutation over the whole batch.  The same batch is also timed for
-NoSort (trace in generation order) and TwoPoint (32-bit 6-D Morton key) for comparison.
-Prints one JSON line on stdout; progress goes to stderr.
+A step = HCC encode + stable radix sort + closest-hit trace through the sorted permutation
+over the whole batch.  The same batch is also timed for NoSort (trace in generation order)
+and TwoPoint (6-D Morton key).  Each method runs in its own fastest configuration, chosen
+before the timed region by the autotuner (trace launch options; key length; for HCC the cut
+size, C = K as in the paper).  Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -44,10 +46,16 @@ def parse():
     ap.add_argument("--spp", type=int, default=8)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--tune", type=int, default=1, help="autotune each method (0: use the flags below)")
     ap.add_argument("--cut", type=int, default=32)
     ap.add_argument("--key-bits", type=int, default=32)
     ap.add_argument("--block", type=int, default=64)
-    ap.add_argument("--stack", type=int, default=1, help="0 LDS, 1 scratch, 2 LDS+scratch")
+    ap.add_argument("--stack", type=int, default=0, help="0 scratch, 1 LDS, 2 LDS+scratch")
+    ap.add_argument("--persistent", type=int, default=1)
+    ap.add_argument("--refill", type=int, default=32)
+    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--waves", type=int, default=8192)
+    ap.add_argument("--flags", type=int, default=1)
     ap.add_argument("--remap", type=int, default=0, help="1 = XCD-contiguous block order")
     ap.add_argument("--methods", default="nosort,twopoint,hcc")
     ap.add_argument("--no-stats", action="store_true", help="skip the fetch-counting trace (roofline bytes)")
@@ -70,6 +78,7 @@ def main():
     import torch
 
     import paper_2305_16652_amd as H
+    from paper_2305_16652_amd import autotune as AT
     import workloads as W
 
     torch.cuda.set_device(0)
@@ -89,7 +98,6 @@ def main():
     tris_h = spec.tris
     tris = torch.from_numpy(tris_h).to(dev)
     log(f"scene {tris_h.shape[0]} triangles ({time.time() - t0:.1f}s)")
-
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     e0, e1 = ev(), ev()
     e0.record()
@@ -97,17 +105,13 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     build_ms = e0.elapsed_time(e1)
-    e0.record()
-    cut = H.select_cut(bvh, args.cut)
-    e1.record()
-    torch.cuda.synchronize()
-    cut_ms = e0.elapsed_time(e1)
-    log(f"BVH built in {build_ms:.1f} ms, cut of {cut.c_eff} in {cut_ms:.1f} ms")
 
+    flag_opts = H.TraceOpts(args.block, args.stack, args.remap, args.persistent, args.refill, args.chunk,
+                            args.waves, args.flags)
     t0 = time.time()
     prim = W.pinhole_rays(spec, args.width, args.height, args.spp, seed=2)
     prim_d = torch.from_numpy(prim).to(dev)
-    ph = H.trace(bvh, prim_d, opts=H.TraceOpts(args.block, args.stack, args.remap, 0)).cpu().numpy()
+    ph = H.trace(bvh, prim_d, opts=flag_opts).cpu().numpy()
     del prim_d
     p_t = ph[:, 0].copy()
     p_prim = ph[:, 1].copy().view(np.uint32)
@@ -122,44 +126,72 @@ def main():
         log(f"{shadow.shape[0]} shadow rays")
     del prim, ph
 
-    K = args.key_bits
-    kdt = torch.int32 if K <= 32 else torch.int64
-    keys = torch.empty(R, dtype=kdt, device=dev)
-    perm = torch.empty(R, dtype=torch.int32, device=dev)
-    ws = torch.empty(H.sort_workspace_bytes(R, K), dtype=torch.uint8, device=dev)
-    hits = torch.empty((R, 4), dtype=torch.float32, device=dev)
-    opts = H.TraceOpts(args.block, args.stack, args.remap, 0)
-
-    def run(method: str, stage_events=None):
-        if method == "nosort":
-            if stage_events:
-                stage_events[0].record()
-            H.trace(bvh, rays, None, out=hits, opts=opts)
-            if stage_events:
-                stage_events[3].record()
-            return
-        if stage_events:
-            stage_events[0].record()
-        if method == "hcc":
-            H.encode(bvh, cut, H.KEY_HCC, K, rays, out=keys)
+    # ------------------------------------------------------------------ configuration per method
+    t0 = time.time()
+    conf = {}
+    if "nosort" in methods:
+        o = AT.tune_trace(bvh, rays, None)[0] if args.tune else flag_opts
+        conf["nosort"] = dict(cut=0, key_bits=0, opts=o)
+    for m in ("twopoint", "hcc"):
+        if m not in methods:
+            continue
+        if args.tune:
+            ch, _ = AT.tune_reorder(bvh, rays, m)
+            conf[m] = dict(cut=ch.cut, key_bits=ch.key_bits, opts=ch.opts)
         else:
-            H.encode(bvh, None, H.KEY_TWOPOINT, K, rays, out=keys)
-        if stage_events:
-            stage_events[1].record()
-        H.sort(keys, K, perm=perm, ws=ws)
-        if stage_events:
-            stage_events[2].record()
-        H.trace(bvh, rays, perm, out=hits, opts=opts)
-        if stage_events:
-            stage_events[3].record()
+            conf[m] = dict(cut=args.cut if m == "hcc" else 0, key_bits=args.key_bits, opts=flag_opts)
+    if args.tune:
+        log(f"autotuned in {time.time() - t0:.1f}s: " +
+            "; ".join(f"{m} C={c['cut']} K={c['key_bits']} {AT.opts_dict(c['opts'])}" for m, c in conf.items()))
+    e0.record()
+    cuts = {m: H.select_cut(bvh, c["cut"]) for m, c in conf.items() if m == "hcc"}
+    e1.record()
+    torch.cuda.synchronize()
+    cut_ms = e0.elapsed_time(e1)
+
+    hits = torch.empty((R, 4), dtype=torch.float32, device=dev)
+    bufs = {}
+    for m, c in conf.items():
+        if m == "nosort":
+            continue
+        k = c["key_bits"]
+        bufs[m] = dict(keys=torch.empty(R, dtype=torch.int32 if k <= 32 else torch.int64, device=dev),
+                       perm=torch.empty(R, dtype=torch.int32, device=dev),
+                       ws=torch.empty(H.sort_workspace_bytes(R, k), dtype=torch.uint8, device=dev))
+
+    def run(method: str, evs=None, rr=None, closest=True, out=None, b=None):
+        rr = rays if rr is None else rr
+        out = hits if out is None else out
+        b = bufs.get(method) if b is None else b
+        c = conf[method]
+        if evs:
+            evs[0].record()
+        perm = None
+        if method != "nosort":
+            k = c["key_bits"]
+            if method == "hcc":
+                H.encode(bvh, cuts["hcc"], H.KEY_HCC, k, rr, out=b["keys"])
+            else:
+                H.encode(bvh, None, H.KEY_TWOPOINT, k, rr, out=b["keys"])
+            if evs:
+                evs[1].record()
+            H.sort(b["keys"], k, perm=b["perm"], ws=b["ws"])
+            perm = b["perm"]
+        elif evs:
+            evs[1].record()
+        if evs:
+            evs[2].record()
+        H.trace(bvh, rr, perm, closest=closest, out=out, opts=c["opts"])
+        if evs:
+            evs[3].record()
 
     def timed(method: str):
         for _ in range(args.warmup):
             run(method)
         torch.cuda.synchronize()
         evs = [[ev() for _ in range(4)] for _ in range(args.steps)]
-        torch.cuda.synchronize()
         start, stop = ev(), ev()
+        torch.cuda.synchronize()
         t_wall = time.time()
         start.record()
         for s in range(args.steps):
@@ -167,72 +199,59 @@ def main():
         stop.record()
         torch.cuda.synchronize()
         wall = time.time() - t_wall
-        total_ms = start.elapsed_time(stop)
-        enc = [e[0].elapsed_time(e[1]) for e in evs] if method != "nosort" else [0.0]
-        srt = [e[1].elapsed_time(e[2]) for e in evs] if method != "nosort" else [0.0]
-        trc = [(e[2] if method != "nosort" else e[0]).elapsed_time(e[3]) for e in evs]
-        ms = total_ms / args.steps
+        ms = start.elapsed_time(stop) / args.steps
+        enc = [e[0].elapsed_time(e[1]) for e in evs]
+        srt = [e[1].elapsed_time(e[2]) for e in evs]
+        trc = [e[2].elapsed_time(e[3]) for e in evs]
         res = dict(ms_per_step=ms, mrays_s=R / (ms * 1e-3) / 1e6, encode_ms=float(np.median(enc)),
-                   sort_ms=float(np.median(srt)), trace_ms=float(np.median(trc)),
-                   trace_ms_mean=float(np.mean(trc)), trace_only_mrays_s=R / (np.median(trc) * 1e-3) / 1e6,
-                   wall_s=wall)
+                   sort_ms=float(np.median(srt)), trace_ms=float(np.median(trc)), trace_ms_mean=float(np.mean(trc)),
+                   trace_only_mrays_s=R / (np.median(trc) * 1e-3) / 1e6, wall_s=wall)
         log(f"{method}: {ms:.3f} ms/step ({res['mrays_s']:.1f} Mrays/s), encode {res['encode_ms']:.3f} "
             f"sort {res['sort_ms']:.3f} trace {res['trace_ms']:.3f} ms")
         return res
 
-    results = {}
-    for m in ("nosort", "twopoint", "hcc"):
-        if m in methods:
-            results[m] = timed(m)
+    results = {m: timed(m) for m in ("nosort", "twopoint", "hcc") if m in conf}
     hcc_hits = hits.clone()
 
-    # any-hit (shadow) rays: NoSort vs HCC incl. encode+sort, median of the steps
+    # any-hit (shadow) rays, each method in its secondary-ray configuration
     shadow_res = None
     if shadow is not None:
         S = shadow.shape[0]
         occ = torch.empty(S, dtype=torch.uint8, device=dev)
-        skeys = torch.empty(S, dtype=kdt, device=dev)
-        sperm = torch.empty(S, dtype=torch.int32, device=dev)
-        sws = torch.empty(H.sort_workspace_bytes(S, K), dtype=torch.uint8, device=dev)
-        shadow_res = {}
-        for m in [x for x in ("nosort", "twopoint", "hcc") if x in methods]:
+        shadow_res = {"rays": S}
+        for m in conf:
+            sb = None
+            if m != "nosort":
+                k = conf[m]["key_bits"]
+                sb = dict(keys=torch.empty(S, dtype=torch.int32 if k <= 32 else torch.int64, device=dev),
+                          perm=torch.empty(S, dtype=torch.int32, device=dev),
+                          ws=torch.empty(H.sort_workspace_bytes(S, k), dtype=torch.uint8, device=dev))
             times = []
             for s in range(args.warmup + args.steps):
                 a, b = ev(), ev()
                 a.record()
-                if m != "nosort":
-                    if m == "hcc":
-                        H.encode(bvh, cut, H.KEY_HCC, K, shadow, out=skeys)
-                    else:
-                        H.encode(bvh, None, H.KEY_TWOPOINT, K, shadow, out=skeys)
-                    H.sort(skeys, K, perm=sperm, ws=sws)
-                    H.trace(bvh, shadow, sperm, closest=False, out=occ, opts=opts)
-                else:
-                    H.trace(bvh, shadow, None, closest=False, out=occ, opts=opts)
+                run(m, rr=shadow, closest=False, out=occ, b=sb)
                 b.record()
                 torch.cuda.synchronize()
                 if s >= args.warmup:
                     times.append(a.elapsed_time(b))
             ms = float(np.median(times))
-            shadow_res[m] = dict(ms=ms, mrays_s=S / (ms * 1e-3) / 1e6)
-        shadow_res["rays"] = S
-        log("shadow: " + ", ".join(f"{m} {v['mrays_s']:.0f}" for m, v in shadow_res.items() if m != "rays"))
+            shadow_res[m] = dict(ms=round(ms, 4), mrays_s=round(S / (ms * 1e-3) / 1e6, 2))
+            del sb
+        log("shadow Mrays/s: " + ", ".join(f"{m} {shadow_res[m]['mrays_s']:.0f}" for m in conf))
 
-    # ------------------------------------------------------------------ roofline of the trace kernel
-    # algorithmic bytes: per wavefront and lockstep iteration, every distinct node (64 B) and
-    # triangle (48 B) fetched, plus each ray's record, permutation entry and hit record
-    if args.no_stats or "hcc" not in results:
-        roofline = None
-    else:
-        roofline = roofline_of(H, bvh, rays, perm, R, results["hcc"]["trace_ms_mean"])
-
-    # ------------------------------------------------------------------ CPU oracle baseline
+    roofline = None
+    if not args.no_stats and "hcc" in results:
+        roofline = roofline_of(H, bvh, rays, bufs["hcc"]["perm"], R, results["hcc"]["trace_ms_mean"],
+                               conf["hcc"]["opts"])
     cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(tris_h, sec, args, hcc_hits.cpu().numpy())
+    if not args.no_cpu and "hcc" in conf:
+        cpu = cpu_baseline(tris_h, sec, args, hcc_hits.cpu().numpy(), conf["hcc"]["cut"], conf["hcc"]["key_bits"])
 
-    hcc = results.get("hcc") or next(iter(results.values()))
+    head = "hcc" if "hcc" in results else next(iter(results))
+    hcc = results[head]
     nos, tpt = results.get("nosort"), results.get("twopoint")
+    hc = conf[head]
     line = {
         "metric": METRIC,
         "value": round(hcc["mrays_s"], 2),
@@ -249,11 +268,13 @@ def main():
         "config": {
             "workload": (f"frame: {tris_h.shape[0]:,}-triangle room with 100 icospheres + 100 tori, "
                          f"{args.width}x{args.height}x{args.spp} spp, bounce-1 diffuse secondary rays; "
-                         f"HCC cut {cut.c_eff} nodes, {K}-bit keys"),
-            "triangles": int(tris_h.shape[0]), "rays": int(R), "cut": int(cut.c_eff), "key_bits": K,
-            "trace_block": args.block, "stack": args.stack, "xcd_remap": args.remap,
+                         f"{head} cut {hc['cut']} nodes, {hc['key_bits']}-bit keys"),
+            "triangles": int(tris_h.shape[0]), "rays": int(R), "cut": hc["cut"], "key_bits": hc["key_bits"],
+            "trace_opts": AT.opts_dict(hc["opts"]),
         },
-        "methods": {m: {k: round(v, 4) for k, v in r.items()} for m, r in results.items()},
+        "methods": {m: dict({k: round(v, 4) for k, v in r.items()}, cut=conf[m]["cut"],
+                            key_bits=conf[m]["key_bits"], trace_opts=AT.opts_dict(conf[m]["opts"]))
+                    for m, r in results.items()},
         "speedup_vs_nosort": round(hcc["mrays_s"] / nos["mrays_s"], 3) if nos else None,
         "speedup_vs_twopoint": round(hcc["mrays_s"] / tpt["mrays_s"], 3) if tpt else None,
         "shadow": shadow_res,
@@ -268,7 +289,6 @@ def main():
 def measured_traffic():
     """HBM bytes per trace launch from the committed PMC summary, if it still describes the
     current trace kernel sources (else None)."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "trace_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -280,19 +300,21 @@ def measured_traffic():
     return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
 
 
-def roofline_of(H, bvh, rays, perm, R, trace_ms_mean):
+def roofline_of(H, bvh, rays, perm, R, trace_ms_mean, opts):
+    """Roofline of the trace kernel.  Algorithmic bytes per launch: for each wavefront of 64
+    consecutive rays in trace order and each lockstep iteration, every distinct node (64 B) and
+    triangle (48 B) fetched, plus each ray's record, permutation entry and hit record."""
     import torch
-    _, _, _, wn, wt = H.trace_stats(bvh, rays, perm)
+    _, nn, nt, wn, wt = H.trace_stats(bvh, rays, perm)
     wn_sum = int(wn.to(torch.int64).sum().item())
     wt_sum = int(wt.to(torch.int64).sum().item())
-    _, nn, nt, wn0, wt0 = H.trace_stats(bvh, rays, None)
+    _, _, _, wn0, _ = H.trace_stats(bvh, rays, None)
     fetch_nosort = int(wn0.to(torch.int64).sum().item())
     bytes_per_launch = NODE_BYTES * wn_sum + TRI_BYTES * wt_sum + R * (RAY_BYTES + PERM_BYTES + HIT_BYTES)
-    trace_s = trace_ms_mean * 1e-3
-    achieved = bytes_per_launch / trace_s / 1e9
+    achieved = bytes_per_launch / (trace_ms_mean * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
-                    kernel="k_trace<closest> on HCC-sorted rays",
+                    kernel=("k_trace_persistent" if opts.persistent else "k_trace") + "<closest> on HCC-sorted rays",
                     bytes_per_ray=round(bytes_per_launch / R, 1),
                     node_fetches_per_ray=round(wn_sum / R, 3), tri_fetches_per_ray=round(wt_sum / R, 3),
                     node_fetches_per_ray_nosort=round(fetch_nosort / R, 3),
@@ -303,7 +325,7 @@ def roofline_of(H, bvh, rays, perm, R, trace_ms_mean):
     return roofline
 
 
-def cpu_baseline(tris_h, sec, args, gpu_hits):
+def cpu_baseline(tris_h, sec, args, gpu_hits, cut_size, key_bits):
     """The oracle's encode + sort + trace on a strided sample of the same secondary rays."""
     import oracle as O
     cores = len(os.sched_getaffinity(0))
@@ -311,10 +333,9 @@ def cpu_baseline(tris_h, sec, args, gpu_hits):
     n = sample.shape[0]
     log(f"CPU oracle on {n} rays with {cores} threads")
     ob = O.build_bvh(tris_h)
-    ids = O.select_cut(ob, O.had(ob), args.cut)
-    cb = O.cut_boxes(ob, ids)
+    cb = O.cut_boxes(ob, O.select_cut(ob, O.had(ob), cut_size))
     t0 = time.time()
-    keys = O.encode_hcc(sample, cb, args.key_bits, threads=cores)
+    keys = O.encode_hcc(sample, cb, key_bits, threads=cores)
     perm = O.sort(keys)
     h = O.trace(ob, sample, perm=perm, threads=cores)
     dt = time.time() - t0
@@ -322,8 +343,8 @@ def cpu_baseline(tris_h, sec, args, gpu_hits):
     agree = float(np.mean(g[:, 1].copy().view(np.uint32) == h.prim))
     log(f"CPU oracle: {dt:.1f}s, {n / dt / 1e6:.3f} Mrays/s; prim agreement with GPU {agree:.6f}")
     return dict(value=round(n / dt / 1e6, 4), unit="Mrays/s", cores=cores, kind="oracle",
-                sample=f"every {args.cpu_stride}th bounce-1 secondary ray ({n} rays): HCC encode + stable sort + "
-                       f"closest-hit trace, {dt:.1f} s wall",
+                sample=f"every {args.cpu_stride}th bounce-1 secondary ray ({n} rays): HCC encode (C={cut_size}, "
+                       f"K={key_bits}) + stable sort + closest-hit trace, {dt:.1f} s wall",
                 prim_agreement_with_gpu=agree)
 
 

@@ -54,9 +54,9 @@ typedef enum {
 typedef enum { HCC_TRACE_CLOSEST = 0, HCC_TRACE_ANY = 1 } hcc_trace_mode;
 
 typedef enum {
-    HCC_STACK_LDS = 0,        /* per-lane traversal stack in LDS (64 entries) */
-    HCC_STACK_SCRATCH = 1,    /* per-lane traversal stack in private (scratch) memory */
-    HCC_STACK_SHORT = 2       /* short stack in registers, spilling to an LDS stack */
+    HCC_STACK_SCRATCH = 0,    /* per-lane traversal stack in private (scratch) memory (default) */
+    HCC_STACK_LDS = 1,        /* per-lane traversal stack in LDS (64 entries) */
+    HCC_STACK_SHORT = 2       /* first 16 entries in LDS, deeper entries in scratch */
 } hcc_stack_mode;
 
 typedef struct hcc_bvh_s* hcc_bvh;
@@ -68,10 +68,14 @@ typedef struct hcc_hit { float t; uint32_t prim; float u, v; } hcc_hit;   /* mis
 
 /* Launch options of the trace kernel (the autotuner's knobs).  Zero-initialised = defaults. */
 typedef struct hcc_trace_opts {
-    uint32_t block;           /* threads per block: 64, 128 or 256 (0 = 128) */
+    uint32_t block;           /* one-ray-per-lane launch: threads per block, 64, 128 or 256 (0 = 64) */
     uint32_t stack;           /* hcc_stack_mode */
     uint32_t xcd_remap;       /* 1 = give each XCD a contiguous range of rays (0 = hardware order) */
-    uint32_t reserved;
+    uint32_t persistent;      /* 1 = persistent wavefronts that refill idle lanes with new rays */
+    uint32_t refill;          /* persistent: refill when at least this many lanes are idle, 1..64 (0 = 16) */
+    uint32_t chunk;           /* persistent: consecutive rays a wavefront owns at a time, >= 64 (0 = 256) */
+    uint32_t waves;           /* persistent: wavefronts launched (0 = 8192) */
+    uint32_t flags;           /* persistent: bit 0 = keep descending while one leaf is postponed */
 } hcc_trace_opts;
 
 /* ---------------------------------------------------------------------------------------

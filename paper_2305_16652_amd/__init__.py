@@ -29,7 +29,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhcc.so")
 
 KEY_NONE, KEY_HCC, KEY_TWOPOINT = 0, 1, 2
 CLOSEST, ANY = 0, 1
-STACK_LDS, STACK_SCRATCH, STACK_SHORT = 0, 1, 2
+STACK_SCRATCH, STACK_LDS, STACK_SHORT = 0, 1, 2
 _STATUS = {0: "HCC_OK", 1: "HCC_ERR_INVALID", 2: "HCC_ERR_OOM", 3: "HCC_ERR_DEVICE", 4: "HCC_ERR_UNSUPPORTED",
            5: "HCC_ERR_BUDGET"}
 
@@ -41,7 +41,10 @@ class HCCError(RuntimeError):
 
 
 class TraceOpts(C.Structure):
-    _fields_ = [("block", C.c_uint32), ("stack", C.c_uint32), ("xcd_remap", C.c_uint32), ("reserved", C.c_uint32)]
+    """hcc_trace_opts: block, stack, xcd_remap, persistent, refill, chunk, waves, flags (0 = default)."""
+    _fields_ = [("block", C.c_uint32), ("stack", C.c_uint32), ("xcd_remap", C.c_uint32),
+                ("persistent", C.c_uint32), ("refill", C.c_uint32), ("chunk", C.c_uint32),
+                ("waves", C.c_uint32), ("flags", C.c_uint32)]
 
 
 if not os.path.exists(LIB_PATH):

@@ -49,11 +49,13 @@ __device__ __forceinline__ bool slab(float ox, float oy, float oz, float ix, flo
     float t0x = (lx - ox) * ix, t1x = (hx - ox) * ix;
     float t0y = (ly - oy) * iy, t1y = (hy - oy) * iy;
     float t0z = (lz - oz) * iz, t1z = (hz - oz) * iz;
-    float nx = fminf(t0x, t1x), fx = fmaxf(t0x, t1x) * 0x1.000006p+0f;
-    float ny = fminf(t0y, t1y), fy = fmaxf(t0y, t1y) * 0x1.000006p+0f;
-    float nz = fminf(t0z, t1z), fz = fmaxf(t0z, t1z) * 0x1.000006p+0f;
+    float nx = fminf(t0x, t1x), fx = fmaxf(t0x, t1x);
+    float ny = fminf(t0y, t1y), fy = fmaxf(t0y, t1y);
+    float nz = fminf(t0z, t1z), fz = fmaxf(t0z, t1z);
     tnear = fmaxf(fmaxf(fmaxf(nx, ny), nz), tmin);
-    float tfar = fminf(fminf(fminf(fx, fy), fz), tmax);
+    // scaling after the minimum equals scaling each axis first: rounding of a product by a
+    // positive constant is monotone, and a NaN axis is dropped by fminf either way
+    float tfar = fminf(fminf(fminf(fx, fy), fz) * 0x1.000006p+0f, tmax);
     return tnear <= tfar;
 }
 

@@ -193,6 +193,166 @@ __global__ __launch_bounds__(kBlock) void k_trace(const Node* __restrict__ nodes
     }
 }
 
+__device__ __forceinline__ uint64_t lanes_below() {
+    const uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64u - lane));
+}
+
+// Persistent wavefronts (one wavefront per block).  Wavefront b owns chunks b, b + grid,
+// b + 2 grid, ... of the trace order; whenever at least 'refill' of its lanes are idle it
+// hands them the next rays of its current chunk.  Lanes whose ray finished early therefore
+// pick up new work instead of idling until the wavefront's slowest ray completes, and the
+// rays in flight in one wavefront stay neighbours in the (sorted) order.
+//
+// Leaf triangles are not tested inside the node step: a lane that meets leaves records up
+// to two of them and pauses; the wavefront runs the triangle tests as one batch once at
+// least half of its busy lanes have some pending (or no lane can step), so the triangle
+// code runs with most lanes active instead of in a branch taken by a few.  Every wave-level
+// decision is taken on ballots (uniform values); the loop ends once the wavefront's chunks
+// are exhausted and all lanes are idle.
+template <bool kClosest, int kStack, bool kSpec>
+__global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict__ nodes, const Tri* __restrict__ tris,
+                                                         uint32_t n_int, const float4* __restrict__ rays,
+                                                         const uint32_t* __restrict__ perm, uint32_t n,
+                                                         float4* __restrict__ hits, uint8_t* __restrict__ occ,
+                                                         uint32_t refill, uint32_t chunk) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    __shared__ uint32_t s_stack[lds_entries<kStack>() * 64];
+    const uint32_t nchunks = (n + chunk - 1) / chunk;
+    uint32_t cidx = blockIdx.x;
+    if (cidx >= nchunks) return;
+    uint32_t next = cidx * chunk;
+    uint32_t end = min(next + chunk, n);
+    const uint64_t below = lanes_below();
+    Stack<kStack, 64> st;
+    st.init(s_stack);
+    bool has = false;
+    uint32_t rid = 0, node = kNone, sp = 0, best_prim = kMissPrim;
+    uint32_t pend0 = kNone, pend1 = kNone, pend2 = kNone;   // postponed leaves (triangle slots)
+    float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0, tmin = 0, tmax = 0;
+    float best_t = 0, best_u = 0, best_v = 0;
+    bool found = false;
+
+    auto test_tri = [&](uint32_t slot) {
+        const Tri tr = tris[slot];
+        const uint32_t prim = __float_as_uint(tr.r.y);
+        float t, u, v;
+        if (tri_test(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v)) {
+            if (!kClosest) {
+                found = true;
+            } else if (t < best_t || (t == best_t && prim < best_prim)) {
+                best_t = t; best_u = u; best_v = v; best_prim = prim;
+                found = true;
+            }
+        }
+    };
+
+    while (true) {
+        // ---- refill idle lanes from the current chunk
+        const uint64_t idle = __ballot(!has);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (nidle >= refill) {
+            while (next >= end && cidx < nchunks) {
+                cidx += gridDim.x;
+                if (cidx < nchunks) {
+                    next = cidx * chunk;
+                    end = min(next + chunk, n);
+                }
+            }
+            if (next < end) {
+                const uint32_t k = next + (uint32_t)__popcll(idle & below);
+                if (!has && k < end) {
+                    rid = perm ? perm[k] : k;
+                    if (rid < n) {
+                        const float4 ra = rays[2 * (size_t)rid];
+                        const float4 rb = rays[2 * (size_t)rid + 1];
+                        ox = ra.x; oy = ra.y; oz = ra.z; tmin = ra.w;
+                        dx = rb.x; dy = rb.y; dz = rb.z; tmax = rb.w;
+                        ix = 1.0f / dx; iy = 1.0f / dy; iz = 1.0f / dz;
+                        best_t = tmax; best_u = 0.0f; best_v = 0.0f;
+                        best_prim = kMissPrim;
+                        found = false;
+                        node = 0;
+                        sp = 0;
+                        pend0 = pend1 = pend2 = kNone;
+                        has = true;
+                    }
+                }
+                next = min(next + nidle, end);
+            } else if (nidle == 64) {
+                break;
+            }
+        }
+
+        // ---- one node step for lanes with a node and room for two more postponed leaves
+        // (kSpec: a lane keeps descending while it holds one postponed leaf)
+        if (has && node != kNone && (kSpec ? pend1 == kNone : pend0 == kNone)) {
+            const Node nd = nodes[node];
+            const float lim = kClosest ? best_t : tmax;
+            float tn0, tn1;
+            bool h0 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, tn0);
+            bool h1 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, tn1);
+            const uint32_t c0 = nd.d.x, c1 = nd.d.y;
+            const bool leaf0 = h0 && c0 >= n_int;
+            const bool leaf1 = h1 && c1 >= n_int;
+            // append the hit leaves to the postponed list
+            if (leaf0 || leaf1) {
+                const uint32_t a = leaf0 ? c0 - n_int : c1 - n_int;
+                const uint32_t b = (leaf0 && leaf1) ? c1 - n_int : kNone;
+                if (pend0 == kNone) {
+                    pend0 = a;
+                    pend1 = b;
+                } else {
+                    pend1 = a;
+                    pend2 = b;
+                }
+            }
+            h0 = h0 && !leaf0;
+            h1 = h1 && !leaf1;
+            if (h0 && h1) {
+                const bool near1 = tn1 < tn0;
+                st.push(sp, near1 ? c0 : c1);
+                ++sp;
+                node = near1 ? c1 : c0;
+            } else if (h0) {
+                node = c0;
+            } else if (h1) {
+                node = c1;
+            } else if (sp == 0) {
+                node = kNone;
+            } else {
+                --sp;
+                node = st.pop(sp);
+            }
+        }
+
+        // ---- batched leaf tests
+        const uint64_t busy = __ballot(has);
+        const bool can_step = has && node != kNone && (kSpec ? pend1 == kNone : pend0 == kNone);
+        const uint64_t waiting = __ballot(has && pend0 != kNone && !can_step);
+        const uint64_t stepping = __ballot(can_step);
+        if (waiting != 0 && (2 * __popcll(waiting) >= __popcll(busy) || stepping == 0)) {
+            if (has && pend0 != kNone) {
+                test_tri(pend0);
+                if (pend1 != kNone && (kClosest || !found)) test_tri(pend1);
+                if (kSpec && pend2 != kNone && (kClosest || !found)) test_tri(pend2);
+                pend0 = pend1 = pend2 = kNone;
+                if (!kClosest && found) node = kNone;
+            }
+        }
+
+        // ---- finished rays
+        if (has && node == kNone && pend0 == kNone) {
+            if (kClosest)
+                hits[rid] = make_float4(found ? best_t : INFINITY, __uint_as_float(found ? best_prim : kMissPrim),
+                                        found ? best_u : 0.0f, found ? best_v : 0.0f);
+            else
+                occ[rid] = found ? 1 : 0;
+            has = false;
+        }
+    }
+}
+
 template <bool kClosest, int kStack, int kBlock, bool kStats>
 void launch(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, hcc_hit* hits, uint8_t* occ,
             uint32_t remap, uint32_t* cn, uint32_t* ct, uint32_t* wn, uint32_t* wt, hipStream_t stream) {
@@ -227,7 +387,39 @@ hcc_status dispatch_stack(uint32_t stack, uint32_t block, const hcc_bvh_s* b, co
 
 hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
                  hcc_hit* hits, uint8_t* occ, const hcc_trace_opts& o, hipStream_t s) {
-    const uint32_t block = o.block ? o.block : 128;
+    if (o.persistent && b->n_int > 0) {
+        const uint32_t refill = std::min<uint32_t>(64u, std::max<uint32_t>(1u, o.refill ? o.refill : 16u));
+        const uint32_t chunk = std::max<uint32_t>(64u, o.chunk ? o.chunk : 256u);
+        const uint32_t nchunks = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
+        const uint32_t waves = std::min<uint32_t>(nchunks, o.waves ? o.waves : 8192u);
+        const float4* r = (const float4*)rays;
+#define HCC_PERSIST(CL, STK)                                                                                  \
+    do {                                                                                                      \
+        if (o.flags & 1u)                                                                                  \
+            k_trace_persistent<CL, STK, true><<<waves, 64, 0, s>>>(b->nodes, b->tris, b->n_int, r, perm, n,     \
+                                                                   (float4*)hits, occ, refill, chunk);        \
+        else                                                                                                  \
+            k_trace_persistent<CL, STK, false><<<waves, 64, 0, s>>>(b->nodes, b->tris, b->n_int, r, perm, n,    \
+                                                                    (float4*)hits, occ, refill, chunk);       \
+    } while (0)
+        switch (o.stack) {
+            case HCC_STACK_SCRATCH:
+                if (closest) HCC_PERSIST(true, HCC_STACK_SCRATCH); else HCC_PERSIST(false, HCC_STACK_SCRATCH);
+                break;
+            case HCC_STACK_LDS:
+                if (closest) HCC_PERSIST(true, HCC_STACK_LDS); else HCC_PERSIST(false, HCC_STACK_LDS);
+                break;
+            case HCC_STACK_SHORT:
+                if (closest) HCC_PERSIST(true, HCC_STACK_SHORT); else HCC_PERSIST(false, HCC_STACK_SHORT);
+                break;
+            default:
+                return fail(HCC_ERR_INVALID, "hcc_trace: unknown stack mode");
+        }
+#undef HCC_PERSIST
+        HCC_HIP(hipGetLastError());
+        return HCC_OK;
+    }
+    const uint32_t block = o.block ? o.block : 64;
     if (closest)
         return dispatch_stack<true, false>(o.stack, block, b, rays, perm, n, hits, occ, o.xcd_remap, nullptr, nullptr,
                                            nullptr, nullptr, s);

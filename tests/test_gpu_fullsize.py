@@ -20,7 +20,9 @@ from parity_utils import assert_any, assert_closest, assert_stable_sort
 pytestmark = pytest.mark.gpu
 
 THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
-BENCH_OPTS = (64, 1, 0)   # bench.py defaults: 64-lane blocks, scratch stack, hardware block order
+# bench.py's default launch configuration (block, stack, remap, persistent, refill, chunk, waves, flags);
+# the autotuner picks among these and the one-ray-per-lane launch, which test_gpu_parity covers
+BENCH_OPTS = (64, 0, 0, 1, 32, 64, 8192, 1)
 
 
 def _say(msg):
@@ -47,7 +49,7 @@ def frame():
 
 
 def _opts(H):
-    return H.TraceOpts(*BENCH_OPTS, 0)
+    return H.TraceOpts(*BENCH_OPTS)
 
 
 def test_fullsize_bvh_and_cut(frame):

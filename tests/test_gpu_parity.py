@@ -167,12 +167,17 @@ def test_sort_empty(H):
 
 # ----------------------------------------------------------------------------- trace
 
-OPTS = [(128, 0, 0), (64, 0, 1), (256, 0, 0), (64, 1, 0), (128, 1, 1), (256, 2, 0), (128, 2, 1)]
+# (block, stack, remap, persistent, refill, chunk, waves); stack 0 scratch, 1 LDS, 2 LDS+scratch
+OPTS = [(128, 1, 0, 0, 0, 0, 0), (64, 1, 1, 0, 0, 0, 0), (256, 1, 0, 0, 0, 0, 0), (64, 0, 0, 0, 0, 0, 0),
+        (128, 0, 1, 0, 0, 0, 0), (256, 2, 0, 0, 0, 0, 0), (128, 2, 1, 0, 0, 0, 0),
+        (0, 0, 0, 1, 16, 256, 0), (0, 1, 0, 1, 1, 64, 3), (0, 2, 0, 1, 64, 1000, 7), (0, 0, 0, 1, 33, 4096, 1),
+        (0, 0, 0, 1, 32, 64, 0, 1), (0, 2, 0, 1, 5, 128, 11, 1)]
 
 
-@pytest.mark.parametrize("block,stack,remap", OPTS)
-def test_trace_closest(H, gpu_bvh, tiny, block, stack, remap):
-    o = H.TraceOpts(block, stack, remap, 0)
+@pytest.mark.parametrize("opt", OPTS)
+def test_trace_closest(H, gpu_bvh, tiny, opt):
+    o = H.TraceOpts(*opt)
+    block, stack = opt[0], opt[1]
     tris = tiny["spec"].tris
     for name in ("primary", "secondary"):
         rays = tiny[name]
@@ -185,9 +190,9 @@ def test_trace_closest(H, gpu_bvh, tiny, block, stack, remap):
         assert np.array_equal(hits_p.view(np.uint32), hits.view(np.uint32))
 
 
-@pytest.mark.parametrize("block,stack,remap", OPTS)
-def test_trace_any(H, gpu_bvh, tiny, block, stack, remap):
-    o = H.TraceOpts(block, stack, remap, 0)
+@pytest.mark.parametrize("opt", OPTS)
+def test_trace_any(H, gpu_bvh, tiny, opt):
+    o = H.TraceOpts(*opt)
     rays = tiny["shadow"]
     ref = O.trace(tiny["ob"], rays, closest=False)
     occ = H.trace(gpu_bvh, _dev(rays), closest=False, opts=o).cpu().numpy()
@@ -284,7 +289,9 @@ def test_invalid_arguments(H, gpu_bvh):
     with pytest.raises(H.HCCError):
         H.select_cut(gpu_bvh, 8, float("nan"))
     with pytest.raises(H.HCCError):
-        H.trace(gpu_bvh, rays, opts=H.TraceOpts(96, 0, 0, 0))
+        H.trace(gpu_bvh, rays, opts=H.TraceOpts(96, 0, 0, 0, 0, 0, 0, 0))
+    with pytest.raises(H.HCCError):
+        H.trace(gpu_bvh, rays, opts=H.TraceOpts(64, 7, 0, 0, 0, 0, 0, 0))
     other = H.build_bvh(torch.tensor([[0, 0, 0, 1, 0, 0, 0, 1, 0]], dtype=torch.float32, device="cuda"))
     with pytest.raises(H.HCCError):
         H.encode(gpu_bvh, H.select_cut(other, 1), H.KEY_HCC, 32, rays)   # cut from another BVH
