@@ -64,6 +64,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-stride", type=int, default=8, help="oracle sample: every k-th secondary ray")
     ap.add_argument("--no-shadow", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch engine workload")
+    ap.add_argument("--no-serve", action="store_true", help="skip the request-server workload")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=50)
     return ap.parse_args()
 
 
@@ -248,6 +252,9 @@ def main():
     if not args.no_cpu and "hcc" in conf:
         cpu = cpu_baseline(tris_h, sec, args, hcc_hits.cpu().numpy(), conf["hcc"]["cut"], conf["hcc"]["key_bits"])
 
+    batched = None if args.no_batched else run_batched(H, args)
+    serve = None if args.no_serve else run_serving(H, args)
+
     head = "hcc" if "hcc" in results else next(iter(results))
     hcc = results[head]
     nos, tpt = results.get("nosort"), results.get("twopoint")
@@ -280,10 +287,200 @@ def main():
         "shadow": shadow_res,
         "build_ms": round(build_ms, 2),
         "select_cut_ms": round(cut_ms, 2),
+        "batched": batched,
+        "serve": serve,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+_SCENES = None
+
+
+def cluster_scenes(H):
+    """The four resident cluster scenes (10K, 100K, 1M, 2M triangles) with device ray pools:
+    bounce-1 diffuse rays and shadow rays from a 1024x512 camera (primary hits from the
+    library's trace)."""
+    global _SCENES
+    if _SCENES is not None:
+        return _SCENES
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    scenes = []
+    for i, n in enumerate((10_000, 100_000, 1_000_000, 2_000_000)):
+        spec = W.cluster_scene(n, seed=40 + i)
+        bvh = H.build_bvh(torch.from_numpy(spec.tris).to(dev))
+        prim = W.pinhole_rays(spec, 1024, 512, 1, seed=50 + i)
+        ph = H.trace(bvh, torch.from_numpy(prim).to(dev)).cpu().numpy()
+        pt, pp = ph[:, 0].copy(), ph[:, 1].copy().view(np.uint32)
+        dif, _ = W.spawn_diffuse(prim, pt, pp, spec.tris, seed=60 + i, bounce=0)
+        shd, _ = W.spawn_shadow(prim, pt, pp, spec.tris, spec.lights)
+        scenes.append(dict(n=n, bvh=bvh, diffuse=torch.from_numpy(dif).to(dev), shadow=torch.from_numpy(shd).to(dev)))
+    _SCENES = scenes
+    return scenes
+
+
+def run_serving(H, args):
+    """Poisson stream of trace requests (ray count log-uniform in [4K, 4M], scene uniform over
+    the 4 resident scenes, 70% closest / 30% any hit) at 3 offered loads relative to the plain
+    one-request-at-a-time capacity, admitted under a 64 GiB budget.  Reports p50/p99 latency
+    and Mrays/s for the continuous-batching server and for the plain FIFO path."""
+    import torch
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    scenes = cluster_scenes(H)
+    cuts = [H.select_cut(s["bvh"], 32) for s in scenes]
+    n_req = args.serve_requests + args.serve_warmup
+    plan = W.batch_plan(n_req, seed=77, lo=4096, hi=4_194_304)
+    pools = {}
+    for si, s in enumerate(scenes):
+        for kind in ("diffuse", "shadow"):
+            p = s[kind]
+            reps = (4_194_304 + p.shape[0] - 1) // p.shape[0] + 1
+            pools[(si, kind)] = p.repeat(reps, 1)[: 4_194_304 + p.shape[0]].contiguous()
+    reqs = []
+    for b in plan:
+        pool = pools[(b["scene"], "diffuse" if b["closest"] else "shadow")]
+        off = b["offset"] % (pool.shape[0] - b["n"] + 1)
+        reqs.append(H.Batch(scenes[b["scene"]]["bvh"], pool[off:off + b["n"]], b["closest"], cut=cuts[b["scene"]]))
+    total_rays = sum(b["n"] for b in plan[args.serve_warmup:])
+
+    def serve(server, rate=None):
+        """Submit every request (at Poisson times if rate is given, else all at once)."""
+        rng = np.random.default_rng(5)
+        gaps = rng.exponential(1.0 / rate, n_req) if rate else np.zeros(n_req)
+        ids = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for i, b in enumerate(reqs):
+            t_next += gaps[i]
+            while time.perf_counter() < t_next:
+                pass
+            ids.append(server.submit(b))
+        server.drain()
+        t_end = time.perf_counter()
+        lat = np.array([server.poll(i)[1] for i in ids[args.serve_warmup:]])
+        return lat, t_end - t_start
+
+    # plain capacity: the FIFO path with every request queued at once
+    plain = H.Server(key_mode=H.KEY_HCC, key_bits=32, plain=True)
+    _, wall = serve(plain)
+    capacity = n_req / wall
+    out = dict(requests=args.serve_requests, warmup=args.serve_warmup, rays=int(total_rays),
+               plain_capacity_req_s=round(capacity, 1), budget_gib=64, loads={})
+    for rho in (0.5, 0.8, 0.95):
+        rate = rho * capacity
+        row = {}
+        for name, server in (("plain", plain), ("continuous", None)):
+            if server is None:
+                server = H.Server(key_mode=H.KEY_HCC, key_bits=32, max_group=16, streams=4)
+            lat, wall = serve(server, rate)
+            row[name] = dict(p50_ms=round(float(np.percentile(lat, 50)) / 1e3, 3),
+                             p99_ms=round(float(np.percentile(lat, 99)) / 1e3, 3),
+                             mrays_s=round(total_rays / wall / 1e6, 1))
+            if name == "continuous":
+                server.close()
+        out["loads"][str(rho)] = row
+        log(f"serve rho={rho}: plain p50 {row['plain']['p50_ms']} p99 {row['plain']['p99_ms']} ms; "
+            f"continuous p50 {row['continuous']['p50_ms']} p99 {row['continuous']['p99_ms']} ms")
+    plain.close()
+    return out
+
+
+def run_batched(H, args):
+    """Uneven-batch workload: 4 resident cluster scenes (10K, 100K, 1M, 2M triangles), 64 batches
+    of log-uniform size in [1K, 2M] rays, 70% closest-hit diffuse / 30% any-hit shadow.  Times
+    the plain path (per batch: encode, sort, trace launches) against the engine's single
+    persistent launch, each for NoSort and for HCC, with the engine's options autotuned."""
+    import torch
+    import workloads as W
+    from paper_2305_16652_amd import autotune as AT
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    scenes = cluster_scenes(H)
+    plan = W.batch_plan(64, seed=21)
+    batches = []
+    for b in plan:
+        s = scenes[b["scene"]]
+        pool = s["diffuse"] if b["closest"] else s["shadow"]
+        idx = (torch.arange(b["n"], device=dev, dtype=torch.int64) + b["offset"] % pool.shape[0]) % pool.shape[0]
+        batches.append(H.Batch(s["bvh"], pool[idx].contiguous(), b["closest"]))
+    total = sum(b["n"] for b in plan)
+    log(f"batched workload: {len(plan)} batches, {total} rays over 4 scenes ({time.time() - t0:.1f}s)")
+
+    def timeit(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            e.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(e))
+        return float(np.median(ts))
+
+    topts = H.TraceOpts(64, 0, 0, 1, 32, 64, 8192, 1)
+    bufs = {}
+
+    def plain(mode, K):
+        for b in batches:
+            n = b.rays.shape[0]
+            perm = None
+            if mode == H.KEY_HCC:
+                key = (id(b), K)
+                if key not in bufs:
+                    bufs[key] = (torch.empty(n, dtype=torch.int32 if K <= 32 else torch.int64, device=dev),
+                                 torch.empty(n, dtype=torch.int32, device=dev),
+                                 torch.empty(H.sort_workspace_bytes(n, K), dtype=torch.uint8, device=dev))
+                keys, perm, ws = bufs[key]
+                H.encode(b.bvh, b.cut, H.KEY_HCC, K, b.rays, out=keys)
+                H.sort(keys, K, perm=perm, ws=ws)
+            H.trace(b.bvh, b.rays, perm, closest=b.closest, out=b.out, opts=topts)
+
+    res = {}
+    cuts = {}
+    for K in (16, 24, 32):
+        cuts[K] = [H.select_cut(s["bvh"], K) for s in scenes]
+    # engine options: autotuned over chunk, refill and key length (cut = key length)
+    best = None
+    table = []
+    for K in (16, 24, 32):
+        for b, p in zip(batches, plan):
+            b.cut = cuts[K][p["scene"]]
+        ws = H.batch_run(batches, H.KEY_HCC, K)
+        for chunk in (128, 256, 512):
+            for refill in (24, 32):
+                o = H.BatchOpts(chunk, refill, 8192, 0)
+                ms = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws), reps=2)
+                table.append((ms, K, chunk, refill))
+                if best is None or ms < best[0]:
+                    best = (ms, K, chunk, refill)
+    _, K, chunk, refill = best
+    for b, p in zip(batches, plan):
+        b.cut = cuts[K][p["scene"]]
+    o = H.BatchOpts(chunk, refill, 8192, 0)
+    ws = H.batch_run(batches, H.KEY_HCC, K, opts=o)
+    res["engine_hcc_ms"] = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws))
+    wsn = H.batch_run(batches, 0, K, opts=o)
+    res["engine_nosort_ms"] = timeit(lambda: H.batch_run(batches, 0, K, opts=o, ws=wsn))
+    res["plain_hcc_ms"] = timeit(lambda: plain(H.KEY_HCC, K))
+    res["plain_nosort_ms"] = timeit(lambda: plain(0, K))
+    out = {k.replace("_ms", "_mrays_s"): round(total / (v * 1e-3) / 1e6, 1) for k, v in res.items()}
+    out.update({k: round(v, 3) for k, v in res.items()})
+    out.update(dict(batches=len(plan), rays=total, key_bits=K, cut=K, engine_opts=dict(chunk=chunk, refill=refill),
+                    plain_trace_opts=AT.opts_dict(topts),
+                    speedup_engine_vs_plain_hcc=round(res["plain_hcc_ms"] / res["engine_hcc_ms"], 3),
+                    scenes="cluster 10K/100K/1M/2M triangles",
+                    tuning=[dict(ms=round(t[0], 3), key_bits=t[1], chunk=t[2], refill=t[3]) for t in sorted(table)[:5]]))
+    log(f"batched: engine HCC {out['engine_hcc_mrays_s']} Mrays/s vs plain {out['plain_hcc_mrays_s']}; "
+        f"NoSort engine {out['engine_nosort_mrays_s']} vs plain {out['plain_nosort_mrays_s']}")
+    return out
 
 
 def measured_traffic():

@@ -170,6 +170,84 @@ hcc_status hcc_trace_stats(hcc_bvh bvh, const hcc_ray* d_rays, const uint32_t* d
                            hcc_trace_mode mode, hcc_hit* d_hits, uint8_t* d_occluded, uint32_t* d_nodes,
                            uint32_t* d_tris, uint32_t* d_wave_nodes, uint32_t* d_wave_tris, hcc_stream stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Batched engine: encode + sort + trace of many ray batches of different sizes over several
+ * resident scenes in ONE persistent launch (not in the paper: the engine around its path).
+ * Each batch is sorted on its own (stable, by its own keys) and traced through its own
+ * permutation, exactly as hcc_encode + hcc_sort + hcc_trace would do it batch by batch, so
+ * the results are identical to that sequence.
+ */
+typedef struct hcc_batch_desc {
+    hcc_bvh bvh;              /* scene of the batch */
+    hcc_cut cut;              /* cut of that scene (HCC_KEY_HCC); ignored otherwise */
+    const hcc_ray* d_rays;    /* device, n rays */
+    uint32_t n;               /* rays in the batch, < 2^30 (0 allowed) */
+    uint32_t mode;            /* hcc_trace_mode */
+    hcc_hit* d_hits;          /* closest hit: n records, by original index within the batch */
+    uint8_t* d_occluded;      /* any hit: n flags, by original index within the batch */
+} hcc_batch_desc;
+
+typedef struct hcc_batch_opts {
+    uint32_t chunk;           /* rays per trace item (>= 64; 0 = 256) */
+    uint32_t refill;          /* lane refill threshold 1..64 (0 = 32) */
+    uint32_t waves;           /* persistent wavefronts launched (0 = 8192) */
+    uint32_t reserved;        /* must be 0 */
+} hcc_batch_opts;
+
+/* Device workspace needed by hcc_batch_run for this batch list, key mode and key length. */
+hcc_status hcc_batch_workspace(const hcc_batch_desc* batches, uint32_t nb, hcc_key_mode mode, uint32_t key_bits,
+                               size_t* bytes);
+
+/* Run the batch list in one persistent launch on the stream (mode HCC_KEY_NONE: trace only, in
+ * generation order).  The host copies a small descriptor table to the workspace and waits for
+ * that copy; the launch itself is asynchronous.  d_ws: hcc_batch_workspace bytes, 256-byte
+ * aligned, not used by another call until this one has finished.  opts may be NULL. */
+hcc_status hcc_batch_run(const hcc_batch_desc* batches, uint32_t nb, hcc_key_mode mode, uint32_t key_bits,
+                         const hcc_batch_opts* opts, void* d_ws, size_t ws_bytes, hcc_stream stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Request server with continuous batching (not in the paper: serving around its path).
+ * A worker thread admits queued requests in arrival order while the device ray-state budget
+ * and the slot limit allow, launches each set of newly admitted requests as one engine batch on
+ * the next of its streams (so later requests overlap with earlier ones still running), and
+ * retires groups when their completion events fire.  A request's budget charge is its rays and
+ * results plus the engine workspace for its size.  Results are exactly those of a lone
+ * hcc_encode + hcc_sort + hcc_trace of the request.  plain = 1 runs one request at a time
+ * through those three calls instead (the baseline).  Buffers named in a request stay owned by
+ * the caller and must stay valid until the request is done or cancelled.
+ */
+typedef struct hcc_server_s* hcc_server;
+
+typedef struct hcc_server_opts {
+    uint64_t budget_bytes;    /* device bytes of admitted requests (0 = 64 GiB) */
+    uint32_t max_inflight;    /* admitted requests at once (0 = 64) */
+    uint32_t max_group;       /* requests per launch (0 = 16) */
+    uint32_t streams;         /* HIP streams used for launches, <= 32 (0 = 4) */
+    uint32_t key_mode;        /* hcc_key_mode for every request */
+    uint32_t key_bits;        /* 1..64 (0 = 32) */
+    uint32_t plain;           /* 1 = one request at a time through encode / sort / trace */
+    hcc_batch_opts batch;     /* engine options */
+} hcc_server_opts;
+
+typedef struct hcc_server_stats {
+    uint64_t launches, completed, queued, running, used_bytes;
+} hcc_server_counters;
+
+enum { HCC_REQ_QUEUED = 0, HCC_REQ_RUNNING = 1, HCC_REQ_DONE = 2, HCC_REQ_CANCELLED = 3, HCC_REQ_FAILED = 4 };
+
+hcc_status hcc_server_create(const hcc_server_opts* opts, hcc_server* out);
+/* Queue a request; HCC_ERR_BUDGET if it alone needs more than the whole budget. */
+hcc_status hcc_server_submit(hcc_server server, const hcc_batch_desc* request, uint64_t* id);
+/* State of a request (HCC_REQ_*) and, once done, its latency from submission in microseconds. */
+hcc_status hcc_server_poll(hcc_server server, uint64_t id, uint32_t* state, double* latency_us);
+/* Cancel a request that has not been admitted yet (HCC_ERR_INVALID once it has). */
+hcc_status hcc_server_cancel(hcc_server server, uint64_t id);
+/* Block until every submitted request is done or cancelled. */
+hcc_status hcc_server_drain(hcc_server server);
+hcc_status hcc_server_stats(hcc_server server, hcc_server_counters* out);
+/* Cancels queued requests, waits for admitted ones, releases the server. */
+void hcc_server_destroy(hcc_server server);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char* hcc_last_error(void);
 const char* hcc_version(void);

@@ -252,3 +252,141 @@ def trace_stats(bvh: BVH, rays: torch.Tensor, perm=None, closest: bool = True, s
 def hits_prim(hits: torch.Tensor) -> torch.Tensor:
     """The prim-id column of closest-hit results as int32 (0xFFFFFFFF shows as -1)."""
     return hits[:, 1].contiguous().view(torch.int32)
+
+
+# ------------------------------------------------------------------------------ batched engine
+
+class BatchDesc(C.Structure):
+    _fields_ = [("bvh", C.c_void_p), ("cut", C.c_void_p), ("d_rays", C.c_void_p), ("n", C.c_uint32),
+                ("mode", C.c_uint32), ("d_hits", C.c_void_p), ("d_occluded", C.c_void_p)]
+
+
+class BatchOpts(C.Structure):
+    """hcc_batch_opts: chunk (rays per trace item), refill, waves (0 = default)."""
+    _fields_ = [("chunk", C.c_uint32), ("refill", C.c_uint32), ("waves", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+lib.hcc_batch_workspace.argtypes = [C.c_void_p, C.c_uint32, C.c_int, C.c_uint32, C.POINTER(C.c_size_t)]
+lib.hcc_batch_workspace.restype = C.c_int
+lib.hcc_batch_run.argtypes = [C.c_void_p, C.c_uint32, C.c_int, C.c_uint32, C.c_void_p, C.c_void_p, C.c_size_t,
+                              C.c_void_p]
+lib.hcc_batch_run.restype = C.c_int
+
+
+class Batch:
+    """One ray batch for the engine: scene (BVH + cut), rays, trace mode and output tensor."""
+
+    def __init__(self, bvh: BVH, rays: torch.Tensor, closest: bool = True, cut: Cut | None = None, out=None):
+        _check_rays(rays)
+        self.bvh, self.cut, self.rays, self.closest = bvh, cut, rays, closest
+        n = rays.shape[0]
+        if out is None:
+            out = (torch.empty((n, 4), dtype=torch.float32, device=rays.device) if closest
+                   else torch.empty(n, dtype=torch.uint8, device=rays.device))
+        self.out = out
+
+    def desc(self) -> BatchDesc:
+        n = self.rays.shape[0]
+        return BatchDesc(self.bvh.handle.value, self.cut.handle.value if self.cut is not None else None,
+                         self.rays.data_ptr() if n else None, n, CLOSEST if self.closest else ANY,
+                         self.out.data_ptr() if (self.closest and n) else None,
+                         self.out.data_ptr() if (not self.closest and n) else None)
+
+
+def _descs(batches):
+    arr = (BatchDesc * len(batches))(*[b.desc() for b in batches])
+    return arr
+
+
+def batch_workspace_bytes(batches, mode: int, key_bits: int) -> int:
+    arr = _descs(batches)
+    b = C.c_size_t()
+    _check(lib.hcc_batch_workspace(C.cast(arr, C.c_void_p), len(batches), mode, key_bits, C.byref(b)))
+    return b.value
+
+
+def batch_run(batches, mode: int, key_bits: int = 32, opts: BatchOpts | None = None, ws=None, stream=None):
+    """Run every batch (encode + sort + trace, or trace only for KEY_NONE) in one persistent
+    launch.  Results land in each Batch's ``out``.  Returns the workspace tensor (reusable)."""
+    arr = _descs(batches)
+    need = batch_workspace_bytes(batches, mode, key_bits)
+    dev = batches[0].rays.device
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    _check(lib.hcc_batch_run(C.cast(arr, C.c_void_p), len(batches), mode, key_bits,
+                             C.byref(opts) if opts is not None else None, C.c_void_p(ws.data_ptr()), ws.numel(),
+                             _stream(stream)))
+    return ws
+
+
+# ------------------------------------------------------------------------------ request server
+
+class ServerOpts(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("max_inflight", C.c_uint32), ("max_group", C.c_uint32),
+                ("streams", C.c_uint32), ("key_mode", C.c_uint32), ("key_bits", C.c_uint32), ("plain", C.c_uint32),
+                ("batch", BatchOpts)]
+
+
+class ServerCounters(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("completed", C.c_uint64), ("queued", C.c_uint64),
+                ("running", C.c_uint64), ("used_bytes", C.c_uint64)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, 4
+
+lib.hcc_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(C.c_void_p)]
+lib.hcc_server_submit.argtypes = [C.c_void_p, C.POINTER(BatchDesc), C.POINTER(C.c_uint64)]
+lib.hcc_server_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint32), C.POINTER(C.c_double)]
+lib.hcc_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
+lib.hcc_server_drain.argtypes = [C.c_void_p]
+lib.hcc_server_stats.argtypes = [C.c_void_p, C.POINTER(ServerCounters)]
+for _f in (lib.hcc_server_create, lib.hcc_server_submit, lib.hcc_server_poll, lib.hcc_server_cancel,
+           lib.hcc_server_drain, lib.hcc_server_stats):
+    _f.restype = C.c_int
+lib.hcc_server_destroy.argtypes = [C.c_void_p]
+lib.hcc_server_destroy.restype = None
+
+
+class Server:
+    """Continuous-batching request server (native worker thread in libhcc)."""
+
+    def __init__(self, key_mode: int = KEY_HCC, key_bits: int = 32, budget_bytes: int = 64 << 30,
+                 max_inflight: int = 64, max_group: int = 16, streams: int = 4, plain: bool = False,
+                 batch: BatchOpts | None = None):
+        o = ServerOpts(budget_bytes, max_inflight, max_group, streams, key_mode, key_bits, 1 if plain else 0,
+                       batch if batch is not None else BatchOpts())
+        h = C.c_void_p()
+        _check(lib.hcc_server_create(C.byref(o), C.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, batch: Batch) -> int:
+        d = batch.desc()
+        rid = C.c_uint64()
+        _check(lib.hcc_server_submit(self._h, C.byref(d), C.byref(rid)))
+        self._keep[rid.value] = batch          # buffers must outlive the request
+        return rid.value
+
+    def poll(self, rid: int):
+        st, lat = C.c_uint32(), C.c_double()
+        _check(lib.hcc_server_poll(self._h, rid, C.byref(st), C.byref(lat)))
+        return st.value, lat.value
+
+    def cancel(self, rid: int):
+        _check(lib.hcc_server_cancel(self._h, rid))
+
+    def drain(self):
+        _check(lib.hcc_server_drain(self._h))
+
+    def counters(self) -> dict:
+        c = ServerCounters()
+        _check(lib.hcc_server_stats(self._h, C.byref(c)))
+        return {name: int(getattr(c, name)) for name, _ in c._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value and lib is not None:
+            lib.hcc_server_destroy(self._h)
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        self.close()

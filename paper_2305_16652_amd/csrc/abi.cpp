@@ -27,6 +27,9 @@ hcc_status trace_stats(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* 
                        hcc_hit* hits, uint8_t* occ, uint32_t* cn, uint32_t* ct, uint32_t* wn, uint32_t* wt,
                        hipStream_t s);
 hcc_status fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+hcc_status batch_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, size_t* bytes);
+hcc_status batch_run(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, const hcc_batch_opts& o,
+                     void* d_ws, size_t ws_bytes, hipStream_t stream);
 
 namespace {
 thread_local std::string g_error;
@@ -295,6 +298,52 @@ __attribute__((visibility("default"))) hcc_status hcc_trace_stats(hcc_bvh bvh, c
     if (st != HCC_OK) return st;
     return trace_stats(bvh, d_rays, d_perm, n, mode == HCC_TRACE_CLOSEST, d_hits, d_occluded, d_nodes, d_tris,
                        d_wave_nodes, d_wave_tris, S(stream));
+}
+
+}  // extern "C"
+
+static hcc_status check_batches(const hcc_batch_desc* d, uint32_t nb, hcc_key_mode mode, uint32_t key_bits) {
+    if (!d || nb == 0) return fail(HCC_ERR_INVALID, "hcc_batch: empty batch list");
+    if (mode != HCC_KEY_NONE && mode != HCC_KEY_HCC && mode != HCC_KEY_TWOPOINT)
+        return fail(HCC_ERR_INVALID, "hcc_batch: bad key mode");
+    if (key_bits < 1 || key_bits > 64) return fail(HCC_ERR_INVALID, "hcc_batch: key_bits must be in [1, 64]");
+    for (uint32_t b = 0; b < nb; ++b) {
+        const hcc_batch_desc& x = d[b];
+        const std::string at = " (batch " + std::to_string(b) + ")";
+        if (!valid_bvh(x.bvh)) return fail(HCC_ERR_INVALID, "hcc_batch: invalid bvh" + at);
+        if (mode == HCC_KEY_HCC && (!valid_cut(x.cut) || x.cut->bvh != x.bvh))
+            return fail(HCC_ERR_INVALID, "hcc_batch: HCC needs a cut of the batch's bvh" + at);
+        if (x.n >= (1u << 30)) return fail(HCC_ERR_INVALID, "hcc_batch: n must be below 2^30" + at);
+        if (x.mode != HCC_TRACE_CLOSEST && x.mode != HCC_TRACE_ANY) return fail(HCC_ERR_INVALID, "hcc_batch: bad trace mode" + at);
+        if (x.n > 0 && !x.d_rays) return fail(HCC_ERR_INVALID, "hcc_batch: null rays" + at);
+        if (x.n > 0 && x.mode == HCC_TRACE_CLOSEST && !x.d_hits) return fail(HCC_ERR_INVALID, "hcc_batch: null hits" + at);
+        if (x.n > 0 && x.mode == HCC_TRACE_ANY && !x.d_occluded) return fail(HCC_ERR_INVALID, "hcc_batch: null occluded" + at);
+    }
+    return HCC_OK;
+}
+
+extern "C" {
+
+__attribute__((visibility("default"))) hcc_status hcc_batch_workspace(const hcc_batch_desc* batches, uint32_t nb,
+                                                                      hcc_key_mode mode, uint32_t key_bits,
+                                                                      size_t* bytes) {
+    if (!bytes) return fail(HCC_ERR_INVALID, "hcc_batch_workspace: null bytes");
+    hcc_status st = check_batches(batches, nb, mode, key_bits);
+    if (st != HCC_OK) return st;
+    return batch_workspace(batches, nb, mode, key_bits, bytes);
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_batch_run(const hcc_batch_desc* batches, uint32_t nb,
+                                                                hcc_key_mode mode, uint32_t key_bits,
+                                                                const hcc_batch_opts* opts, void* d_ws,
+                                                                size_t ws_bytes, hcc_stream stream) {
+    hcc_status st = check_batches(batches, nb, mode, key_bits);
+    if (st != HCC_OK) return st;
+    if (!d_ws || ((uintptr_t)d_ws & 255u)) return fail(HCC_ERR_INVALID, "hcc_batch_run: workspace must be 256-byte aligned");
+    hcc_batch_opts o{};
+    if (opts) o = *opts;
+    if (o.reserved != 0) return fail(HCC_ERR_INVALID, "hcc_batch_run: opts.reserved must be 0");
+    return batch_run(batches, nb, mode, key_bits, o, d_ws, ws_bytes, S(stream));
 }
 
 }  // extern "C"

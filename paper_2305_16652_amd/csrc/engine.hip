@@ -1,0 +1,583 @@
+// Batched engine: many ray batches of different sizes over several resident scenes in ONE
+// persistent launch (encode -> per-batch radix sort -> trace), for gfx950.
+//
+// The launch works through a queue of items in batch-major order; for every batch:
+//   E   tiles of 1024 rays: sorting keys (HCC of the batch's scene, or TwoPoint) and the
+//       batch's digit histograms for every sort pass (wavefront-aggregated atomics);
+//   S_p for each 8-bit pass p, tiles of 1024 keys: stable ranking with wavefront ballots,
+//       decoupled look-back over the batch's earlier tiles, scatter to the pass's output;
+//   T   chunks of rays traced through the batch's final permutation with lane refill and
+//       batched leaf tests (as the persistent trace kernel).
+// A wavefront takes the next item from a global counter.  Before an item of phase q it waits
+// until every item of phase q-1 of the same batch has signalled completion; look-back waits
+// only on earlier tiles of the same pass.  Everything waited on sits earlier in the queue and
+// is therefore already held by a running wavefront that waits only on still earlier items, so
+// the launch always drains.  Completion is signalled with a release fence + counter increment
+// and observed with an agent-scope load + acquire fence.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "hcc_internal.h"
+
+namespace hcc {
+
+struct EngScene {
+    const Node* nodes;
+    const Tri* tris;
+    const CutBox* cut;
+    uint32_t n_int;
+    uint32_t m;            // cut boxes encoded (min(c_eff, key_bits)); 0 for TwoPoint / NoSort
+    float lo[3], hi[3];    // scene box (TwoPoint)
+};
+
+struct EngBatch {
+    const float4* rays;
+    float4* hits;
+    uint8_t* occ;
+    void* keys_a;
+    void* keys_b;
+    uint32_t* vals_a;
+    uint32_t* vals_b;
+    uint32_t* hist;        // passes x 256
+    uint32_t* lookback;    // passes x tiles x 256
+    uint32_t* done;        // passes + 1 completion counters
+    uint32_t scene, n, closest, tiles, trace_items, item0, items, pad;
+};
+
+namespace {
+
+constexpr uint32_t kTile = 1024;      // keys per encode / sort tile (64 lanes x 16)
+constexpr uint32_t kPerLane = 16;
+constexpr uint32_t kRadix = 256;
+constexpr uint32_t kFlagAgg = 1u << 30, kFlagIncl = 2u << 30, kCountMask = (1u << 30) - 1u;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint64_t below_mask() {
+    const uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64u - lane));
+}
+
+__device__ __forceinline__ uint64_t same_digit(uint32_t d, uint32_t nbits, bool alive) {
+    uint64_t m = __ballot(alive);
+    for (uint32_t b = 0; b < nbits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t& total) {
+    const uint32_t lane = __lane_id();
+    uint32_t incl = x;
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - x;
+}
+
+// Every wait is bounded: after about a second of spinning the wave gives up, records the
+// fault in 'err' and carries on, so a broken dependency yields wrong results, never a hang.
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+__device__ __forceinline__ void wait_count(const uint32_t* p, uint32_t target, uint32_t* err) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins == kSpinLimit) {
+            if (__lane_id() == 0) atomicOr(err, 1u);
+            break;
+        }
+    }
+    __threadfence();
+}
+
+__device__ __forceinline__ void signal(uint32_t* p) {
+    __threadfence();
+    if (__lane_id() == 0) atomicAdd(p, 1u);
+}
+
+template <typename K>
+__device__ K hcc_key(const CutBox* s_cut, uint32_t m, uint32_t key_bits, float4 a, float4 b) {
+    const float ix = 1.0f / b.x, iy = 1.0f / b.y, iz = 1.0f / b.z;
+    K key = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        const CutBox c = s_cut[i];
+        float tn;
+        const bool hit = slab(a.x, a.y, a.z, ix, iy, iz, a.w, b.w, c.lo.x, c.lo.y, c.lo.z, c.hi.x, c.hi.y, c.hi.z, tn);
+        key |= (K)hit << (key_bits - 1 - i);
+    }
+    return key;
+}
+
+template <typename K>
+__device__ K twopoint_key(const EngScene& sc, uint32_t key_bits, float4 a, float4 b) {
+    const float lo[3] = {sc.lo[0], sc.lo[1], sc.lo[2]};
+    const float ext[3] = {sc.hi[0] - sc.lo[0], sc.hi[1] - sc.lo[1], sc.hi[2] - sc.lo[2]};
+    const float L = fmaxf(fmaxf(ext[0], ext[1]), ext[2]);
+    const float len = sqrtf((b.x * b.x + b.y * b.y) + b.z * b.z);
+    const float dist = fminf(0.25f * L, b.w * len);
+    const float dir[3] = {b.x, b.y, b.z}, org[3] = {a.x, a.y, a.z};
+    float p[6];
+    for (int k = 0; k < 3; ++k) {
+        p[k] = org[k];
+        p[3 + k] = org[k] + (dir[k] / len) * dist;
+    }
+    uint32_t bits[6], q[6];
+    for (uint32_t d = 0; d < 6; ++d) bits[d] = key_bits / 6 + (d < key_bits % 6 ? 1u : 0u);
+    for (int d = 0; d < 6; ++d) {
+        const int ax = d % 3;
+        float u = ext[ax] > 0.0f ? (p[d] - lo[ax]) / ext[ax] : 0.0f;
+        u = fminf(fmaxf(u, 0.0f), 1.0f);
+        const uint32_t qi = (uint32_t)floorf(u * (float)(1u << bits[d]));
+        const uint32_t qmax = (1u << bits[d]) - 1u;
+        q[d] = qi > qmax ? qmax : qi;
+    }
+    K key = 0;
+    for (uint32_t level = 0; level < bits[0]; ++level)
+        for (int d = 0; d < 6; ++d)
+            if (level < bits[d]) key = (key << 1) | (K)((q[d] >> (bits[d] - 1 - level)) & 1u);
+    return key;
+}
+
+// ---- E: keys of one tile + histogram of every pass
+template <typename K>
+__device__ void encode_tile(const EngScene& sc, const EngBatch& bt, uint32_t tile, uint32_t mode, uint32_t key_bits,
+                            uint32_t passes, CutBox* s_cut) {
+    const uint32_t lane = __lane_id();
+    if (mode == HCC_KEY_HCC) {
+        for (uint32_t i = lane; i < sc.m; i += 64) s_cut[i] = sc.cut[i];
+        __syncthreads();
+    }
+    const uint64_t lt = below_mask();
+    K* keys = (K*)bt.keys_a;
+    for (uint32_t i = 0; i < kPerLane; ++i) {
+        const uint32_t idx = tile * kTile + i * 64 + lane;
+        const bool valid = idx < bt.n;
+        K key = 0;
+        if (valid) {
+            const float4 a = bt.rays[2 * (size_t)idx], b = bt.rays[2 * (size_t)idx + 1];
+            key = mode == HCC_KEY_HCC ? hcc_key<K>(s_cut, sc.m, key_bits, a, b) : twopoint_key<K>(sc, key_bits, a, b);
+            keys[idx] = key;
+        }
+        for (uint32_t p = 0; p < passes; ++p) {
+            const uint32_t nb = min(8u, key_bits - 8u * p);
+            const uint32_t d = (uint32_t)(key >> (8u * p)) & ((1u << nb) - 1u);
+            const uint64_t m = same_digit(d, nb, valid);
+            if (valid && (m & lt) == 0) atomicAdd(&bt.hist[p * kRadix + d], (uint32_t)__popcll(m));
+        }
+    }
+    __syncthreads();
+}
+
+// ---- S_p: one tile of one pass
+template <typename K>
+__device__ void scatter_tile(const EngBatch& bt, uint32_t tile, uint32_t p, uint32_t key_bits, uint32_t* s_whist,
+                             uint32_t* s_gbase, uint32_t* err) {
+    const uint32_t lane = __lane_id();
+    const K* kin = (const K*)((p & 1) ? bt.keys_b : bt.keys_a);
+    K* kout = (K*)((p & 1) ? bt.keys_a : bt.keys_b);
+    const uint32_t* vin = (p & 1) ? bt.vals_b : bt.vals_a;
+    uint32_t* vout = (p & 1) ? bt.vals_a : bt.vals_b;
+    const uint32_t shift = 8u * p, nbits = min(8u, key_bits - 8u * p), mask = (1u << nbits) - 1u;
+    for (uint32_t j = 0; j < 4; ++j) s_whist[lane * 4 + j] = 0;
+    __syncthreads();
+    const uint64_t lt = below_mask();
+    K k[kPerLane];
+    uint32_t v[kPerLane], r[kPerLane];
+#pragma unroll
+    for (uint32_t i = 0; i < kPerLane; ++i) {
+        const uint32_t idx = tile * kTile + i * 64 + lane;
+        const bool valid = idx < bt.n;
+        k[i] = valid ? kin[idx] : K(0);
+        v[i] = p == 0 ? idx : (valid ? vin[idx] : 0u);
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < kPerLane; ++i) {
+        const bool valid = tile * kTile + i * 64 + lane < bt.n;
+        const uint32_t d = (uint32_t)(k[i] >> shift) & mask;
+        const uint64_t m = same_digit(d, nbits, valid);
+        const uint32_t below = (uint32_t)__popcll(m & lt);
+        const uint32_t prev = valid ? s_whist[d] : 0u;
+        r[i] = prev + below;
+        if (valid && below == 0) s_whist[d] = prev + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    // lane owns digits 4 lane .. 4 lane + 3
+    uint32_t cnt[4], excl[4];
+    uint32_t* lb = bt.lookback + ((size_t)p * bt.tiles + tile) * kRadix;
+    for (uint32_t j = 0; j < 4; ++j) {
+        cnt[j] = s_whist[lane * 4 + j];
+        excl[j] = 0;
+        __hip_atomic_store(lb + lane * 4 + j, (tile == 0 ? kFlagIncl : kFlagAgg) | cnt[j], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tile > 0) {
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t d = lane * 4 + j;
+            int64_t t = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            while (true) {
+                const uint32_t x = __hip_atomic_load(bt.lookback + ((size_t)p * bt.tiles + t) * kRadix + d,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t f = x & ~kCountMask;
+                if (f == 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins == kSpinLimit) {
+                        atomicOr(err, 2u);
+                        break;
+                    }
+                    continue;
+                }
+                excl[j] += x & kCountMask;
+                if (f == kFlagIncl) break;
+                --t;
+            }
+            __hip_atomic_store(lb + d, kFlagIncl | (excl[j] + cnt[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // global start of each digit: exclusive scan of the pass histogram + earlier tiles
+    uint32_t h[4], hs = 0, total;
+    for (uint32_t j = 0; j < 4; ++j) {
+        h[j] = bt.hist[p * kRadix + lane * 4 + j];
+        hs += h[j];
+    }
+    uint32_t base = wave_excl_scan(hs, total);
+    for (uint32_t j = 0; j < 4; ++j) {
+        s_gbase[lane * 4 + j] = base + excl[j];
+        base += h[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t i = 0; i < kPerLane; ++i) {
+        if (tile * kTile + i * 64 + lane < bt.n) {
+            const uint32_t d = (uint32_t)(k[i] >> shift) & mask;
+            const uint32_t pos = s_gbase[d] + r[i];
+            if (pos < bt.n) {   // always true unless a dependency failed (then 'err' is set)
+                kout[pos] = k[i];
+                vout[pos] = v[i];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// ---- T: trace rays [begin, end) of the batch's order with lane refill and batched leaves
+__device__ void trace_range(const EngScene& sc, const EngBatch& bt, const uint32_t* perm, uint32_t begin,
+                            uint32_t end, uint32_t refill) {
+    const bool closest = bt.closest != 0;
+    const uint64_t below = below_mask();
+    uint32_t stk[kStackDepth];
+    uint32_t next = begin;
+    bool has = false;
+    uint32_t rid = 0, node = kNone, sp = 0, best_prim = kMissPrim, pend0 = kNone, pend1 = kNone, pend2 = kNone;
+    float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0, tmin = 0, tmax = 0;
+    float best_t = 0, best_u = 0, best_v = 0;
+    bool found = false;
+    const uint32_t n_int = sc.n_int;
+    auto test_tri = [&](uint32_t slot) {
+        const Tri tr = sc.tris[slot];
+        const uint32_t prim = __float_as_uint(tr.r.y);
+        float t, u, v;
+        if (tri_test(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v)) {
+            if (!closest) {
+                found = true;
+            } else if (t < best_t || (t == best_t && prim < best_prim)) {
+                best_t = t; best_u = u; best_v = v; best_prim = prim;
+                found = true;
+            }
+        }
+    };
+    while (true) {
+        const uint64_t idle = __ballot(!has);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (nidle >= refill || nidle == 64) {
+            if (next < end) {
+                const uint32_t k = next + (uint32_t)__popcll(idle & below);
+                if (!has && k < end) {
+                    rid = perm ? perm[k] : k;
+                    if (rid < bt.n) {
+                        const float4 ra = bt.rays[2 * (size_t)rid], rb = bt.rays[2 * (size_t)rid + 1];
+                        ox = ra.x; oy = ra.y; oz = ra.z; tmin = ra.w;
+                        dx = rb.x; dy = rb.y; dz = rb.z; tmax = rb.w;
+                        ix = 1.0f / dx; iy = 1.0f / dy; iz = 1.0f / dz;
+                        best_t = tmax; best_u = 0.0f; best_v = 0.0f; best_prim = kMissPrim;
+                        found = false;
+                        sp = 0;
+                        pend0 = pend1 = pend2 = kNone;
+                        node = 0;
+                        if (n_int == 0) {          // single-triangle scene: the root is leaf 0
+                            node = kNone;
+                            pend0 = 0;
+                        }
+                        has = true;
+                    }
+                }
+                next = min(next + nidle, end);
+            } else if (nidle == 64) {
+                break;
+            }
+        }
+        if (has && node != kNone && pend1 == kNone) {
+            const Node nd = sc.nodes[node];
+            const float lim = closest ? best_t : tmax;
+            float tn0, tn1;
+            bool h0 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, tn0);
+            bool h1 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, tn1);
+            const uint32_t c0 = nd.d.x, c1 = nd.d.y;
+            const bool leaf0 = h0 && c0 >= n_int, leaf1 = h1 && c1 >= n_int;
+            if (leaf0 || leaf1) {
+                const uint32_t a = leaf0 ? c0 - n_int : c1 - n_int;
+                const uint32_t b = (leaf0 && leaf1) ? c1 - n_int : kNone;
+                if (pend0 == kNone) { pend0 = a; pend1 = b; } else { pend1 = a; pend2 = b; }
+            }
+            h0 = h0 && !leaf0;
+            h1 = h1 && !leaf1;
+            if (h0 && h1) {
+                const bool near1 = tn1 < tn0;
+                stk[sp++] = near1 ? c0 : c1;
+                node = near1 ? c1 : c0;
+            } else if (h0) {
+                node = c0;
+            } else if (h1) {
+                node = c1;
+            } else if (sp == 0) {
+                node = kNone;
+            } else {
+                node = stk[--sp];
+            }
+        }
+        const bool can_step = has && node != kNone && pend1 == kNone;
+        const uint64_t busy = __ballot(has);
+        const uint64_t waiting = __ballot(has && pend0 != kNone && !can_step);
+        const uint64_t stepping = __ballot(can_step);
+        if (waiting != 0 && (2 * __popcll(waiting) >= __popcll(busy) || stepping == 0)) {
+            if (has && pend0 != kNone) {
+                test_tri(pend0);
+                if (pend1 != kNone && (closest || !found)) test_tri(pend1);
+                if (pend2 != kNone && (closest || !found)) test_tri(pend2);
+                pend0 = pend1 = pend2 = kNone;
+                if (!closest && found) node = kNone;
+            }
+        }
+        if (has && node == kNone && pend0 == kNone) {
+            if (closest)
+                bt.hits[rid] = make_float4(found ? best_t : INFINITY, __uint_as_float(found ? best_prim : kMissPrim),
+                                           found ? best_u : 0.0f, found ? best_v : 0.0f);
+            else
+                bt.occ[rid] = found ? 1 : 0;
+            has = false;
+        }
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(64) void k_engine(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
+                                               uint32_t nb, uint32_t total_items, uint32_t* queue, uint32_t mode,
+                                               uint32_t key_bits, uint32_t passes, uint32_t chunk, uint32_t refill) {
+    __shared__ CutBox s_cut[64];
+    __shared__ uint32_t s_whist[kRadix];
+    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_item;
+    while (true) {
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= total_items) break;
+        // batch owning this item (item0 ascending)
+        uint32_t lo = 0, hi = nb - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (batches[mid].item0 <= item) lo = mid; else hi = mid - 1;
+        }
+        const EngBatch& bt = batches[lo];
+        const EngScene& sc = scenes[bt.scene];
+        const uint32_t j = item - bt.item0;
+        if (mode == HCC_KEY_NONE) {
+            trace_range(sc, bt, nullptr, j * chunk, min(bt.n, (j + 1) * chunk), refill);
+            continue;
+        }
+        const uint32_t tiles = bt.tiles;
+        if (j < tiles) {
+            encode_tile<K>(sc, bt, j, mode, key_bits, passes, s_cut);
+            signal(bt.done);
+        } else if (j < tiles * (1 + passes)) {
+            const uint32_t p = (j - tiles) / tiles, tile = (j - tiles) % tiles;
+            wait_count(bt.done + p, tiles, queue + 1);
+            scatter_tile<K>(bt, tile, p, key_bits, s_whist, s_gbase, queue + 1);
+            signal(bt.done + p + 1);
+        } else {
+            const uint32_t c = j - tiles * (1 + passes);
+            wait_count(bt.done + passes, tiles, queue + 1);
+            const uint32_t* perm = ((passes - 1) & 1) ? bt.vals_a : bt.vals_b;
+            trace_range(sc, bt, perm, c * chunk, min(bt.n, (c + 1) * chunk), refill);
+        }
+    }
+}
+
+__global__ void k_zero(uint32_t* p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+    size_t tables, scenes_off, batches_off, zero_off, zero_bytes, total;
+    std::vector<size_t> keys_a, keys_b, vals_a, vals_b, hist, lookback, done;
+    uint32_t total_items = 0;
+};
+
+}  // namespace
+
+// Workspace layout for a batch list (the caller allocates it once, e.g. for the largest set).
+static Plan plan_batches(const hcc_batch_desc* d, uint32_t nb, uint32_t n_scenes, uint32_t mode, uint32_t key_bits,
+                         uint32_t chunk) {
+    Plan P;
+    const size_t ks = key_bits <= 32 ? 4 : 8;
+    const uint32_t passes = mode == HCC_KEY_NONE ? 0 : (key_bits + 7) / 8;
+    size_t off = 0;
+    P.scenes_off = off; off += al(sizeof(EngScene) * n_scenes);
+    P.batches_off = off; off += al(sizeof(EngBatch) * nb);
+    P.tables = off;
+    // zeroed region: queue counter, histograms, look-back, completion counters
+    P.zero_off = off;
+    off += 256;   // queue counter
+    P.hist.resize(nb); P.lookback.resize(nb); P.done.resize(nb);
+    for (uint32_t b = 0; b < nb; ++b) {
+        const size_t tiles = (d[b].n + kTile - 1) / kTile;
+        P.hist[b] = off; off += al((size_t)passes * kRadix * 4);
+        P.lookback[b] = off; off += al((size_t)passes * tiles * kRadix * 4);
+        P.done[b] = off; off += al((passes + 1) * 4);
+    }
+    P.zero_bytes = off - P.zero_off;
+    P.keys_a.resize(nb); P.keys_b.resize(nb); P.vals_a.resize(nb); P.vals_b.resize(nb);
+    for (uint32_t b = 0; b < nb; ++b) {
+        const size_t n = d[b].n;
+        if (mode == HCC_KEY_NONE) continue;
+        P.keys_a[b] = off; off += al(n * ks);
+        P.keys_b[b] = off; off += al(n * ks);
+        P.vals_a[b] = off; off += al(n * 4);
+        P.vals_b[b] = off; off += al(n * 4);
+    }
+    P.total = off;
+    (void)chunk;
+    return P;
+}
+
+hcc_status batch_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, size_t* bytes) {
+    *bytes = plan_batches(d, nb, nb, mode, key_bits, 0).total;
+    return HCC_OK;
+}
+
+// Host size of the descriptor tables a launch copies to the device.
+size_t batch_table_bytes(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits) {
+    return plan_batches(d, nb, nb, mode, key_bits, 0).tables;
+}
+
+// Launch a batch list.  With 'pinned' (page-locked host memory of at least
+// batch_table_bytes, kept alive by the caller until the stream has passed this launch) the
+// descriptor copy is asynchronous; without it a private buffer is used and the copy waited for.
+hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
+                        const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, hipStream_t stream, void* pinned,
+                        size_t pinned_bytes) {
+    const uint32_t chunk = std::max<uint32_t>(64u, o.chunk ? o.chunk : 256u);
+    const uint32_t refill = std::min<uint32_t>(64u, std::max<uint32_t>(1u, o.refill ? o.refill : 32u));
+    const uint32_t waves = o.waves ? o.waves : 8192u;
+    // scenes: distinct (bvh, cut) pairs
+    std::vector<const hcc_bvh_s*> sb;
+    std::vector<const hcc_cut_s*> sc;
+    std::vector<uint32_t> scene_of(nb);
+    for (uint32_t b = 0; b < nb; ++b) {
+        uint32_t s = 0;
+        while (s < sb.size() && !(sb[s] == d[b].bvh && sc[s] == d[b].cut)) ++s;
+        if (s == sb.size()) {
+            sb.push_back(d[b].bvh);
+            sc.push_back(d[b].cut);
+        }
+        scene_of[b] = s;
+    }
+    const Plan P = plan_batches(d, nb, (uint32_t)sb.size(), mode, key_bits, chunk);
+    if (ws_bytes < P.total) return fail(HCC_ERR_INVALID, "hcc_batch_run: workspace too small (see hcc_batch_workspace)");
+    const uint32_t passes = mode == HCC_KEY_NONE ? 0 : (key_bits + 7) / 8;
+    char* ws = (char*)d_ws;
+    std::vector<EngScene> hs(sb.size());
+    for (size_t s = 0; s < sb.size(); ++s) {
+        hs[s].nodes = sb[s]->nodes;
+        hs[s].tris = sb[s]->tris;
+        hs[s].n_int = sb[s]->n_int;
+        hs[s].cut = sc[s] ? sc[s]->d_boxes : nullptr;
+        hs[s].m = (mode == HCC_KEY_HCC && sc[s]) ? std::min(sc[s]->c_eff, key_bits) : 0;
+        for (int a = 0; a < 3; ++a) {
+            hs[s].lo[a] = sb[s]->scene_box[a];
+            hs[s].hi[a] = sb[s]->scene_box[3 + a];
+        }
+    }
+    std::vector<EngBatch> hb(nb);
+    uint32_t item = 0;
+    for (uint32_t b = 0; b < nb; ++b) {
+        EngBatch& e = hb[b];
+        e.rays = (const float4*)d[b].d_rays;
+        e.hits = (float4*)d[b].d_hits;
+        e.occ = d[b].d_occluded;
+        e.scene = scene_of[b];
+        e.n = d[b].n;
+        e.closest = d[b].mode == HCC_TRACE_CLOSEST ? 1u : 0u;
+        e.tiles = (d[b].n + kTile - 1) / kTile;
+        e.trace_items = (d[b].n + chunk - 1) / chunk;
+        e.hist = (uint32_t*)(ws + P.hist[b]);
+        e.lookback = (uint32_t*)(ws + P.lookback[b]);
+        e.done = (uint32_t*)(ws + P.done[b]);
+        if (mode != HCC_KEY_NONE) {
+            e.keys_a = ws + P.keys_a[b];
+            e.keys_b = ws + P.keys_b[b];
+            e.vals_a = (uint32_t*)(ws + P.vals_a[b]);
+            e.vals_b = (uint32_t*)(ws + P.vals_b[b]);
+        } else {
+            e.keys_a = e.keys_b = nullptr;
+            e.vals_a = e.vals_b = nullptr;
+        }
+        e.item0 = item;
+        e.items = mode == HCC_KEY_NONE ? e.trace_items : e.tiles * (1 + passes) + e.trace_items;
+        item += e.items;
+    }
+    // the descriptor tables travel with the launch on the stream; the host copies are kept
+    // alive until the stream has consumed them
+    static thread_local std::vector<char> staging;
+    char* host = (char*)pinned;
+    if (pinned) {
+        if (pinned_bytes < P.tables) return fail(HCC_ERR_INVALID, "batch launch: staging buffer too small");
+    } else {
+        staging.assign(P.tables, 0);
+        host = staging.data();
+    }
+    std::memcpy(host + P.scenes_off, hs.data(), sizeof(EngScene) * hs.size());
+    std::memcpy(host + P.batches_off, hb.data(), sizeof(EngBatch) * hb.size());
+    HCC_HIP(hipMemcpyAsync(ws, host, P.tables, hipMemcpyHostToDevice, stream));
+    if (!pinned) HCC_HIP(hipStreamSynchronize(stream));
+    const size_t zw = P.zero_bytes / 4;
+    k_zero<<<(unsigned)std::min<size_t>(2048, (zw + 255) / 256), 256, 0, stream>>>((uint32_t*)(ws + P.zero_off), zw);
+    const EngScene* dsc = (const EngScene*)(ws + P.scenes_off);
+    const EngBatch* dbt = (const EngBatch*)(ws + P.batches_off);
+    uint32_t* queue = (uint32_t*)(ws + P.zero_off);
+    const unsigned grid = std::max(1u, std::min(waves, item));
+    if (key_bits <= 32)
+        k_engine<uint32_t><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes, chunk, refill);
+    else
+        k_engine<uint64_t><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes, chunk, refill);
+    HCC_HIP(hipGetLastError());
+    return HCC_OK;
+}
+
+}  // namespace hcc
+
+namespace hcc {
+hcc_status batch_run(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, const hcc_batch_opts& o,
+                     void* d_ws, size_t ws_bytes, hipStream_t stream) {
+    return batch_launch(d, nb, mode, key_bits, o, d_ws, ws_bytes, stream, nullptr, 0);
+}
+}  // namespace hcc

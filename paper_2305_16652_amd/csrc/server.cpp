@@ -1,0 +1,366 @@
+// Request loop with continuous batching (the serving layer around the batched engine).
+//
+// A worker thread owns the device side.  Each pass it
+//   1. retires finished launch groups (their completion events have fired): marks their
+//      requests done, returns their budget and slots, frees their workspace;
+//   2. admits queued requests in arrival order while the HBM ray-state budget and the slot
+//      limit allow (a request never jumps ahead of an earlier one);
+//   3. launches the newly admitted requests together as one engine batch on the next of its
+//      streams, with an event behind it.
+// Requests that arrive while others run are therefore admitted as soon as budget and slots
+// free up, and their work overlaps on the device with the groups still in flight.  In the
+// plain mode (the baseline) one request at a time goes through hcc_encode, hcc_sort and
+// hcc_trace and the next starts only after it finished.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "hcc_internal.h"
+
+namespace hcc {
+size_t batch_table_bytes(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits);
+hcc_status batch_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, size_t* bytes);
+hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
+                        const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, hipStream_t stream, void* pinned,
+                        size_t pinned_bytes);
+hcc_status encode_hcc(const hcc_cut_s* cut, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
+                      hipStream_t stream);
+hcc_status encode_twopoint(const hcc_bvh_s* bvh, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n,
+                           void* d_keys, hipStream_t stream);
+hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
+                 hcc_hit* hits, uint8_t* occ, const hcc_trace_opts& o, hipStream_t s);
+}  // namespace hcc
+
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+enum : uint32_t { kQueued = 0, kRunning = 1, kDone = 2, kCancelled = 3, kFailed = 4 };
+
+struct Req {
+    hcc_batch_desc desc{};
+    size_t bytes = 0;
+    uint32_t state = kQueued;
+    Clock::time_point t_submit, t_start, t_done;
+};
+
+struct Group {
+    std::vector<uint64_t> ids;
+    hipEvent_t done = nullptr;
+    void* ws = nullptr;
+    void* pinned = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+};
+
+}  // namespace
+
+struct hcc_server_s {
+    hcc_server_opts opts{};
+    int device = 0;
+    std::vector<hipStream_t> streams;
+    size_t next_stream = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<uint64_t> pending;
+    std::unordered_map<uint64_t, Req> reqs;
+    std::vector<Group> inflight;
+    uint64_t next_id = 1;
+    size_t used_bytes = 0;
+    uint32_t running = 0;
+    uint64_t launches = 0, completed = 0;
+    std::string error;
+    bool stop = false;
+    std::thread worker;
+    uint64_t magic = 0x6863637372760001ull;
+};
+
+namespace {
+
+bool valid_server(const hcc_server_s* s) { return s && s->magic == 0x6863637372760001ull; }
+
+// Device bytes a request holds while admitted: its rays and results, plus the engine's
+// per-ray workspace (keys, permutation, ping-pong buffers) of a batch of that size.
+size_t request_bytes(const hcc_batch_desc& d, uint32_t mode, uint32_t key_bits) {
+    size_t ws = 0;
+    hcc::batch_workspace(&d, 1, mode, key_bits, &ws);
+    return (size_t)d.n * (sizeof(hcc_ray) + (d.mode == HCC_TRACE_CLOSEST ? sizeof(hcc_hit) : 1)) + ws;
+}
+
+void finish_group(hcc_server_s* s, Group& g, bool ok) {
+    const auto now = Clock::now();
+    for (uint64_t id : g.ids) {
+        Req& r = s->reqs[id];
+        r.state = ok ? kDone : kFailed;
+        r.t_done = now;
+        s->used_bytes -= r.bytes;
+        s->running -= 1;
+        s->completed += 1;
+    }
+    if (g.ws) (void)hipFreeAsync(g.ws, g.stream);
+    if (g.pinned) (void)hipHostFree(g.pinned);
+    if (g.done) (void)hipEventDestroy(g.done);
+    g = Group();
+}
+
+// Plain mode: one request through encode / sort / trace, waited for before the next.
+bool run_plain(hcc_server_s* s, const hcc_batch_desc& d) {
+    hipStream_t st = s->streams[0];
+    const uint32_t mode = s->opts.key_mode, kb = s->opts.key_bits;
+    uint32_t* perm = nullptr;
+    void* keys = nullptr;
+    void* ws = nullptr;
+    bool ok = true;
+    if (mode != HCC_KEY_NONE && d.n > 0) {
+        const size_t ks = kb <= 32 ? 4 : 8;
+        const size_t wsb = hcc::sort_workspace_bytes(d.n, kb);
+        ok = hipMallocAsync(&keys, (size_t)d.n * ks, st) == hipSuccess &&
+             hipMallocAsync((void**)&perm, (size_t)d.n * 4, st) == hipSuccess &&
+             hipMallocAsync(&ws, wsb, st) == hipSuccess;
+        if (ok) ok = (mode == HCC_KEY_HCC ? hcc::encode_hcc(d.cut, kb, d.d_rays, d.n, keys, st)
+                                          : hcc::encode_twopoint(d.bvh, kb, d.d_rays, d.n, keys, st)) == HCC_OK;
+        if (ok) ok = hcc::radix_sort(keys, kb, d.n, perm, nullptr, nullptr, ws, wsb, st) == HCC_OK;
+    }
+    hcc_trace_opts to{};
+    to.persistent = 1;
+    to.refill = 32;
+    to.chunk = 64;
+    to.flags = 1;
+    if (ok && d.n > 0)
+        ok = hcc::trace(d.bvh, d.d_rays, perm, d.n, d.mode == HCC_TRACE_CLOSEST, d.d_hits, d.d_occluded, to, st) ==
+             HCC_OK;
+    if (keys) (void)hipFreeAsync(keys, st);
+    if (perm) (void)hipFreeAsync(perm, st);
+    if (ws) (void)hipFreeAsync(ws, st);
+    return hipStreamSynchronize(st) == hipSuccess && ok;
+}
+
+void worker_loop(hcc_server_s* s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        // 1. retire finished groups
+        for (auto& g : s->inflight) {
+            if (!g.done) continue;
+            const hipError_t q = hipEventQuery(g.done);
+            if (q == hipSuccess) finish_group(s, g, true);
+            else if (q != hipErrorNotReady) finish_group(s, g, false);
+        }
+        s->inflight.erase(std::remove_if(s->inflight.begin(), s->inflight.end(),
+                                         [](const Group& g) { return g.ids.empty(); }),
+                          s->inflight.end());
+        if (s->stop && s->pending.empty() && s->inflight.empty()) break;
+
+        // 2. admission in arrival order
+        std::vector<uint64_t> admit;
+        while (!s->pending.empty()) {
+            const uint64_t id = s->pending.front();
+            Req& r = s->reqs[id];
+            if (r.state == kCancelled) {
+                s->pending.pop_front();
+                continue;
+            }
+            const bool slots = s->running + admit.size() < s->opts.max_inflight;
+            const bool budget = s->used_bytes + r.bytes <= s->opts.budget_bytes;
+            const bool room = admit.size() < (s->opts.plain ? 1u : s->opts.max_group);
+            if (!(slots && budget && room)) break;
+            s->pending.pop_front();
+            s->used_bytes += r.bytes;
+            r.state = kRunning;
+            r.t_start = Clock::now();
+            admit.push_back(id);
+        }
+        s->running += (uint32_t)admit.size();
+
+        // 3. launch
+        if (!admit.empty()) {
+            if (s->opts.plain) {
+                const hcc_batch_desc d = s->reqs[admit[0]].desc;
+                lk.unlock();
+                const bool ok = run_plain(s, d);
+                lk.lock();
+                Group g;
+                g.ids = admit;
+                finish_group(s, g, ok);
+                s->launches += 1;
+                continue;
+            }
+            std::vector<hcc_batch_desc> ds;
+            for (uint64_t id : admit) ds.push_back(s->reqs[id].desc);
+            Group g;
+            g.ids = admit;
+            g.stream = s->streams[s->next_stream++ % s->streams.size()];
+            bool ok = hcc::batch_workspace(ds.data(), (uint32_t)ds.size(), s->opts.key_mode, s->opts.key_bits,
+                                           &g.bytes) == HCC_OK;
+            const size_t tb = hcc::batch_table_bytes(ds.data(), (uint32_t)ds.size(), s->opts.key_mode,
+                                                     s->opts.key_bits);
+            ok = ok && hipMallocAsync(&g.ws, g.bytes, g.stream) == hipSuccess;
+            ok = ok && hipHostMalloc(&g.pinned, tb, hipHostMallocDefault) == hipSuccess;
+            ok = ok && hcc::batch_launch(ds.data(), (uint32_t)ds.size(), s->opts.key_mode, s->opts.key_bits,
+                                         s->opts.batch, g.ws, g.bytes, g.stream, g.pinned, tb) == HCC_OK;
+            ok = ok && hipEventCreateWithFlags(&g.done, hipEventDisableTiming) == hipSuccess;
+            ok = ok && hipEventRecord(g.done, g.stream) == hipSuccess;
+            s->launches += 1;
+            if (!ok) {
+                s->error = "launch failed: " + std::string(hcc_last_error());
+                if (g.done) {
+                    (void)hipStreamSynchronize(g.stream);
+                }
+                finish_group(s, g, false);
+            } else {
+                s->inflight.push_back(std::move(g));
+            }
+            continue;
+        }
+        // 4. wait: poll quickly while work is on the device, sleep otherwise
+        if (!s->inflight.empty()) {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(10));
+            lk.lock();
+        } else {
+            s->cv.wait_for(lk, std::chrono::milliseconds(2));
+        }
+    }
+}
+
+}  // namespace
+
+using namespace hcc;
+
+extern "C" {
+
+__attribute__((visibility("default"))) hcc_status hcc_server_create(const hcc_server_opts* opts, hcc_server* out) {
+    if (!out) return fail(HCC_ERR_INVALID, "hcc_server_create: null out");
+    hcc_server_opts o{};
+    if (opts) o = *opts;
+    if (o.budget_bytes == 0) o.budget_bytes = 64ull << 30;
+    if (o.max_inflight == 0) o.max_inflight = 64;
+    if (o.max_group == 0) o.max_group = 16;
+    if (o.streams == 0) o.streams = 4;
+    if (o.key_bits == 0) o.key_bits = 32;
+    if (o.key_bits > 64 || o.streams > 32 || o.key_mode > HCC_KEY_TWOPOINT)
+        return fail(HCC_ERR_INVALID, "hcc_server_create: bad options");
+    hcc_server_s* s = new hcc_server_s();
+    s->opts = o;
+    (void)hipGetDevice(&s->device);
+    for (uint32_t i = 0; i < o.streams; ++i) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (auto x : s->streams) (void)hipStreamDestroy(x);
+            delete s;
+            return fail(HCC_ERR_DEVICE, "hcc_server_create: stream creation failed");
+        }
+        s->streams.push_back(st);
+    }
+    s->worker = std::thread(worker_loop, s);
+    *out = s;
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_server_submit(hcc_server s, const hcc_batch_desc* req,
+                                                                    uint64_t* id) {
+    if (!valid_server(s) || !req || !id) return fail(HCC_ERR_INVALID, "hcc_server_submit: invalid argument");
+    const hcc_batch_desc& d = *req;
+    if (!d.bvh || d.bvh->magic != 0x6863636276680001ull) return fail(HCC_ERR_INVALID, "hcc_server_submit: invalid bvh");
+    if (s->opts.key_mode == HCC_KEY_HCC && (!d.cut || d.cut->magic != 0x6863636375740001ull || d.cut->bvh != d.bvh))
+        return fail(HCC_ERR_INVALID, "hcc_server_submit: HCC needs a cut of the request's bvh");
+    if (d.n >= (1u << 30) || (d.n > 0 && !d.d_rays) || (d.mode != HCC_TRACE_CLOSEST && d.mode != HCC_TRACE_ANY) ||
+        (d.n > 0 && d.mode == HCC_TRACE_CLOSEST && !d.d_hits) || (d.n > 0 && d.mode == HCC_TRACE_ANY && !d.d_occluded))
+        return fail(HCC_ERR_INVALID, "hcc_server_submit: bad request");
+    const size_t bytes = request_bytes(d, s->opts.key_mode, s->opts.key_bits);
+    if (bytes > s->opts.budget_bytes)
+        return fail(HCC_ERR_BUDGET, "hcc_server_submit: request needs " + std::to_string(bytes) +
+                                        " bytes, more than the whole budget");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return fail(HCC_ERR_INVALID, "hcc_server_submit: server is shutting down");
+    const uint64_t rid = s->next_id++;
+    Req& r = s->reqs[rid];
+    r.desc = d;
+    r.bytes = bytes;
+    r.t_submit = Clock::now();
+    s->pending.push_back(rid);
+    s->cv.notify_one();
+    *id = rid;
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_server_poll(hcc_server s, uint64_t id, uint32_t* state,
+                                                                  double* latency_us) {
+    if (!valid_server(s) || !state) return fail(HCC_ERR_INVALID, "hcc_server_poll: invalid argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(HCC_ERR_INVALID, "hcc_server_poll: unknown request");
+    *state = it->second.state;
+    if (latency_us) {
+        *latency_us = (it->second.state == kDone || it->second.state == kFailed)
+                          ? std::chrono::duration<double, std::micro>(it->second.t_done - it->second.t_submit).count()
+                          : -1.0;
+    }
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_server_cancel(hcc_server s, uint64_t id) {
+    if (!valid_server(s)) return fail(HCC_ERR_INVALID, "hcc_server_cancel: invalid server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(HCC_ERR_INVALID, "hcc_server_cancel: unknown request");
+    if (it->second.state != kQueued) return fail(HCC_ERR_INVALID, "hcc_server_cancel: request already admitted");
+    it->second.state = kCancelled;
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_server_drain(hcc_server s) {
+    if (!valid_server(s)) return fail(HCC_ERR_INVALID, "hcc_server_drain: invalid server");
+    while (true) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            bool busy = !s->inflight.empty() || s->running > 0;
+            for (uint64_t id : s->pending)
+                if (s->reqs[id].state == kQueued) busy = true;
+            if (!busy) break;
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_server_stats(hcc_server s, hcc_server_counters* out) {
+    if (!valid_server(s) || !out) return fail(HCC_ERR_INVALID, "hcc_server_stats: invalid argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    out->launches = s->launches;
+    out->completed = s->completed;
+    out->queued = 0;
+    for (uint64_t id : s->pending)
+        if (s->reqs[id].state == kQueued) out->queued += 1;
+    out->running = s->running;
+    out->used_bytes = s->used_bytes;
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) void hcc_server_destroy(hcc_server s) {
+    if (!valid_server(s)) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (uint64_t id : s->pending) {
+            Req& r = s->reqs[id];
+            if (r.state == kQueued) r.state = kCancelled;
+        }
+        s->pending.clear();
+        s->cv.notify_one();
+    }
+    s->worker.join();
+    for (auto st : s->streams) (void)hipStreamDestroy(st);
+    s->magic = 0;
+    delete s;
+}
+
+}  // extern "C"

@@ -17,26 +17,6 @@ namespace {
 
 constexpr int kShortDepth = 16;
 
-// Moller-Trumbore, double sided, float32, fixed operation order, no FMA contraction.
-__device__ __forceinline__ bool tri_test(const Tri& tr, float ox, float oy, float oz, float dx, float dy, float dz,
-                                         float tmin, float tmax, float& t, float& u, float& v) {
-    const float v0x = tr.p.x, v0y = tr.p.y, v0z = tr.p.z;
-    const float e1x = tr.p.w, e1y = tr.q.x, e1z = tr.q.y;
-    const float e2x = tr.q.z, e2y = tr.q.w, e2z = tr.r.x;
-    const float px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
-    const float det = (e1x * px + e1y * py) + e1z * pz;
-    if (det == 0.0f) return false;
-    const float inv = 1.0f / det;
-    const float sx = ox - v0x, sy = oy - v0y, sz = oz - v0z;
-    u = ((sx * px + sy * py) + sz * pz) * inv;
-    if (!(u >= 0.0f && u <= 1.0f)) return false;
-    const float qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
-    v = ((dx * qx + dy * qy) + dz * qz) * inv;
-    if (!(v >= 0.0f && u + v <= 1.0f)) return false;
-    t = ((e2x * qx + e2y * qy) + e2z * qz) * inv;
-    return t > tmin && t < tmax;
-}
-
 template <int kStack, int kBlock>
 struct Stack;
 

@@ -1,0 +1,110 @@
+"""Batched engine (one persistent launch over many uneven batches and several resident scenes)
+against the oracle and against the plain per-batch path."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from parity_utils import assert_any, assert_closest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    assert torch.cuda.is_available()
+    import paper_2305_16652_amd as H
+    return H
+
+
+@pytest.fixture(scope="module")
+def scenes(H):
+    """Three resident scenes with oracle BVHs and ray pools (diffuse + shadow) from oracle hits."""
+    out = []
+    specs = [W.tiny_scene(), W.cluster_scene(20_000, seed=9), W.tiny_scene(seed=3, n_random=1)]
+    for si, spec in enumerate(specs):
+        ob = O.build_bvh(spec.tris)
+        prim = W.pinhole_rays(spec, 96, 96, 1)
+        ph = O.trace(ob, prim)
+        dif, _ = W.spawn_diffuse(prim, ph.t, ph.prim, spec.tris, seed=11 + si, bounce=0)
+        shd, _ = W.spawn_shadow(prim, ph.t, ph.prim, spec.tris, spec.lights)
+        bvh = H.build_bvh(torch.from_numpy(spec.tris).cuda())
+        out.append(dict(spec=spec, ob=ob, bvh=bvh, cut32=H.select_cut(bvh, 32), cut64=H.select_cut(bvh, 64),
+                        diffuse=dif, shadow=shd))
+    return out
+
+
+SIZES = [0, 1, 63, 64, 1023, 1024, 1025, 4097, 9000]
+
+
+def _batches(H, scenes, seed, key_cut):
+    rng = np.random.default_rng(seed)
+    res = []
+    for i, n in enumerate(SIZES + list(rng.integers(1, 9000, 6))):
+        s = scenes[int(rng.integers(0, len(scenes)))]
+        closest = bool(rng.random() < 0.7)
+        pool = s["diffuse"] if closest else s["shadow"]
+        start = int(rng.integers(0, max(1, pool.shape[0] - n))) if pool.shape[0] > n else 0
+        sel = np.resize(pool[start:], (n, 8)) if n else np.zeros((0, 8), np.float32)
+        rays = torch.from_numpy(np.ascontiguousarray(sel, np.float32)).cuda()
+        res.append((s, H.Batch(s["bvh"], rays, closest, cut=s[key_cut] if key_cut else None), sel))
+    return res
+
+
+@pytest.mark.parametrize("mode,key_bits,cut", [("hcc", 32, "cut32"), ("hcc", 64, "cut64"), ("hcc", 16, "cut32"),
+                                               ("twopoint", 32, None), ("twopoint", 64, None), ("none", 32, None)])
+@pytest.mark.parametrize("opts", [None, (64, 1, 7, 0), (1000, 64, 3, 0)])
+def test_engine_matches_oracle_and_plain_path(H, scenes, mode, key_bits, cut, opts):
+    key_mode = {"hcc": H.KEY_HCC, "twopoint": H.KEY_TWOPOINT, "none": 0}[mode]
+    items = _batches(H, scenes, seed=key_bits + (opts[0] if opts else 0), key_cut=cut if mode == "hcc" else None)
+    o = H.BatchOpts(*opts) if opts else None
+    H.batch_run([b for _, b, _ in items], key_mode, key_bits, opts=o)
+    torch.cuda.synchronize()
+    for s, b, rays in items:
+        n = rays.shape[0]
+        if n == 0:
+            continue
+        got = b.out.cpu().numpy()
+        # the plain path, batch by batch
+        perm = None
+        if mode != "none":
+            keys = H.encode(s["bvh"], b.cut, key_mode, key_bits, b.rays)
+            perm = H.sort(keys, key_bits)
+        ref_gpu = H.trace(s["bvh"], b.rays, perm, closest=b.closest).cpu().numpy()
+        if b.closest:
+            assert np.array_equal(got.view(np.uint32), ref_gpu.view(np.uint32))
+            assert_closest(got, O.trace(s["ob"], rays), rays, s["spec"].tris)
+        else:
+            assert np.array_equal(got, ref_gpu)
+            assert_any(got, O.trace(s["ob"], rays, closest=False))
+
+
+def test_engine_reuses_workspace_and_is_deterministic(H, scenes):
+    items = _batches(H, scenes, seed=5, key_cut="cut32")
+    batches = [b for _, b, _ in items]
+    ws = H.batch_run(batches, H.KEY_HCC, 32)
+    first = [b.out.clone() for b in batches]
+    for b in batches:
+        b.out.zero_()
+    H.batch_run(batches, H.KEY_HCC, 32, ws=ws)
+    torch.cuda.synchronize()
+    for a, b in zip(first, batches):
+        # compare bits: a miss stores prim 0xFFFFFFFF, a NaN pattern in the float view
+        if a.dtype == torch.float32:
+            assert torch.equal(a.view(torch.int32), b.out.view(torch.int32))
+        else:
+            assert torch.equal(a, b.out)
+
+
+def test_engine_invalid_arguments(H, scenes):
+    s = scenes[0]
+    rays = torch.from_numpy(s["diffuse"][:10]).cuda()
+    with pytest.raises(H.HCCError):
+        H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_HCC, 32)          # HCC without a cut
+    with pytest.raises(H.HCCError):
+        H.batch_run([H.Batch(s["bvh"], rays, True, cut=scenes[1]["cut32"])], H.KEY_HCC, 32)   # cut of another BVH
+    with pytest.raises(H.HCCError):
+        H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 0)
+    with pytest.raises(H.HCCError):
+        H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 1))

@@ -351,6 +351,27 @@ def spawn_shadow(rays: np.ndarray, t: np.ndarray, prim: np.ndarray, tris: np.nda
     return out.reshape(-1, 8), parent
 
 
+def batch_plan(n_batches: int = 64, seed: int = 21, lo: int = 1024, hi: int = 2_097_152, n_scenes: int = 4,
+               frac_closest: float = 0.7) -> list[dict]:
+    """Uneven ray batches: size floor(exp(U[ln lo, ln hi])), scene uniform, closest hit with
+    probability frac_closest (diffuse rays) else any hit (shadow rays), and an offset into the
+    scene's ray pool."""
+    k = np.arange(n_batches, dtype=np.uint64)
+    size = np.floor(np.exp(np.log(lo) + (np.log(hi) - np.log(lo)) * uniform01(seed, 60, k))).astype(np.int64)
+    scene = (u64_hash(seed, 61, k) % np.uint64(n_scenes)).astype(np.int64)
+    closest = uniform01(seed, 62, k) < frac_closest
+    offset = u64_hash(seed, 63, k)
+    return [dict(n=int(size[i]), scene=int(scene[i]), closest=bool(closest[i]), offset=int(offset[i] % (1 << 40)))
+            for i in range(n_batches)]
+
+
+def take_rays(pool: np.ndarray, n: int, offset: int) -> np.ndarray:
+    """n consecutive rays of a pool starting at offset (wrapping around)."""
+    m = pool.shape[0]
+    idx = (np.arange(n, dtype=np.int64) + (offset % m)) % m
+    return np.ascontiguousarray(pool[idx])
+
+
 # Named workload sizes (scene generator, camera resolution, samples, bounces).
 TINY = dict(scene=tiny_scene, width=64, height=64, spp=1, bounces=1, cut=64, key_bits=32)
 FRAME = dict(scene=frame_scene, width=1920, height=1080, spp=8, bounces=3, cut=(256, 4096), key_bits=32)
