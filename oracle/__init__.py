@@ -249,3 +249,69 @@ def anc(keys, perm=None, width: int = 32) -> float:
 
 def cut_boxes(bvh: OracleBVH, ids) -> np.ndarray:
     return np.ascontiguousarray(bvh.boxes[np.asarray(ids, np.int64)])
+
+
+def _load_extra():
+    lib = _load()
+    if getattr(lib, "_extra", False):
+        return lib
+    P, u32 = C.c_void_p, C.c_uint32
+    lib.oracle_select_mlhcc_cut.argtypes = [u32, P, P, u32, u32, P, P]
+    lib.oracle_select_mlhcc_cut.restype = C.c_int
+    lib.oracle_encode_mlhcc.argtypes = [P, u32, P, u32, P, u32, u32, P]
+    lib.oracle_grid_boxes.argtypes = [P, u32, u32, u32, P]
+    lib._extra = True
+    return lib
+
+
+def select_mlhcc_cut(bvh: OracleBVH, had_values, top: int, low: int):
+    """Two-level cut (Section 4.3, Alg. 3): (top_ids (T',), low_ids (T', low))."""
+    had_values = np.ascontiguousarray(had_values, np.float64)
+    top_ids = np.empty(top + 2, np.uint32)
+    low_ids = np.empty((top + 2) * low, np.uint32)
+    m = _load_extra().oracle_select_mlhcc_cut(bvh.n, _ptr(bvh.child), _ptr(had_values), top, low, _ptr(top_ids),
+                                              _ptr(low_ids))
+    if m < 0:
+        raise ValueError(f"oracle_select_mlhcc_cut failed ({m})")
+    return top_ids[:m].copy(), low_ids[: m * low].reshape(m, low).copy()
+
+
+def encode_mlhcc(rays, top_boxes, low_boxes, low: int, key_bits: int, threads: int = 1) -> np.ndarray:
+    rays = _f32(rays, 8)
+    tb = _f32(top_boxes, 6)
+    lb = _f32(low_boxes, 6)
+    n = rays.shape[0]
+    out = np.empty(n, np.uint64)
+    lib = _load_extra()
+
+    def run(rng):
+        k0, k1 = rng
+        lib.oracle_encode_mlhcc(_ptr(rays[k0:k1]), k1 - k0, _ptr(tb), tb.shape[0], _ptr(lb), low, key_bits,
+                                _ptr(out[k0:k1]))
+
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        list(ex.map(run, _chunks(n, threads)))
+    return out.astype(_key_dtype(key_bits))
+
+
+def grid_dims(key_bits: int):
+    """Most cubic gx >= gy >= gz with gx*gy*gz == key_bits (the regular-grid control)."""
+    best = None
+    for gz in range(1, key_bits + 1):
+        for gy in range(gz, key_bits + 1):
+            if key_bits % (gy * gz):
+                continue
+            gx = key_bits // (gy * gz)
+            if gx < gy:
+                continue
+            score = gx - gz
+            if best is None or score < best[0]:
+                best = (score, gx, gy, gz)
+    return best[1:]
+
+
+def grid_boxes(scene_lohi, gx: int, gy: int, gz: int) -> np.ndarray:
+    lohi = np.ascontiguousarray(scene_lohi, np.float32).reshape(6)
+    out = np.empty((gx * gy * gz, 6), np.float32)
+    _load_extra().oracle_grid_boxes(_ptr(lohi), gx, gy, gz, _ptr(out))
+    return out

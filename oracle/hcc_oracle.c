@@ -267,6 +267,124 @@ int oracle_select_cut(uint32_t n, const uint32_t* child, const double* had, uint
     return (int)m;
 }
 
+/* ------------------------------------------------------------------ MLHCC cut, Alg. 3
+ * Two-level cut of the multi-level hierarchy cut code (Section 4.3).  Top level: the
+ * priority-queue search of Alg. 2 (largest HAD first, ties by smaller id) that keeps only
+ * nodes with a sufficient subtree.  Reading of "sufficient": at least L leaves, so that a
+ * low-level cut of exactly L nodes exists below the node.  When a node is removed from the
+ * queue, its children with at least L leaves are pushed and the others are discarded; a node
+ * none of whose children qualifies cannot be refined and joins the top-level list (as a leaf
+ * does in Alg. 2, the target shrinking by one).  Top-level cut = that list + the queue,
+ * ordered by HAD descending.  Low level: for each top node, the Alg. 2 cut of size L of its
+ * subtree, ordered by HAD descending.  Returns the number of top nodes T' (<= top), or -1
+ * on bad input, -2 on allocation failure.  low_ids: top x low entries (row i for top node i). */
+static uint32_t count_leaves(uint32_t n, const uint32_t* child, uint32_t id, uint32_t* cache) {
+    if (n == 1 || id >= n - 1) return 1;
+    if (cache[id]) return cache[id];
+    uint32_t c = count_leaves(n, child, child[2 * (size_t)id], cache) +
+                 count_leaves(n, child, child[2 * (size_t)id + 1], cache);
+    cache[id] = c;
+    return c;
+}
+
+/* Alg. 2 below an arbitrary node (the same search as oracle_select_cut, rooted at 'root'). */
+static int subtree_cut(uint32_t n, const uint32_t* child, const double* had, uint32_t root, uint32_t cut_size,
+                       uint32_t* cut_ids) {
+    uint32_t* q = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)cut_size + 2));
+    uint32_t* list = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)cut_size + 2));
+    if (!q || !list) { free(q); free(list); return -2; }
+    size_t qn = 0, ln = 0;
+    int64_t max_q = cut_size;
+    q[qn++] = root;
+    while ((int64_t)qn < max_q) {
+        if (qn == 0) break;
+        size_t best = 0;
+        for (size_t k = 1; k < qn; ++k)
+            if (before(had[q[k]], q[k], had[q[best]], q[best])) best = k;
+        uint32_t node = q[best];
+        q[best] = q[qn - 1];
+        --qn;
+        if (n == 1 || node >= n - 1) { list[ln++] = node; max_q -= 1; }
+        else { q[qn++] = child[2 * (size_t)node]; q[qn++] = child[2 * (size_t)node + 1]; }
+    }
+    size_t m = 0;
+    for (size_t k = 0; k < ln; ++k) cut_ids[m++] = list[k];
+    for (size_t k = 0; k < qn; ++k) cut_ids[m++] = q[k];
+    for (size_t i = 1; i < m; ++i) {
+        uint32_t x = cut_ids[i];
+        size_t j = i;
+        while (j > 0 && before(had[x], x, had[cut_ids[j - 1]], cut_ids[j - 1])) { cut_ids[j] = cut_ids[j - 1]; --j; }
+        cut_ids[j] = x;
+    }
+    free(q); free(list);
+    return (int)m;
+}
+
+int oracle_select_mlhcc_cut(uint32_t n, const uint32_t* child, const double* had, uint32_t top, uint32_t low,
+                            uint32_t* top_ids, uint32_t* low_ids) {
+    if (n == 0 || top == 0 || low == 0) return -1;
+    uint32_t* cache = (uint32_t*)calloc(n, sizeof(uint32_t));
+    uint32_t* q = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)top + 2));
+    uint32_t* list = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)top + 2));
+    if (!cache || !q || !list) { free(cache); free(q); free(list); return -2; }
+    size_t qn = 0, ln = 0;
+    int64_t max_q = top;
+    if (count_leaves(n, child, 0, cache) >= low) q[qn++] = 0;
+    while ((int64_t)qn < max_q && qn > 0) {
+        size_t best = 0;
+        for (size_t k = 1; k < qn; ++k)
+            if (before(had[q[k]], q[k], had[q[best]], q[best])) best = k;
+        uint32_t node = q[best];
+        q[best] = q[qn - 1];
+        --qn;
+        int pushed = 0;
+        if (!(n == 1 || node >= n - 1)) {
+            for (int c = 0; c < 2; ++c) {
+                uint32_t ch = child[2 * (size_t)node + c];
+                if (count_leaves(n, child, ch, cache) >= low) { q[qn++] = ch; ++pushed; }
+            }
+        }
+        if (!pushed) { list[ln++] = node; max_q -= 1; }
+    }
+    size_t m = 0;
+    for (size_t k = 0; k < ln; ++k) top_ids[m++] = list[k];
+    for (size_t k = 0; k < qn; ++k) top_ids[m++] = q[k];
+    for (size_t i = 1; i < m; ++i) {
+        uint32_t x = top_ids[i];
+        size_t j = i;
+        while (j > 0 && before(had[x], x, had[top_ids[j - 1]], top_ids[j - 1])) { top_ids[j] = top_ids[j - 1]; --j; }
+        top_ids[j] = x;
+    }
+    int rc = (int)m;
+    for (size_t i = 0; i < m && rc >= 0; ++i) {
+        int got = subtree_cut(n, child, had, top_ids[i], low, low_ids + (size_t)i * low);
+        if (got != (int)low) rc = got < 0 ? got : -1;
+    }
+    free(cache); free(q); free(list);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ regular grid (control)
+ * The regular-grid encoding of Section 5: the cut boxes are replaced by the cells of a uniform
+ * gx x gy x gz grid over the scene box.  Reading: cell boundaries at lo + ext * i / g computed
+ * in double and rounded to float; cells numbered x fastest, then y, then z, and cell 0 takes
+ * the most significant bit (there is no HAD to order them). */
+void oracle_grid_boxes(const float* scene_lohi, uint32_t gx, uint32_t gy, uint32_t gz, float* boxes) {
+    const uint32_t g[3] = {gx, gy, gz};
+    size_t k = 0;
+    for (uint32_t z = 0; z < gz; ++z)
+        for (uint32_t y = 0; y < gy; ++y)
+            for (uint32_t x = 0; x < gx; ++x) {
+                const uint32_t idx[3] = {x, y, z};
+                for (int a = 0; a < 3; ++a) {
+                    double lo = scene_lohi[a], ext = (double)scene_lohi[3 + a] - (double)scene_lohi[a];
+                    boxes[6 * k + a] = (float)(lo + ext * (double)idx[a] / (double)g[a]);
+                    boxes[6 * k + 3 + a] = (float)(lo + ext * (double)(idx[a] + 1) / (double)g[a]);
+                }
+                ++k;
+            }
+}
+
 /* ------------------------------------------------------------------ slab test
  * Ray against an axis-aligned box over the ray's own segment [tmin, tmax].  The
  * paper does not spell the test out; reading: IEEE division for 1/d, minNum /
@@ -309,6 +427,34 @@ void oracle_encode_hcc(const float* rays, uint32_t n, const float* cut_boxes, ui
         for (uint32_t i = 0; i < m; ++i)
             if (slab_hit(o, inv, ry[3], ry[7], cut_boxes + 6 * (size_t)i, 0))
                 key |= (uint64_t)1 << (key_bits - 1 - i);
+        keys[r] = key;
+    }
+}
+
+/* ------------------------------------------------------------------ MLHCC key (Section 4.3)
+ * The key has key_bits = top + low bits.  Bit (key_bits-1-i) records whether the ray meets
+ * top node i (top nodes in HAD order, i < t_eff <= top); the representative is the first top
+ * node met in that order; bit (low-1-j) records whether the ray meets node j of the
+ * representative's low-level cut.  A ray meeting no top node has zero low bits. */
+void oracle_encode_mlhcc(const float* rays, uint32_t n, const float* top_boxes, uint32_t t_eff,
+                         const float* low_boxes, uint32_t low, uint32_t key_bits, uint64_t* keys) {
+    for (uint32_t r = 0; r < n; ++r) {
+        const float* ry = rays + 8 * (size_t)r;
+        float o[3] = {ry[0], ry[1], ry[2]};
+        float inv[3] = {1.0f / ry[4], 1.0f / ry[5], 1.0f / ry[6]};
+        uint64_t key = 0;
+        int rep = -1;
+        for (uint32_t i = 0; i < t_eff; ++i) {
+            if (slab_hit(o, inv, ry[3], ry[7], top_boxes + 6 * (size_t)i, 0)) {
+                key |= (uint64_t)1 << (key_bits - 1 - i);
+                if (rep < 0) rep = (int)i;
+            }
+        }
+        if (rep >= 0) {
+            const float* lb = low_boxes + 6 * (size_t)rep * low;
+            for (uint32_t j = 0; j < low; ++j)
+                if (slab_hit(o, inv, ry[3], ry[7], lb + 6 * (size_t)j, 0)) key |= (uint64_t)1 << (low - 1 - j);
+        }
         keys[r] = key;
     }
 }
