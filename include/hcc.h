@@ -48,7 +48,8 @@ typedef enum {
 typedef enum {
     HCC_KEY_NONE = 0,         /* no key: rays traced in generation order ("NoSort") */
     HCC_KEY_HCC = 1,          /* hierarchy cut code (Section 4.2, Algorithm 1) */
-    HCC_KEY_TWOPOINT = 2      /* origin + estimated end point 6-D Morton code (Section 3.2) */
+    HCC_KEY_TWOPOINT = 2,     /* origin + estimated end point 6-D Morton code (Section 3.2) */
+    HCC_KEY_MLHCC = 3         /* multi-level hierarchy cut code (Section 4.3), two-level cut */
 } hcc_key_mode;
 
 typedef enum { HCC_TRACE_CLOSEST = 0, HCC_TRACE_ANY = 1 } hcc_trace_mode;
@@ -122,6 +123,33 @@ hcc_status hcc_cut_info(hcc_cut cut, uint32_t* c_eff);
 hcc_status hcc_cut_export(hcc_cut cut, uint32_t* h_ids, double* h_had, float* h_boxes);
 
 void hcc_cut_destroy(hcc_cut cut);
+
+/* hcc_select_mlhcc_cut -- two-level cut of the multi-level hierarchy cut code (Section 4.3,
+ * Algorithm 3).  Top level: the Algorithm 2 search (largest HAD first, ties by smaller id) over
+ * nodes with a sufficient subtree -- at least 'low' leaves, so that each top node can be split
+ * into 'low' low-level nodes; a removed node pushes its children with at least 'low' leaves and
+ * discards the others, and a node none of whose children qualifies joins the top level as it
+ * is.  At most 'top' top nodes (HAD descending); for each, the Algorithm 2 cut of size 'low' of
+ * its subtree (HAD descending).  1 <= top, low <= 64, top * low <= 2048.  Blocking.
+ * Encode with HCC_KEY_MLHCC and key_bits >= top nodes + low: bit (key_bits-1-i) <=> the ray
+ * meets top node i; the representative is the first top node met; bit (low-1-j) <=> the ray
+ * meets node j of the representative's low-level cut (zero when no top node is met). */
+hcc_status hcc_select_mlhcc_cut(hcc_bvh bvh, uint32_t top, uint32_t low, double lambda, hcc_stream stream,
+                                hcc_cut* out);
+
+/* hcc_grid_cut -- the regular-grid control encoding (Section 5): a "cut" whose boxes are the
+ * cells of a uniform gx x gy x gz grid over the scene box (boundaries lo + ext*i/g computed in
+ * double, rounded to float; cells numbered x fastest, then y, then z; cell 0 = most significant
+ * bit).  Encode with HCC_KEY_HCC.  1 <= gx*gy*gz <= 64.  Blocking. */
+hcc_status hcc_grid_cut(hcc_bvh bvh, uint32_t gx, uint32_t gy, uint32_t gz, hcc_stream stream, hcc_cut* out);
+
+/* Kind of a cut (0 Algorithm 2 cut, 1 two-level cut, 2 regular grid), its (top-level) size and,
+ * for a two-level cut, the low-level size.  Any out pointer may be NULL. */
+hcc_status hcc_cut_shape(hcc_cut cut, uint32_t* kind, uint32_t* top, uint32_t* low);
+
+/* Low level of a two-level cut: h_low_ids (top x low uint32 node ids, row i for top node i) and
+ * h_low_boxes (top x low x 6 float32).  Either pointer may be NULL. */
+hcc_status hcc_cut_export_low(hcc_cut cut, uint32_t* h_low_ids, float* h_low_boxes);
 
 /* ---------------------------------------------------------------------------------------
  * hcc_encode -- one sorting key per ray.

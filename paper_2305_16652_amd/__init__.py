@@ -184,6 +184,44 @@ def select_cut(bvh: BVH, cut_size: int, lam: float = 0.125, stream=None) -> Cut:
     return Cut(h.value, bvh)
 
 
+KEY_MLHCC = 3
+lib.hcc_select_mlhcc_cut.argtypes = [_H, _U32, _U32, C.c_double, _P, C.POINTER(_H)]
+lib.hcc_grid_cut.argtypes = [_H, _U32, _U32, _U32, _P, C.POINTER(_H)]
+lib.hcc_cut_shape.argtypes = [_H, C.POINTER(_U32), C.POINTER(_U32), C.POINTER(_U32)]
+lib.hcc_cut_export_low.argtypes = [_H, _P, _P]
+for _f in (lib.hcc_select_mlhcc_cut, lib.hcc_grid_cut, lib.hcc_cut_shape, lib.hcc_cut_export_low):
+    _f.restype = C.c_int
+
+
+def select_mlhcc_cut(bvh: BVH, top: int, low: int, lam: float = 0.125, stream=None) -> Cut:
+    """Two-level cut of the multi-level hierarchy cut code (encode with KEY_MLHCC)."""
+    h = _H()
+    _check(lib.hcc_select_mlhcc_cut(bvh.handle, top, low, float(lam), _stream(stream), C.byref(h)))
+    return Cut(h.value, bvh)
+
+
+def grid_cut(bvh: BVH, gx: int, gy: int, gz: int, stream=None) -> Cut:
+    """Regular-grid control encoding: grid cells in place of cut nodes (encode with KEY_HCC)."""
+    h = _H()
+    _check(lib.hcc_grid_cut(bvh.handle, gx, gy, gz, _stream(stream), C.byref(h)))
+    return Cut(h.value, bvh)
+
+
+def cut_shape(cut: Cut):
+    k, t, l = _U32(), _U32(), _U32()
+    _check(lib.hcc_cut_shape(cut.handle, C.byref(k), C.byref(t), C.byref(l)))
+    return k.value, t.value, l.value
+
+
+def cut_export_low(cut: Cut):
+    import numpy as np
+    _, t, l = cut_shape(cut)
+    ids = np.empty((t, l), np.uint32)
+    boxes = np.empty((t, l, 6), np.float32)
+    _check(lib.hcc_cut_export_low(cut.handle, ids.ctypes.data_as(_P), boxes.ctypes.data_as(_P)))
+    return ids, boxes
+
+
 def _check_rays(rays: torch.Tensor):
     if rays.dtype != torch.float32 or rays.dim() != 2 or rays.shape[1] != 8:
         raise ValueError("rays must be an (R, 8) float32 tensor")

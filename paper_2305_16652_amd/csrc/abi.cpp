@@ -19,6 +19,8 @@ void free_bvh(hcc_bvh_s* b);
 hcc_status recompute_had(hcc_bvh_s* b, double lambda, hipStream_t stream);
 hcc_status encode_hcc(const hcc_cut_s* cut, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
                       hipStream_t stream);
+hcc_status encode_mlhcc(const hcc_cut_s* cut, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
+                        hipStream_t stream);
 hcc_status encode_twopoint(const hcc_bvh_s* bvh, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n,
                            void* d_keys, hipStream_t stream);
 hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
@@ -67,7 +69,7 @@ hcc_status ensure_host_mirror(hcc_bvh_s* b, hipStream_t stream) {
 }
 
 // Algorithm 2 with a binary heap ordered by (HAD descending, id ascending).
-std::vector<uint32_t> cut_search(const hcc_bvh_s* b, uint32_t cut_size) {
+std::vector<uint32_t> cut_search(const hcc_bvh_s* b, uint32_t cut_size, uint32_t root = 0) {
     const std::vector<double>& had = b->h_had;
     auto lower = [&](uint32_t x, uint32_t y) {   // true if x has lower priority than y
         if (had[x] != had[y]) return had[x] < had[y];
@@ -76,7 +78,7 @@ std::vector<uint32_t> cut_search(const hcc_bvh_s* b, uint32_t cut_size) {
     std::priority_queue<uint32_t, std::vector<uint32_t>, decltype(lower)> q(lower);
     std::vector<uint32_t> cut;
     int64_t max_q = cut_size;
-    q.push(0);
+    q.push(root);
     while ((int64_t)q.size() < max_q && !q.empty()) {
         const uint32_t node = q.top();
         q.pop();
@@ -100,6 +102,105 @@ std::vector<uint32_t> cut_search(const hcc_bvh_s* b, uint32_t cut_size) {
 }
 
 inline hipStream_t S(hcc_stream s) { return (hipStream_t)s; }
+
+// Leaves below every node (post-order over the host mirror).
+void ensure_leaf_counts(hcc_bvh_s* b) {
+    const size_t nn = 2 * (size_t)b->n - 1;
+    if (b->h_leaves.size() == nn) return;
+    b->h_leaves.assign(nn, 1);
+    if (b->n_int == 0) return;
+    // children of internal node i have ids > i is not guaranteed, so walk an explicit stack
+    std::vector<uint32_t> order;
+    order.reserve(b->n_int);
+    std::vector<uint32_t> st{0};
+    while (!st.empty()) {
+        const uint32_t x = st.back();
+        st.pop_back();
+        order.push_back(x);
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t ch = b->h_child[2 * (size_t)x + c];
+            if (ch < b->n_int) st.push_back(ch);
+        }
+    }
+    for (size_t k = order.size(); k-- > 0;) {
+        const uint32_t x = order[k];
+        b->h_leaves[x] = b->h_leaves[b->h_child[2 * (size_t)x]] + b->h_leaves[b->h_child[2 * (size_t)x + 1]];
+    }
+}
+
+// Two-level cut (Alg. 3): a node removed from the queue pushes its children that have at least
+// 'low' leaves; if none has, the node itself joins the top-level list and the target shrinks.
+std::vector<uint32_t> mlhcc_top_search(const hcc_bvh_s* b, uint32_t top, uint32_t low) {
+    const std::vector<double>& had = b->h_had;
+    auto lower = [&](uint32_t x, uint32_t y) {
+        if (had[x] != had[y]) return had[x] < had[y];
+        return x > y;
+    };
+    std::priority_queue<uint32_t, std::vector<uint32_t>, decltype(lower)> q(lower);
+    std::vector<uint32_t> out;
+    int64_t max_q = top;
+    if (b->h_leaves[0] >= low) q.push(0);
+    while ((int64_t)q.size() < max_q && !q.empty()) {
+        const uint32_t node = q.top();
+        q.pop();
+        int pushed = 0;
+        if (node < b->n_int) {
+            for (int c = 0; c < 2; ++c) {
+                const uint32_t ch = b->h_child[2 * (size_t)node + c];
+                if (b->h_leaves[ch] >= low) {
+                    q.push(ch);
+                    ++pushed;
+                }
+            }
+        }
+        if (!pushed) {
+            out.push_back(node);
+            --max_q;
+        }
+    }
+    while (!q.empty()) {
+        out.push_back(q.top());
+        q.pop();
+    }
+    std::sort(out.begin(), out.end(), [&](uint32_t x, uint32_t y) {
+        if (had[x] != had[y]) return had[x] > had[y];
+        return x < y;
+    });
+    return out;
+}
+
+hcc_status download_boxes(const hcc_bvh_s* b, std::vector<float>& all) {
+    all.resize(6 * (2 * (size_t)b->n - 1));
+    HCC_HIP(hipMemcpy(all.data(), b->boxes, sizeof(float) * all.size(), hipMemcpyDeviceToHost));
+    return HCC_OK;
+}
+
+// Upload a cut's boxes (top/cut boxes, then low boxes) and hand out the handle.
+hcc_status finish_cut(hcc_cut_s* c, hipStream_t stream, hcc_cut* out) {
+    const size_t nb = c->boxes.size() / 6 + c->low_boxes.size() / 6;
+    std::vector<CutBox> up(std::max<size_t>(nb, 1));
+    for (size_t i = 0; i < c->boxes.size() / 6; ++i) {
+        const float* bx = &c->boxes[6 * i];
+        up[i].lo = make_float4(bx[0], bx[1], bx[2], 0.0f);
+        up[i].hi = make_float4(bx[3], bx[4], bx[5], 0.0f);
+    }
+    const size_t off = c->boxes.size() / 6;
+    for (size_t i = 0; i < c->low_boxes.size() / 6; ++i) {
+        const float* bx = &c->low_boxes[6 * i];
+        up[off + i].lo = make_float4(bx[0], bx[1], bx[2], 0.0f);
+        up[off + i].hi = make_float4(bx[3], bx[4], bx[5], 0.0f);
+    }
+    hipError_t e = hipMalloc((void**)&c->d_boxes, sizeof(CutBox) * up.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_boxes, up.data(), sizeof(CutBox) * up.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        (void)hipFree(c->d_boxes);
+        delete c;
+        return hip_fail(e, "cut upload");
+    }
+    *out = c;
+    return HCC_OK;
+}
 
 }  // namespace
 }  // namespace hcc
@@ -231,11 +332,18 @@ __attribute__((visibility("default"))) hcc_status hcc_encode(hcc_bvh bvh, hcc_cu
         case HCC_KEY_HCC:
             if (!valid_cut(cut)) return fail(HCC_ERR_INVALID, "hcc_encode: HCC needs a cut");
             if (cut->bvh != bvh) return fail(HCC_ERR_INVALID, "hcc_encode: cut belongs to another BVH");
+            if (cut->kind == 1) return fail(HCC_ERR_INVALID, "hcc_encode: a two-level cut needs HCC_KEY_MLHCC");
             return encode_hcc(cut, key_bits, d_rays, n, d_keys, S(stream));
+        case HCC_KEY_MLHCC:
+            if (!valid_cut(cut) || cut->kind != 1) return fail(HCC_ERR_INVALID, "hcc_encode: MLHCC needs a two-level cut");
+            if (cut->bvh != bvh) return fail(HCC_ERR_INVALID, "hcc_encode: cut belongs to another BVH");
+            if (key_bits < cut->low + cut->c_eff)
+                return fail(HCC_ERR_INVALID, "hcc_encode: key_bits must be at least top nodes + low nodes");
+            return encode_mlhcc(cut, key_bits, d_rays, n, d_keys, S(stream));
         case HCC_KEY_TWOPOINT:
             return encode_twopoint(bvh, key_bits, d_rays, n, d_keys, S(stream));
         default:
-            return fail(HCC_ERR_INVALID, "hcc_encode: mode must be HCC_KEY_HCC or HCC_KEY_TWOPOINT");
+            return fail(HCC_ERR_INVALID, "hcc_encode: mode must be HCC_KEY_HCC, HCC_KEY_TWOPOINT or HCC_KEY_MLHCC");
     }
 }
 
@@ -344,6 +452,88 @@ __attribute__((visibility("default"))) hcc_status hcc_batch_run(const hcc_batch_
     if (opts) o = *opts;
     if (o.reserved != 0) return fail(HCC_ERR_INVALID, "hcc_batch_run: opts.reserved must be 0");
     return batch_run(batches, nb, mode, key_bits, o, d_ws, ws_bytes, S(stream));
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_select_mlhcc_cut(hcc_bvh bvh, uint32_t top, uint32_t low,
+                                                                       double lambda, hcc_stream stream,
+                                                                       hcc_cut* out) {
+    if (!valid_bvh(bvh) || !out) return fail(HCC_ERR_INVALID, "hcc_select_mlhcc_cut: invalid handle or null out");
+    if (top == 0 || low == 0 || top > 64 || low > 64 || top * low > 2048)
+        return fail(HCC_ERR_INVALID, "hcc_select_mlhcc_cut: need 1 <= top, low <= 64 and top * low <= 2048");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda))
+        return fail(HCC_ERR_INVALID, "hcc_select_mlhcc_cut: lambda must be finite and >= 0");
+    hcc_status st;
+    if (lambda != bvh->had_lambda && (st = recompute_had(bvh, lambda, S(stream))) != HCC_OK) return st;
+    if ((st = ensure_host_mirror(bvh, S(stream))) != HCC_OK) return st;
+    ensure_leaf_counts(bvh);
+    std::vector<float> all;
+    if ((st = download_boxes(bvh, all)) != HCC_OK) return st;
+    hcc_cut_s* c = new hcc_cut_s();
+    c->bvh = bvh;
+    c->kind = 1;
+    c->low = low;
+    c->top_req = top;
+    c->ids = mlhcc_top_search(bvh, top, low);
+    c->c_eff = (uint32_t)c->ids.size();
+    for (uint32_t id : c->ids) {
+        c->had.push_back(bvh->h_had[id]);
+        c->boxes.insert(c->boxes.end(), &all[6 * (size_t)id], &all[6 * (size_t)id] + 6);
+        const std::vector<uint32_t> lo = cut_search(bvh, low, id);
+        if (lo.size() != low) {
+            delete c;
+            return fail(HCC_ERR_INVALID, "hcc_select_mlhcc_cut: internal error (short low-level cut)");
+        }
+        for (uint32_t x : lo) {
+            c->low_ids.push_back(x);
+            c->low_boxes.insert(c->low_boxes.end(), &all[6 * (size_t)x], &all[6 * (size_t)x] + 6);
+        }
+    }
+    return finish_cut(c, S(stream), out);
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_grid_cut(hcc_bvh bvh, uint32_t gx, uint32_t gy, uint32_t gz,
+                                                               hcc_stream stream, hcc_cut* out) {
+    if (!valid_bvh(bvh) || !out) return fail(HCC_ERR_INVALID, "hcc_grid_cut: invalid handle or null out");
+    if (gx == 0 || gy == 0 || gz == 0 || (uint64_t)gx * gy * gz > 64)
+        return fail(HCC_ERR_INVALID, "hcc_grid_cut: need 1 <= gx*gy*gz <= 64");
+    hcc_cut_s* c = new hcc_cut_s();
+    c->bvh = bvh;
+    c->kind = 2;
+    const uint32_t g[3] = {gx, gy, gz};
+    const float* sb = bvh->scene_box;
+    for (uint32_t z = 0; z < gz; ++z)
+        for (uint32_t y = 0; y < gy; ++y)
+            for (uint32_t x = 0; x < gx; ++x) {
+                const uint32_t idx[3] = {x, y, z};
+                float bx[6];
+                for (int a = 0; a < 3; ++a) {
+                    const double lo = sb[a], ext = (double)sb[3 + a] - (double)sb[a];
+                    bx[a] = (float)(lo + ext * (double)idx[a] / (double)g[a]);
+                    bx[3 + a] = (float)(lo + ext * (double)(idx[a] + 1) / (double)g[a]);
+                }
+                c->boxes.insert(c->boxes.end(), bx, bx + 6);
+                c->ids.push_back(0xFFFFFFFFu);
+                c->had.push_back(0.0);
+            }
+    c->c_eff = gx * gy * gz;
+    return finish_cut(c, S(stream), out);
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_cut_shape(hcc_cut cut, uint32_t* kind, uint32_t* top,
+                                                                uint32_t* low) {
+    if (!valid_cut(cut)) return fail(HCC_ERR_INVALID, "hcc_cut_shape: invalid handle");
+    if (kind) *kind = cut->kind;
+    if (top) *top = cut->c_eff;
+    if (low) *low = cut->low;
+    return HCC_OK;
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_cut_export_low(hcc_cut cut, uint32_t* h_low_ids,
+                                                                     float* h_low_boxes) {
+    if (!valid_cut(cut) || cut->kind != 1) return fail(HCC_ERR_INVALID, "hcc_cut_export_low: not a two-level cut");
+    if (h_low_ids) std::memcpy(h_low_ids, cut->low_ids.data(), sizeof(uint32_t) * cut->low_ids.size());
+    if (h_low_boxes) std::memcpy(h_low_boxes, cut->low_boxes.data(), sizeof(float) * cut->low_boxes.size());
+    return HCC_OK;
 }
 
 }  // extern "C"

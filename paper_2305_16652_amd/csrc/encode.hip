@@ -88,6 +88,48 @@ __global__ __launch_bounds__(kBlock) void k_encode_twopoint(const float4* __rest
     }
 }
 
+// MLHCC (Section 4.3): the top-level boxes and every top node's low-level boxes are staged in
+// LDS (top x low <= 2048 boxes, 64 KB).  Top bits as in HCC; the first top node met is the
+// representative, whose low-level boxes give the low bits.
+constexpr uint32_t kMaxLowBoxes = 2048;
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_encode_mlhcc(const float4* __restrict__ rays, uint32_t n,
+                                                         const CutBox* __restrict__ boxes, uint32_t t_eff,
+                                                         uint32_t low, uint32_t key_bits, K* __restrict__ keys) {
+    __shared__ CutBox s_top[kMaxCut];
+    __shared__ CutBox s_low[kMaxLowBoxes];
+    for (uint32_t i = threadIdx.x; i < t_eff; i += kBlock) s_top[i] = boxes[i];
+    for (uint32_t i = threadIdx.x; i < t_eff * low; i += kBlock) s_low[i] = boxes[t_eff + i];
+    __syncthreads();
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+        const float4 a = rays[2 * (size_t)r];
+        const float4 b = rays[2 * (size_t)r + 1];
+        const float ix = 1.0f / b.x, iy = 1.0f / b.y, iz = 1.0f / b.z;
+        K key = 0;
+        int rep = -1;
+        for (uint32_t i = 0; i < t_eff; ++i) {
+            const CutBox c = s_top[i];
+            float tn;
+            const bool hit = slab(a.x, a.y, a.z, ix, iy, iz, a.w, b.w, c.lo.x, c.lo.y, c.lo.z, c.hi.x, c.hi.y,
+                                  c.hi.z, tn);
+            key |= (K)hit << (key_bits - 1 - i);
+            if (hit && rep < 0) rep = (int)i;
+        }
+        if (rep >= 0) {
+            const CutBox* lb = s_low + (uint32_t)rep * low;
+            for (uint32_t j = 0; j < low; ++j) {
+                const CutBox c = lb[j];
+                float tn;
+                const bool hit = slab(a.x, a.y, a.z, ix, iy, iz, a.w, b.w, c.lo.x, c.lo.y, c.lo.z, c.hi.x, c.hi.y,
+                                      c.hi.z, tn);
+                key |= (K)hit << (low - 1 - j);
+            }
+        }
+        keys[r] = key;
+    }
+}
+
 inline unsigned grid_for(uint32_t n) {
     // enough blocks to fill 256 CUs several times over; a grid-stride loop covers the rest
     const uint32_t want = (n + kBlock - 1) / kBlock;
@@ -105,6 +147,20 @@ hcc_status encode_hcc(const hcc_cut_s* cut, uint32_t key_bits, const hcc_ray* d_
     else
         k_encode_hcc<uint64_t><<<grid_for(n), kBlock, 0, stream>>>((const float4*)d_rays, n, cut->d_boxes, m,
                                                                    key_bits, (uint64_t*)d_keys);
+    HCC_HIP(hipGetLastError());
+    return HCC_OK;
+}
+
+hcc_status encode_mlhcc(const hcc_cut_s* cut, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
+                        hipStream_t stream) {
+    if (key_bits <= 32)
+        k_encode_mlhcc<uint32_t><<<grid_for(n), kBlock, 0, stream>>>((const float4*)d_rays, n, cut->d_boxes,
+                                                                     cut->c_eff, cut->low, key_bits,
+                                                                     (uint32_t*)d_keys);
+    else
+        k_encode_mlhcc<uint64_t><<<grid_for(n), kBlock, 0, stream>>>((const float4*)d_rays, n, cut->d_boxes,
+                                                                     cut->c_eff, cut->low, key_bits,
+                                                                     (uint64_t*)d_keys);
     HCC_HIP(hipGetLastError());
     return HCC_OK;
 }

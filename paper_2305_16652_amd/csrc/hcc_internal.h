@@ -125,16 +125,22 @@ struct hcc_bvh_s {
     // host mirror for the cut search
     std::vector<uint32_t> h_child;
     std::vector<double> h_had;
+    std::vector<uint32_t> h_leaves; // leaves below each node (two-level cut search)
     double h_had_lambda = -1.0;
     uint64_t magic = 0x6863636276680001ull;
 };
 
 struct hcc_cut_s {
     const hcc_bvh_s* bvh = nullptr;
-    uint32_t c_eff = 0;
-    std::vector<uint32_t> ids;
+    uint32_t kind = 0;              // 0 cut (Alg. 2), 1 two-level cut (Alg. 3), 2 regular grid
+    uint32_t c_eff = 0;             // cut nodes / top-level nodes / grid cells
+    uint32_t low = 0;               // two-level cut: low-level nodes per top node
+    uint32_t top_req = 0;           // two-level cut: requested top-level size
+    std::vector<uint32_t> ids;      // c_eff (grid: 0xFFFFFFFF)
     std::vector<double> had;
     std::vector<float> boxes;       // c_eff x 6
-    hcc::CutBox* d_boxes = nullptr; // c_eff
+    std::vector<uint32_t> low_ids;  // c_eff x low
+    std::vector<float> low_boxes;   // c_eff x low x 6
+    hcc::CutBox* d_boxes = nullptr; // c_eff boxes, then (two-level) c_eff x low boxes
     uint64_t magic = 0x6863636375740001ull;
 };
