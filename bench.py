@@ -66,6 +66,13 @@ def parse():
     ap.add_argument("--no-shadow", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch engine workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server workload")
+    ap.add_argument("--no-grid", action="store_true", help="skip the frame workload's method grid")
+    ap.add_argument("--grid-reps", type=int, default=5)
+    ap.add_argument("--no-drift", action="store_true", help="skip the 10M-triangle boundary-drift workload")
+    ap.add_argument("--drift-tris", type=int, default=10_000_000)
+    ap.add_argument("--drift-spp", type=int, default=4)
+    ap.add_argument("--drift-keys", default="16,24,32,48,64")
+    ap.add_argument("--drift-reps", type=int, default=5)
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=50)
     return ap.parse_args()
@@ -252,6 +259,11 @@ def main():
     if not args.no_cpu and "hcc" in conf:
         cpu = cpu_baseline(tris_h, sec, args, hcc_hits.cpu().numpy(), conf["hcc"]["cut"], conf["hcc"]["key_bits"])
 
+    grid = None
+    if not args.no_grid and "hcc" in conf:
+        grid = run_method_grid(H, bvh, rays, conf["hcc"]["opts"], args.grid_reps)
+    del bufs
+    drift = None if args.no_drift else run_drift(H, args)
     batched = None if args.no_batched else run_batched(H, args)
     serve = None if args.no_serve else run_serving(H, args)
 
@@ -287,6 +299,8 @@ def main():
         "shadow": shadow_res,
         "build_ms": round(build_ms, 2),
         "select_cut_ms": round(cut_ms, 2),
+        "method_grid": grid,
+        "drift": drift,
         "batched": batched,
         "serve": serve,
         "roofline": roofline,
@@ -483,6 +497,139 @@ def run_batched(H, args):
     return out
 
 
+def variant_name(v) -> str:
+    m = v["mode"]
+    if m == "hcc":
+        return f"hcc C={v['C']} K={v['K']}"
+    if m == "mlhcc":
+        return f"mlhcc{v['top'] + v['low']} ({v['top']}+{v['low']})"
+    if m == "nosort":
+        return "nosort"
+    return f"{m} K={v['K']}"
+
+
+def measure_variant(H, bvh, rays, v, opts, reps=5, closest=True, stats=True):
+    """encode + sort + trace of one reordering variant: median stage times over `reps` steps
+    (after one warm-up), wavefront node/triangle fetches per ray and ANC (distinct keys per
+    group of 32 and of 64 consecutive rays in trace order)."""
+    import torch
+    R = rays.shape[0]
+    dev = rays.device
+    mode, K = v["mode"], v.get("K", 0)
+    cut = None
+    if mode == "hcc":
+        cut = H.select_cut(bvh, v["C"])
+    elif mode == "mlhcc":
+        cut = H.select_mlhcc_cut(bvh, v["top"], v["low"])
+    elif mode == "grid":
+        cut = H.grid_cut(bvh, *H.grid_dims(K))
+    kmode = {"twopoint": H.KEY_TWOPOINT, "hcc": H.KEY_HCC, "grid": H.KEY_HCC, "mlhcc": H.KEY_MLHCC}.get(mode, 0)
+    out = (torch.empty((R, 4), dtype=torch.float32, device=dev) if closest
+           else torch.empty(R, dtype=torch.uint8, device=dev))
+    keys = perm = ws = None
+    if mode != "nosort":
+        keys = torch.empty(R, dtype=torch.int32 if K <= 32 else torch.int64, device=dev)
+        perm = torch.empty(R, dtype=torch.int32, device=dev)
+        ws = torch.empty(H.sort_workspace_bytes(R, K), dtype=torch.uint8, device=dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def step(e=None):
+        if e:
+            e[0].record()
+        if mode != "nosort":
+            H.encode(bvh, cut, kmode, K, rays, out=keys)
+        if e:
+            e[1].record()
+        if mode != "nosort":
+            H.sort(keys, K, perm=perm, ws=ws)
+        if e:
+            e[2].record()
+        H.trace(bvh, rays, perm, closest=closest, out=out, opts=opts)
+        if e:
+            e[3].record()
+
+    step()
+    torch.cuda.synchronize()
+    evs = [[ev() for _ in range(4)] for _ in range(reps)]
+    for e in evs:
+        step(e)
+    torch.cuda.synchronize()
+    enc = float(np.median([e[0].elapsed_time(e[1]) for e in evs]))
+    srt = float(np.median([e[1].elapsed_time(e[2]) for e in evs]))
+    trc = float(np.median([e[2].elapsed_time(e[3]) for e in evs]))
+    tot = float(np.median([e[0].elapsed_time(e[3]) for e in evs]))
+    res = dict(method=variant_name(v), ms=round(tot, 4), encode_ms=round(enc, 4), sort_ms=round(srt, 4),
+               trace_ms=round(trc, 4), mrays_s=round(R / (tot * 1e-3) / 1e6, 1),
+               trace_only_mrays_s=round(R / (trc * 1e-3) / 1e6, 1))
+    if cut is not None:
+        res["cut_eff"] = H.cut_shape(cut)[1]
+    if stats:
+        _, _, _, wn, wt = H.trace_stats(bvh, rays, perm, closest=closest)
+        res["node_fetches_per_ray"] = round(int(wn.to(torch.int64).sum().item()) / R, 3)
+        res["tri_fetches_per_ray"] = round(int(wt.to(torch.int64).sum().item()) / R, 3)
+        if keys is not None:
+            sk = keys[perm.long()]
+            for w in (32, 64):
+                d = torch.ones(R, dtype=torch.int64, device=dev)
+                d[1:] = (sk[1:] != sk[:-1]).to(torch.int64)
+                d[::w] = 1
+                res[f"anc{w}"] = round(int(d.sum().item()) / ((R + w - 1) // w), 3)
+    return res
+
+
+def run_method_grid(H, bvh, rays, opts, reps):
+    """The frame workload's method grid: TwoPoint K in {32, 64}; HCC with the paper-exact cut
+    (C = K) and with larger cuts C in {256 ... 4096} truncated to K bits; MLHCC16 (8+8) and
+    MLHCC32 (16+16); the regular-grid control at K in {32, 64}."""
+    vs = [dict(mode="twopoint", K=k) for k in (32, 64)]
+    vs += [dict(mode="hcc", C=c, K=k) for k in (32, 64) for c in (k, 256, 512, 1024, 2048, 4096)]
+    vs += [dict(mode="mlhcc", top=8, low=8, K=16), dict(mode="mlhcc", top=16, low=16, K=32)]
+    vs += [dict(mode="grid", K=k) for k in (32, 64)]
+    rows = []
+    for v in vs:
+        rows.append(measure_variant(H, bvh, rays, v, opts, reps))
+    best = max(rows, key=lambda r: r["mrays_s"])
+    log("method grid: " + "; ".join(f"{r['method']} {r['mrays_s']:.0f} ({r['node_fetches_per_ray']:.1f} nf/ray)"
+                                    for r in rows))
+    log(f"method grid best: {best['method']} {best['mrays_s']} Mrays/s")
+    return rows
+
+
+def run_drift(H, args):
+    """Boundary-drift workload: 10M thin triangles in 64 Gaussian clusters inside the unit room,
+    1920x1080x4 camera, two diffuse bounces.  For each bounce: NoSort, and TwoPoint, HCC (C = K)
+    and the regular grid at K in {16, 24, 32, 48, 64}, with node fetches/ray and ANC."""
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    spec = W.cluster_scene(args.drift_tris, seed=90)
+    bvh = H.build_bvh(torch.from_numpy(spec.tris).to(dev))
+    opts = H.TraceOpts(64, 0, 0, 1, 32, 64, 8192, 1)
+    rays = W.pinhole_rays(spec, args.width, args.height, args.drift_spp, seed=91)
+    log(f"drift scene: {spec.tris.shape[0]} triangles, {rays.shape[0]} primary rays ({time.time() - t0:.1f}s)")
+    out = dict(triangles=int(spec.tris.shape[0]), camera=f"{args.width}x{args.height}x{args.drift_spp}",
+               bounces={})
+    ks = [int(k) for k in args.drift_keys.split(",")]
+    for bounce in (1, 2):
+        rd = torch.from_numpy(rays).to(dev)
+        h = H.trace(bvh, rd, opts=opts).cpu().numpy()
+        del rd
+        t, prim = h[:, 0].copy(), h[:, 1].copy().view(np.uint32)
+        rays, _ = W.spawn_diffuse(rays, t, prim, spec.tris, seed=92, bounce=bounce - 1)
+        rd = torch.from_numpy(rays).to(dev)
+        rows = [measure_variant(H, bvh, rd, dict(mode="nosort"), opts, args.drift_reps)]
+        for k in ks:
+            for v in (dict(mode="twopoint", K=k), dict(mode="hcc", C=k, K=k), dict(mode="grid", K=k)):
+                rows.append(measure_variant(H, bvh, rd, v, opts, args.drift_reps))
+        out["bounces"][str(bounce)] = dict(rays=int(rd.shape[0]), rows=rows)
+        log(f"drift bounce {bounce} ({rd.shape[0]} rays): " +
+            "; ".join(f"{r['method']} {r['mrays_s']:.0f} Mrays/s {r['node_fetches_per_ray']:.1f} nf/ray "
+                      f"anc32 {r.get('anc32', 0):.2f}" for r in rows))
+        del rd
+    return out
+
+
 def measured_traffic():
     """HBM bytes per trace launch from the committed PMC summary, if it still describes the
     current trace kernel sources (else None)."""
@@ -539,10 +686,19 @@ def cpu_baseline(tris_h, sec, args, gpu_hits, cut_size, key_bits):
     g = gpu_hits[:: args.cpu_stride]
     agree = float(np.mean(g[:, 1].copy().view(np.uint32) == h.prim))
     log(f"CPU oracle: {dt:.1f}s, {n / dt / 1e6:.3f} Mrays/s; prim agreement with GPU {agree:.6f}")
+    # the same oracle on one thread, over a sparser sample of the same rays
+    one = np.ascontiguousarray(sec[:: args.cpu_stride * 8])
+    t0 = time.time()
+    h1 = O.trace(ob, one, perm=O.sort(O.encode_hcc(one, cb, key_bits)), threads=1)
+    dt1 = time.time() - t0
+    log(f"CPU oracle, 1 thread: {one.shape[0]} rays in {dt1:.1f}s, {one.shape[0] / dt1 / 1e6:.4f} Mrays/s")
+    del h1
     return dict(value=round(n / dt / 1e6, 4), unit="Mrays/s", cores=cores, kind="oracle",
                 sample=f"every {args.cpu_stride}th bounce-1 secondary ray ({n} rays): HCC encode (C={cut_size}, "
                        f"K={key_bits}) + stable sort + closest-hit trace, {dt:.1f} s wall",
-                prim_agreement_with_gpu=agree)
+                prim_agreement_with_gpu=agree,
+                single_thread=dict(value=round(one.shape[0] / dt1 / 1e6, 4), unit="Mrays/s", cores=1,
+                                   sample=f"every {args.cpu_stride * 8}th ray ({one.shape[0]} rays), {dt1:.1f} s"))
 
 
 if __name__ == "__main__":

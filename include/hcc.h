@@ -64,6 +64,25 @@ typedef struct hcc_bvh_s* hcc_bvh;
 typedef struct hcc_cut_s* hcc_cut;
 typedef void* hcc_stream;     /* a hipStream_t */
 
+/* ---------------------------------------------------------------------------------------
+ * hcc_set_allocator -- where the library's own device memory comes from (not part of the
+ * paper's method; the memory plumbing around it).  By default BVH and cut handles and the
+ * build's temporaries use hipMalloc / hipFree, and request servers use stream-ordered
+ * hipMallocAsync / hipFreeAsync for their per-launch workspaces.  With hooks installed all
+ * of these go through them instead, e.g. a framework's caching allocator:
+ *   alloc(bytes, stream, ctx)  returns device memory of at least `bytes` for use on `stream`,
+ *                              or NULL, which makes the requesting call fail with HCC_ERR_OOM;
+ *   free(ptr, stream, ctx)     takes back a block alloc returned, once no queued work uses it.
+ * The setting is process-wide and affects objects created after the call.  Each handle and
+ * server keeps the pair it was created with and frees through it, so both functions and ctx
+ * must stay valid until those objects are destroyed.  A server calls them from its worker
+ * thread.  Both NULL restores the defaults; exactly one NULL is HCC_ERR_INVALID.
+ * hcc_encode, hcc_sort and hcc_trace allocate nothing either way.
+ */
+typedef void* (*hcc_alloc_fn)(size_t bytes, hcc_stream stream, void* ctx);
+typedef void (*hcc_free_fn)(void* ptr, hcc_stream stream, void* ctx);
+hcc_status hcc_set_allocator(hcc_alloc_fn alloc, hcc_free_fn free_fn, void* ctx);
+
 typedef struct hcc_ray { float ox, oy, oz, tmin, dx, dy, dz, tmax; } hcc_ray;
 typedef struct hcc_hit { float t; uint32_t prim; float u, v; } hcc_hit;   /* miss: t = +inf, prim = 0xFFFFFFFF */
 

@@ -86,6 +86,47 @@ def _check(status: int):
         raise HCCError(status, lib.hcc_last_error().decode())
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+lib.hcc_set_allocator.argtypes = [_P, _P, _P]
+lib.hcc_set_allocator.restype = C.c_int
+_HOOKS = []   # every installed callback pair stays alive: objects made under it free through it
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the library's own device memory (handles, build temporaries, server workspaces)
+    through ``alloc(nbytes, stream_ptr) -> int`` and ``free(ptr, stream_ptr)``.  With no
+    arguments the library goes back to hipMalloc / hipFree for objects created afterwards."""
+    if alloc is None and free is None:
+        _check(lib.hcc_set_allocator(None, None, None))
+        return
+    if alloc is None or free is None:
+        raise ValueError("give both alloc and free, or neither")
+
+    def _a(nbytes, stream, ctx):
+        try:
+            return alloc(int(nbytes), stream or 0) or None
+        except Exception:       # an exception cannot cross the C boundary: report OOM instead
+            return None
+
+    def _f(ptr, stream, ctx):
+        try:
+            free(ptr, stream or 0)
+        except Exception:
+            pass
+
+    pair = (ALLOC_FN(_a), FREE_FN(_f))
+    _HOOKS.append(pair)
+    _check(lib.hcc_set_allocator(C.cast(pair[0], _P), C.cast(pair[1], _P), None))
+
+
+def use_torch_allocator(device=None):
+    """Back the library's device memory with PyTorch's caching allocator."""
+    dev = torch.cuda.current_device() if device is None else device
+    set_allocator(lambda n, s: torch.cuda.caching_allocator_alloc(max(n, 1), dev, s),
+                  lambda p, s: torch.cuda.caching_allocator_delete(p))
+
+
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
@@ -198,6 +239,21 @@ def select_mlhcc_cut(bvh: BVH, top: int, low: int, lam: float = 0.125, stream=No
     h = _H()
     _check(lib.hcc_select_mlhcc_cut(bvh.handle, top, low, float(lam), _stream(stream), C.byref(h)))
     return Cut(h.value, bvh)
+
+
+def grid_dims(cells: int):
+    """The most cubic factorisation gx >= gy >= gz of a cell count (one key bit per cell)."""
+    best = None
+    for gz in range(1, cells + 1):
+        if cells % gz:
+            continue
+        for gy in range(gz, cells // gz + 1):
+            if (cells // gz) % gy or cells // (gz * gy) < gy:
+                continue
+            gx = cells // (gz * gy)
+            if best is None or gx - gz < best[0] - best[2]:
+                best = (gx, gy, gz)
+    return best
 
 
 def grid_cut(bvh: BVH, gx: int, gy: int, gz: int, stream=None) -> Cut:

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <queue>
 #include <string>
 #include <vector>
@@ -35,6 +36,13 @@ hcc_status batch_run(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32
 
 namespace {
 thread_local std::string g_error;
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+}
+
+Allocator current_allocator() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
 }
 
 void set_error(const std::string& msg) { g_error = msg; }
@@ -190,11 +198,16 @@ hcc_status finish_cut(hcc_cut_s* c, hipStream_t stream, hcc_cut* out) {
         up[off + i].lo = make_float4(bx[0], bx[1], bx[2], 0.0f);
         up[off + i].hi = make_float4(bx[3], bx[4], bx[5], 0.0f);
     }
-    hipError_t e = hipMalloc((void**)&c->d_boxes, sizeof(CutBox) * up.size());
-    if (e == hipSuccess) e = hipMemcpyAsync(c->d_boxes, up.data(), sizeof(CutBox) * up.size(), hipMemcpyHostToDevice, stream);
+    c->alloc = current_allocator();
+    c->d_boxes = (CutBox*)c->alloc.get(sizeof(CutBox) * up.size(), stream);
+    if (!c->d_boxes) {
+        delete c;
+        return fail(HCC_ERR_OOM, "device allocation failed for the cut's boxes");
+    }
+    hipError_t e = hipMemcpyAsync(c->d_boxes, up.data(), sizeof(CutBox) * up.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
-        (void)hipFree(c->d_boxes);
+        c->alloc.put(c->d_boxes, stream);
         delete c;
         return hip_fail(e, "cut upload");
     }
@@ -208,6 +221,17 @@ hcc_status finish_cut(hcc_cut_s* c, hipStream_t stream, hcc_cut* out) {
 using namespace hcc;
 
 extern "C" {
+
+__attribute__((visibility("default"))) hcc_status hcc_set_allocator(hcc_alloc_fn alloc, hcc_free_fn free_fn,
+                                                                    void* ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(HCC_ERR_INVALID, "hcc_set_allocator: give both functions or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.release = free_fn;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+    return HCC_OK;
+}
 
 __attribute__((visibility("default"))) const char* hcc_last_error(void) { return g_error.c_str(); }
 
@@ -267,36 +291,16 @@ __attribute__((visibility("default"))) hcc_status hcc_select_cut(hcc_bvh bvh, ui
     c->bvh = bvh;
     c->c_eff = (uint32_t)ids.size();
     c->ids = ids;
-    c->had.resize(ids.size());
-    c->boxes.resize(ids.size() * 6);
-    std::vector<float> all(6 * (2 * (size_t)bvh->n - 1));
-    hipError_t e = hipMemcpy(all.data(), bvh->boxes, sizeof(float) * all.size(), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) {
+    std::vector<float> all;
+    if ((st = download_boxes(bvh, all)) != HCC_OK) {
         delete c;
-        return hip_fail(e, "hcc_select_cut: box copy");
+        return st;
     }
-    std::vector<CutBox> up(ids.size());
-    for (size_t i = 0; i < ids.size(); ++i) {
-        c->had[i] = bvh->h_had[ids[i]];
-        const float* bx = &all[6 * (size_t)ids[i]];
-        std::memcpy(&c->boxes[6 * i], bx, 6 * sizeof(float));
-        up[i].lo = make_float4(bx[0], bx[1], bx[2], 0.0f);
-        up[i].hi = make_float4(bx[3], bx[4], bx[5], 0.0f);
+    for (uint32_t id : ids) {
+        c->had.push_back(bvh->h_had[id]);
+        c->boxes.insert(c->boxes.end(), &all[6 * (size_t)id], &all[6 * (size_t)id] + 6);
     }
-    e = hipMalloc((void**)&c->d_boxes, sizeof(CutBox) * std::max<size_t>(1, up.size()));
-    if (e != hipSuccess) {
-        delete c;
-        return hip_fail(e, "hcc_select_cut: hipMalloc");
-    }
-    e = hipMemcpyAsync(c->d_boxes, up.data(), sizeof(CutBox) * up.size(), hipMemcpyHostToDevice, S(stream));
-    if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
-    if (e != hipSuccess) {
-        (void)hipFree(c->d_boxes);
-        delete c;
-        return hip_fail(e, "hcc_select_cut: upload");
-    }
-    *out = c;
-    return HCC_OK;
+    return finish_cut(c, S(stream), out);
 }
 
 __attribute__((visibility("default"))) hcc_status hcc_cut_info(hcc_cut cut, uint32_t* c_eff) {
@@ -316,7 +320,7 @@ __attribute__((visibility("default"))) hcc_status hcc_cut_export(hcc_cut cut, ui
 
 __attribute__((visibility("default"))) void hcc_cut_destroy(hcc_cut cut) {
     if (!valid_cut(cut)) return;
-    (void)hipFree(cut->d_boxes);
+    cut->alloc.put(cut->d_boxes, nullptr);
     cut->magic = 0;
     delete cut;
 }

@@ -254,14 +254,10 @@ __global__ void k_leaf_had(const float* __restrict__ boxes, uint32_t n, double* 
 }
 
 template <typename T>
-hcc_status dalloc(T** p, size_t count, size_t& bytes) {
+hcc_status dalloc(const Allocator& A, hipStream_t s, T** p, size_t count, size_t& bytes) {
     const size_t b = std::max<size_t>(count, 1) * sizeof(T);
-    hipError_t e = hipMalloc((void**)p, b);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(HCC_ERR_OOM, "hipMalloc failed in hcc_build_bvh");
-    }
+    *p = (T*)A.get(b, s);
+    if (!*p) return fail(HCC_ERR_OOM, "device allocation failed in hcc_build_bvh");
     bytes += b;
     return HCC_OK;
 }
@@ -272,19 +268,22 @@ inline unsigned blocks_for(size_t n, unsigned per = 256) { return (unsigned)((n 
 
 void free_bvh(hcc_bvh_s* b) {
     if (!b) return;
-    (void)hipFree(b->nodes);
-    (void)hipFree(b->tris);
-    (void)hipFree(b->boxes);
-    (void)hipFree(b->had);
-    (void)hipFree(b->child);
-    (void)hipFree(b->leaf_prim);
-    (void)hipFree(b->parent);
+    const Allocator& A = b->alloc;
+    A.put(b->nodes, nullptr);
+    A.put(b->tris, nullptr);
+    A.put(b->boxes, nullptr);
+    A.put(b->had, nullptr);
+    A.put(b->child, nullptr);
+    A.put(b->leaf_prim, nullptr);
+    A.put(b->parent, nullptr);
     b->magic = 0;
     delete b;
 }
 
 hcc_status build_bvh(const float* d_tris, uint32_t n, hipStream_t stream, hcc_bvh_s** out) {
     hcc_bvh_s* b = new hcc_bvh_s();
+    b->alloc = current_allocator();
+    const Allocator A = b->alloc;
     b->n = n;
     b->n_int = n - 1;
     (void)hipGetDevice(&b->device);
@@ -299,13 +298,13 @@ hcc_status build_bvh(const float* d_tris, uint32_t n, hipStream_t stream, hcc_bv
             return st;              \
         }                           \
     } while (0)
-    TRY(dalloc(&b->nodes, b->n_int, bytes));
-    TRY(dalloc(&b->tris, n, bytes));
-    TRY(dalloc(&b->boxes, nn * 6, bytes));
-    TRY(dalloc(&b->had, nn, bytes));
-    TRY(dalloc(&b->child, 2 * (size_t)b->n_int, bytes));
-    TRY(dalloc(&b->leaf_prim, n, bytes));
-    TRY(dalloc(&b->parent, nn, bytes));
+    TRY(dalloc(A, stream, &b->nodes, b->n_int, bytes));
+    TRY(dalloc(A, stream, &b->tris, n, bytes));
+    TRY(dalloc(A, stream, &b->boxes, nn * 6, bytes));
+    TRY(dalloc(A, stream, &b->had, nn, bytes));
+    TRY(dalloc(A, stream, &b->child, 2 * (size_t)b->n_int, bytes));
+    TRY(dalloc(A, stream, &b->leaf_prim, n, bytes));
+    TRY(dalloc(A, stream, &b->parent, nn, bytes));
     b->bytes = bytes;
 
     // temporaries
@@ -319,12 +318,12 @@ hcc_status build_bvh(const float* d_tris, uint32_t n, hipStream_t stream, hcc_bv
     void* ws = nullptr;
     const size_t ws_bytes = sort_workspace_bytes(n, 30);
     auto cleanup = [&]() {
-        (void)hipFree(partial);
-        (void)hipFree(d_box);
-        (void)hipFree(codes);
-        (void)hipFree(codes_sorted);
-        (void)hipFree(flags);
-        (void)hipFree(ws);
+        A.put(partial, stream);
+        A.put(d_box, stream);
+        A.put(codes, stream);
+        A.put(codes_sorted, stream);
+        A.put(flags, stream);
+        A.put(ws, stream);
     };
 #define TRYT(x)                     \
     do {                            \
@@ -335,13 +334,12 @@ hcc_status build_bvh(const float* d_tris, uint32_t n, hipStream_t stream, hcc_bv
             return st;              \
         }                           \
     } while (0)
-    TRYT(dalloc(&partial, (size_t)nb_bounds * 6, tmp_bytes));
-    TRYT(dalloc(&d_box, 6, tmp_bytes));
-    TRYT(dalloc(&codes, n, tmp_bytes));
-    TRYT(dalloc(&codes_sorted, n, tmp_bytes));
-    TRYT(dalloc(&flags, std::max<size_t>(b->n_int, 1), tmp_bytes));
-    if (hipMalloc(&ws, ws_bytes) != hipSuccess) {
-        (void)hipGetLastError();
+    TRYT(dalloc(A, stream, &partial, (size_t)nb_bounds * 6, tmp_bytes));
+    TRYT(dalloc(A, stream, &d_box, 6, tmp_bytes));
+    TRYT(dalloc(A, stream, &codes, n, tmp_bytes));
+    TRYT(dalloc(A, stream, &codes_sorted, n, tmp_bytes));
+    TRYT(dalloc(A, stream, &flags, std::max<size_t>(b->n_int, 1), tmp_bytes));
+    if ((ws = A.get(ws_bytes, stream)) == nullptr) {
         cleanup();
         free_bvh(b);
         return fail(HCC_ERR_OOM, "hipMalloc failed in hcc_build_bvh (sort workspace)");
@@ -382,17 +380,15 @@ hcc_status recompute_had(hcc_bvh_s* b, double lambda, hipStream_t stream) {
         return HCC_OK;
     }
     uint32_t* flags = nullptr;
-    if (hipMalloc(&flags, sizeof(uint32_t) * b->n_int) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(HCC_ERR_OOM, "hipMalloc failed in hcc_select_cut");
-    }
+    if ((flags = (uint32_t*)b->alloc.get(sizeof(uint32_t) * b->n_int, stream)) == nullptr)
+        return fail(HCC_ERR_OOM, "device allocation failed in hcc_select_cut");
     k_fill<<<blocks_for(b->n_int), 256, 0, stream>>>(flags, b->n_int, 0u);
     k_leaf_had<<<blocks_for(b->n), 256, 0, stream>>>(b->boxes, b->n, b->had);
     k_refit<false><<<blocks_for(b->n), 256, 0, stream>>>(b->n, b->child, b->parent, flags, b->boxes, b->had,
                                                          b->nodes, lambda);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    (void)hipFree(flags);
+    b->alloc.put(flags, stream);
     if (e != hipSuccess) return hip_fail(e, "hcc_select_cut (HAD)");
     b->had_lambda = lambda;
     return HCC_OK;

@@ -84,6 +84,29 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 // Host-side error helpers ---------------------------------------------------------------
 void set_error(const std::string& msg);
 hcc_status fail(hcc_status st, const std::string& msg);
+
+// Device memory the library owns: hipMalloc / hipFree unless hcc_set_allocator installed
+// hooks.  Objects keep the allocator they were created with and free through it.
+struct Allocator {
+    hcc_alloc_fn alloc = nullptr;
+    hcc_free_fn release = nullptr;
+    void* ctx = nullptr;
+    void* get(size_t bytes, hipStream_t s) const {
+        if (alloc) return alloc(bytes, (hcc_stream)s, ctx);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void put(void* p, hipStream_t s) const {
+        if (!p) return;
+        if (release) release(p, (hcc_stream)s, ctx);
+        else (void)hipFree(p);
+    }
+};
+Allocator current_allocator();
 hcc_status hip_fail(hipError_t e, const char* what);
 
 #define HCC_HIP(call)                                                  \
@@ -127,6 +150,7 @@ struct hcc_bvh_s {
     std::vector<double> h_had;
     std::vector<uint32_t> h_leaves; // leaves below each node (two-level cut search)
     double h_had_lambda = -1.0;
+    hcc::Allocator alloc;           // the device memory above came from here
     uint64_t magic = 0x6863636276680001ull;
 };
 
@@ -142,5 +166,6 @@ struct hcc_cut_s {
     std::vector<uint32_t> low_ids;  // c_eff x low
     std::vector<float> low_boxes;   // c_eff x low x 6
     hcc::CutBox* d_boxes = nullptr; // c_eff boxes, then (two-level) c_eff x low boxes
+    hcc::Allocator alloc;           // d_boxes came from here
     uint64_t magic = 0x6863636375740001ull;
 };

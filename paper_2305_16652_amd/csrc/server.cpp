@@ -57,6 +57,7 @@ struct Group {
     hipEvent_t done = nullptr;
     void* ws = nullptr;
     void* pinned = nullptr;
+    size_t pinned_bytes = 0;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
 };
@@ -73,6 +74,11 @@ struct hcc_server_s {
     std::deque<uint64_t> pending;
     std::unordered_map<uint64_t, Req> reqs;
     std::vector<Group> inflight;
+    // reused between groups: pinned staging buffers for the launch tables (size, pointer)
+    // and completion events; allocating either per launch costs more than a small launch
+    std::vector<std::pair<size_t, void*>> pinned_free;
+    std::vector<hipEvent_t> events_free;
+    hcc::Allocator alloc;           // hooks at creation; without hooks, stream-ordered hipMallocAsync
     uint64_t next_id = 1;
     size_t used_bytes = 0;
     uint32_t running = 0;
@@ -95,6 +101,22 @@ size_t request_bytes(const hcc_batch_desc& d, uint32_t mode, uint32_t key_bits) 
     return (size_t)d.n * (sizeof(hcc_ray) + (d.mode == HCC_TRACE_CLOSEST ? sizeof(hcc_hit) : 1)) + ws;
 }
 
+void* dev_get(hcc_server_s* s, size_t bytes, hipStream_t st) {
+    if (s->alloc.alloc) return s->alloc.get(bytes, st);
+    void* p = nullptr;
+    if (hipMallocAsync(&p, bytes, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void dev_put(hcc_server_s* s, void* p, hipStream_t st) {
+    if (!p) return;
+    if (s->alloc.alloc) s->alloc.put(p, st);
+    else (void)hipFreeAsync(p, st);
+}
+
 void finish_group(hcc_server_s* s, Group& g, bool ok) {
     const auto now = Clock::now();
     for (uint64_t id : g.ids) {
@@ -105,10 +127,41 @@ void finish_group(hcc_server_s* s, Group& g, bool ok) {
         s->running -= 1;
         s->completed += 1;
     }
-    if (g.ws) (void)hipFreeAsync(g.ws, g.stream);
-    if (g.pinned) (void)hipHostFree(g.pinned);
-    if (g.done) (void)hipEventDestroy(g.done);
+    if (g.ws) dev_put(s, g.ws, g.stream);
+    if (g.pinned) s->pinned_free.emplace_back(g.pinned_bytes, g.pinned);
+    if (g.done) s->events_free.push_back(g.done);
     g = Group();
+}
+
+// A pinned buffer of at least `bytes` from the free list (the smallest that fits), else a new one.
+void* take_pinned(hcc_server_s* s, size_t bytes, size_t* got) {
+    size_t best = s->pinned_free.size();
+    for (size_t i = 0; i < s->pinned_free.size(); ++i)
+        if (s->pinned_free[i].first >= bytes && (best == s->pinned_free.size() ||
+                                                 s->pinned_free[i].first < s->pinned_free[best].first))
+            best = i;
+    if (best < s->pinned_free.size()) {
+        void* p = s->pinned_free[best].second;
+        *got = s->pinned_free[best].first;
+        s->pinned_free.erase(s->pinned_free.begin() + (ptrdiff_t)best);
+        return p;
+    }
+    const size_t sz = std::max<size_t>(bytes, 64u << 10);
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) return nullptr;
+    *got = sz;
+    return p;
+}
+
+hipEvent_t take_event(hcc_server_s* s) {
+    if (!s->events_free.empty()) {
+        hipEvent_t e = s->events_free.back();
+        s->events_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
 }
 
 // Plain mode: one request through encode / sort / trace, waited for before the next.
@@ -122,9 +175,9 @@ bool run_plain(hcc_server_s* s, const hcc_batch_desc& d) {
     if (mode != HCC_KEY_NONE && d.n > 0) {
         const size_t ks = kb <= 32 ? 4 : 8;
         const size_t wsb = hcc::sort_workspace_bytes(d.n, kb);
-        ok = hipMallocAsync(&keys, (size_t)d.n * ks, st) == hipSuccess &&
-             hipMallocAsync((void**)&perm, (size_t)d.n * 4, st) == hipSuccess &&
-             hipMallocAsync(&ws, wsb, st) == hipSuccess;
+        ok = (keys = dev_get(s, (size_t)d.n * ks, st)) != nullptr &&
+             (perm = (uint32_t*)dev_get(s, (size_t)d.n * 4, st)) != nullptr &&
+             (ws = dev_get(s, wsb, st)) != nullptr;
         if (ok) ok = (mode == HCC_KEY_HCC ? hcc::encode_hcc(d.cut, kb, d.d_rays, d.n, keys, st)
                                           : hcc::encode_twopoint(d.bvh, kb, d.d_rays, d.n, keys, st)) == HCC_OK;
         if (ok) ok = hcc::radix_sort(keys, kb, d.n, perm, nullptr, nullptr, ws, wsb, st) == HCC_OK;
@@ -137,10 +190,11 @@ bool run_plain(hcc_server_s* s, const hcc_batch_desc& d) {
     if (ok && d.n > 0)
         ok = hcc::trace(d.bvh, d.d_rays, perm, d.n, d.mode == HCC_TRACE_CLOSEST, d.d_hits, d.d_occluded, to, st) ==
              HCC_OK;
-    if (keys) (void)hipFreeAsync(keys, st);
-    if (perm) (void)hipFreeAsync(perm, st);
-    if (ws) (void)hipFreeAsync(ws, st);
-    return hipStreamSynchronize(st) == hipSuccess && ok;
+    const bool synced = hipStreamSynchronize(st) == hipSuccess;
+    dev_put(s, keys, st);
+    dev_put(s, perm, st);
+    dev_put(s, ws, st);
+    return synced && ok;
 }
 
 void worker_loop(hcc_server_s* s) {
@@ -202,18 +256,16 @@ void worker_loop(hcc_server_s* s) {
                                            &g.bytes) == HCC_OK;
             const size_t tb = hcc::batch_table_bytes(ds.data(), (uint32_t)ds.size(), s->opts.key_mode,
                                                      s->opts.key_bits);
-            ok = ok && hipMallocAsync(&g.ws, g.bytes, g.stream) == hipSuccess;
-            ok = ok && hipHostMalloc(&g.pinned, tb, hipHostMallocDefault) == hipSuccess;
+            ok = ok && (g.ws = dev_get(s, g.bytes, g.stream)) != nullptr;
+            ok = ok && (g.pinned = take_pinned(s, tb, &g.pinned_bytes)) != nullptr;
             ok = ok && hcc::batch_launch(ds.data(), (uint32_t)ds.size(), s->opts.key_mode, s->opts.key_bits,
                                          s->opts.batch, g.ws, g.bytes, g.stream, g.pinned, tb) == HCC_OK;
-            ok = ok && hipEventCreateWithFlags(&g.done, hipEventDisableTiming) == hipSuccess;
+            ok = ok && (g.done = take_event(s)) != nullptr;
             ok = ok && hipEventRecord(g.done, g.stream) == hipSuccess;
             s->launches += 1;
             if (!ok) {
                 s->error = "launch failed: " + std::string(hcc_last_error());
-                if (g.done) {
-                    (void)hipStreamSynchronize(g.stream);
-                }
+                (void)hipStreamSynchronize(g.stream);   // nothing may still read the staging buffer
                 finish_group(s, g, false);
             } else {
                 s->inflight.push_back(std::move(g));
@@ -250,6 +302,7 @@ __attribute__((visibility("default"))) hcc_status hcc_server_create(const hcc_se
         return fail(HCC_ERR_INVALID, "hcc_server_create: bad options");
     hcc_server_s* s = new hcc_server_s();
     s->opts = o;
+    s->alloc = hcc::current_allocator();
     (void)hipGetDevice(&s->device);
     for (uint32_t i = 0; i < o.streams; ++i) {
         hipStream_t st;
@@ -359,6 +412,8 @@ __attribute__((visibility("default"))) void hcc_server_destroy(hcc_server s) {
     }
     s->worker.join();
     for (auto st : s->streams) (void)hipStreamDestroy(st);
+    for (auto& p : s->pinned_free) (void)hipHostFree(p.second);
+    for (auto e : s->events_free) (void)hipEventDestroy(e);
     s->magic = 0;
     delete s;
 }

@@ -56,3 +56,14 @@ def test_validation_without_device(H):
 def test_sort_workspace_grows_with_n_and_bits(H):
     assert H.sort_workspace_bytes(1 << 20, 64) > H.sort_workspace_bytes(1 << 20, 32) > \
         H.sort_workspace_bytes(1 << 10, 32)
+
+
+def test_set_allocator_validation(H):
+    """Both hooks or neither; a Python pair can be installed and removed without a device."""
+    keep = H.ALLOC_FN(lambda n, s, c: None)
+    assert H.lib.hcc_set_allocator(C.cast(keep, C.c_void_p), None, None) == 1
+    assert H.lib.hcc_set_allocator(None, None, None) == 0
+    with pytest.raises(ValueError):
+        H.set_allocator(alloc=lambda n, s: 0)
+    H.set_allocator(lambda n, s: 0, lambda p, s: None)
+    H.set_allocator()
