@@ -260,6 +260,7 @@ def _load_extra():
     lib.oracle_select_mlhcc_cut.restype = C.c_int
     lib.oracle_encode_mlhcc.argtypes = [P, u32, P, u32, P, u32, u32, P]
     lib.oracle_grid_boxes.argtypes = [P, u32, u32, u32, P]
+    lib.oracle_encode_ppc.argtypes = [P, u32, u32, P, P, u32, P]
     lib._extra = True
     return lib
 
@@ -292,6 +293,42 @@ def encode_mlhcc(rays, top_boxes, low_boxes, low: int, key_bits: int, threads: i
     with ThreadPoolExecutor(max(1, threads)) as ex:
         list(ex.map(run, _chunks(n, threads)))
     return out.astype(_key_dtype(key_bits))
+
+
+def encode_ppc(bvh: OracleBVH, rays, key_bits: int, threads: int = 1) -> np.ndarray:
+    """Prefix path code (Section 4.1): the first key_bits box tests of a forced-order walk."""
+    rays = _f32(rays, 8)
+    n = rays.shape[0]
+    out = np.empty(n, np.uint64)
+    lib = _load_extra()
+
+    def run(rng):
+        k0, k1 = rng
+        lib.oracle_encode_ppc(_ptr(rays[k0:k1]), k1 - k0, bvh.n, _ptr(bvh.child), _ptr(bvh.boxes), key_bits,
+                              _ptr(out[k0:k1]))
+
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        list(ex.map(run, _chunks(n, threads)))
+    return out.astype(_key_dtype(key_bits))
+
+
+def sort_prefix(keys, key_bits: int, skip_bits: int) -> np.ndarray:
+    """Early-terminated sort (Section 6.7's overhead discussion: skip the last bits): the stable
+    ascending permutation by the key's top key_bits - skip_bits bits; the low skip_bits bits do
+    not take part."""
+    k = np.ascontiguousarray(keys).astype(np.uint64) >> np.uint64(skip_bits)
+    return sort(k)
+
+
+def sort_tiles(keys, tile: int) -> np.ndarray:
+    """Tile-local sort: consecutive groups of `tile` rays (the last one ragged) are each sorted
+    stably by key on their own; no ray leaves its group."""
+    k = np.ascontiguousarray(keys).astype(np.uint64)
+    perm = np.empty(k.shape[0], np.uint32)
+    for t0 in range(0, k.shape[0], tile):
+        t1 = min(k.shape[0], t0 + tile)
+        perm[t0:t1] = t0 + sort(k[t0:t1])
+    return perm
 
 
 def grid_dims(key_bits: int):

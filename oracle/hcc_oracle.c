@@ -459,6 +459,48 @@ void oracle_encode_mlhcc(const float* rays, uint32_t n, const float* top_boxes, 
     }
 }
 
+/* ------------------------------------------------------------------ PPC key (Section 4.1)
+ * Prefix path code: every ray walks the BVH in one and the same forced order and each box
+ * test on the walk appends one bit (1 = the ray meets the box), most significant first, until
+ * key_bits tests have been made.  Readings: expanding a node tests its two children, child 0
+ * then child 1; the walk is depth first with child 0's subtree before child 1's; only
+ * internal children that were met are expanded; the segment is the ray's own [tmin, tmax]
+ * throughout (no shortening by hits, since no triangle is tested); a walk that runs out of
+ * nodes leaves the remaining low bits zero.  A one-triangle BVH makes the single test of its
+ * root leaf's box.  n_tris is the triangle count, child the (n-1) x 2 unified child ids and
+ * boxes the (2n-1) x 6 node boxes. */
+void oracle_encode_ppc(const float* rays, uint32_t n, uint32_t n_tris, const uint32_t* child, const float* boxes,
+                       uint32_t key_bits, uint64_t* keys) {
+    uint32_t* stack = (uint32_t*)malloc(sizeof(uint32_t) * (key_bits + 2));
+    for (uint32_t r = 0; r < n; ++r) {
+        const float* ry = rays + 8 * (size_t)r;
+        float o[3] = {ry[0], ry[1], ry[2]};
+        float inv[3] = {1.0f / ry[4], 1.0f / ry[5], 1.0f / ry[6]};
+        uint64_t key = 0;
+        if (n_tris == 1) {
+            if (slab_hit(o, inv, ry[3], ry[7], boxes, 0)) key = (uint64_t)1 << (key_bits - 1);
+            keys[r] = key;
+            continue;
+        }
+        uint32_t bits = 0, sp = 0;
+        stack[sp++] = 0;
+        while (sp > 0 && bits < key_bits) {
+            uint32_t node = stack[--sp];
+            int met[2] = {0, 0};
+            for (int c = 0; c < 2 && bits < key_bits; ++c) {
+                met[c] = slab_hit(o, inv, ry[3], ry[7], boxes + 6 * (size_t)child[2 * node + c], 0);
+                if (met[c]) key |= (uint64_t)1 << (key_bits - 1 - bits);
+                ++bits;
+            }
+            /* child 1 goes below child 0 so that child 0's subtree is walked first */
+            for (int c = 1; c >= 0; --c)
+                if (met[c] && child[2 * node + c] < n_tris - 1) stack[sp++] = child[2 * node + c];
+        }
+        keys[r] = key;
+    }
+    free(stack);
+}
+
 /* ------------------------------------------------------------------ O5: TwoPoint key
  * Baseline of Section 3.2 / Section 5: 6-D Morton code of the origin and an
  * estimated termination point at fixed distance 0.25 * (largest scene extent)

@@ -107,3 +107,91 @@ def test_grid_key_single_cell_segments():
         rays.append([x + 0.3, y + 0.4, z + 0.45, 0, 0.2, 0.1, 0.05, 1.0])   # short segment inside the cell
     keys = O.encode_hcc(np.array(rays, np.float32), boxes, 32)
     assert keys.tolist() == [1 << (31 - c) for c in range(32)]
+
+
+# ----------------------------------------------------------------------------- prefix path code
+
+def _ppc_walk(bvh, ray, key_bits):
+    """The forced-order walk written recursively: expanding a node tests child 0 then child 1;
+    child 0's subtree is finished before child 1's."""
+    from test_oracle import _np_slab
+    seq = []
+
+    def expand(node):
+        met = []
+        for c in bvh.child[node]:
+            if len(seq) == key_bits:
+                return
+            h = _np_slab(ray, bvh.boxes[int(c)])
+            seq.append(h)
+            met.append((int(c), h))
+        for c, h in met:
+            if len(seq) == key_bits:
+                return
+            if h and not bvh.is_leaf(c):
+                expand(c)
+
+    if bvh.n == 1:
+        seq.append(_np_slab(ray, bvh.boxes[0]))
+    else:
+        expand(0)
+    return sum(1 << (key_bits - 1 - i) for i, h in enumerate(seq) if h)
+
+
+def test_ppc_hand_example():
+    bvh = O.build_bvh(_four_triangles())          # root -> (1, 2); 1 -> (T0, T2); 2 -> (T1, T3)
+    rays = np.array([[0.05, 0.03, -1, 0, 0, 0, 1, np.inf],     # T0: 1 met, 2 not; then T0 met, T2 not
+                     [0.9, 0.9, -1, 0, 0, 0, 1, np.inf],       # T3: 1 not, 2 met; then T1 not, T3 met
+                     [0.5, 0.5, -1, 0, 0, 0, 1, np.inf],       # nothing
+                     [0.05, 0.5, -1, 0, 0, 0, 1, np.inf]],     # node 1's box only
+                    np.float32)
+    assert O.encode_ppc(bvh, rays, 4).tolist() == [0b1010, 0b0101, 0, 0b1000]
+    assert O.encode_ppc(bvh, rays, 6).tolist() == [0b101000, 0b010100, 0, 0b100000]
+    assert O.encode_ppc(bvh, rays, 3).tolist() == [0b101, 0b010, 0, 0b100]   # walk cut after 3 tests
+    one = O.build_bvh(_four_triangles()[:1])
+    assert O.encode_ppc(one, rays[:3], 5).tolist() == [0b10000, 0, 0]
+
+
+@pytest.mark.parametrize("key_bits", [1, 7, 16, 32, 64])
+def test_ppc_matches_recursive_walk(key_bits):
+    bvh = O.build_bvh(W.tiny_scene().tris)
+    rays = random_rays(400, 17, 0.0, 1.0)
+    rays[::3, 7] = 0.15
+    keys = O.encode_ppc(bvh, rays, key_bits)
+    for r, k in zip(rays, keys):
+        assert int(k) == _ppc_walk(bvh, r, key_bits)
+
+
+def test_ppc_prefix_property_and_scale():
+    bvh = O.build_bvh(W.tiny_scene().tris)
+    rays = random_rays(600, 19, 0.0, 1.0)
+    k64 = O.encode_ppc(bvh, rays, 64).astype(np.uint64)
+    for kb in (8, 20, 33, 63):
+        assert np.array_equal(k64 >> np.uint64(64 - kb), O.encode_ppc(bvh, rays, kb).astype(np.uint64))
+    big = O.build_bvh(W.tiny_scene().tris * np.float32(4.0))
+    r4 = rays.copy()
+    r4[:, 0:3] *= 4.0
+    assert np.array_equal(O.encode_ppc(big, r4, 64), k64)
+
+
+# ----------------------------------------------------------------------------- shorter sorts
+
+def test_sort_prefix_definition():
+    rng = np.random.default_rng(3)
+    keys = rng.integers(0, 1 << 20, 3000).astype(np.uint32)
+    for skip in (0, 4, 8, 13, 20):
+        perm = O.sort_prefix(keys, 20, skip)
+        expect = sorted(range(keys.size), key=lambda i: (int(keys[i]) >> skip, i))
+        assert perm.tolist() == expect
+
+
+def test_sort_tiles_definition():
+    rng = np.random.default_rng(4)
+    keys = rng.integers(0, 50, 1000).astype(np.uint64)
+    for tile in (1, 64, 100, 999, 1000, 4096):
+        perm = O.sort_tiles(keys, tile)
+        expect = []
+        for t0 in range(0, 1000, tile):
+            idx = range(t0, min(1000, t0 + tile))
+            expect += sorted(idx, key=lambda i: (int(keys[i]), i))
+        assert perm.tolist() == expect
