@@ -500,12 +500,18 @@ def run_batched(H, args):
 def variant_name(v) -> str:
     m = v["mode"]
     if m == "hcc":
-        return f"hcc C={v['C']} K={v['K']}"
-    if m == "mlhcc":
-        return f"mlhcc{v['top'] + v['low']} ({v['top']}+{v['low']})"
-    if m == "nosort":
+        name = f"hcc C={v['C']} K={v['K']}"
+    elif m == "mlhcc":
+        name = f"mlhcc{v['top'] + v['low']} ({v['top']}+{v['low']})"
+    elif m == "nosort":
         return "nosort"
-    return f"{m} K={v['K']}"
+    else:
+        name = f"{m} K={v['K']}"
+    if v.get("skip"):
+        name += f" skip {v['skip']}"
+    if v.get("tile"):
+        name += f" tile {v['tile']}"
+    return name
 
 
 def measure_variant(H, bvh, rays, v, opts, reps=5, closest=True, stats=True):
@@ -523,7 +529,9 @@ def measure_variant(H, bvh, rays, v, opts, reps=5, closest=True, stats=True):
         cut = H.select_mlhcc_cut(bvh, v["top"], v["low"])
     elif mode == "grid":
         cut = H.grid_cut(bvh, *H.grid_dims(K))
-    kmode = {"twopoint": H.KEY_TWOPOINT, "hcc": H.KEY_HCC, "grid": H.KEY_HCC, "mlhcc": H.KEY_MLHCC}.get(mode, 0)
+    kmode = {"twopoint": H.KEY_TWOPOINT, "hcc": H.KEY_HCC, "grid": H.KEY_HCC, "mlhcc": H.KEY_MLHCC,
+             "ppc": H.KEY_PPC}.get(mode, 0)
+    skip, tile = v.get("skip", 0), v.get("tile", 0)
     out = (torch.empty((R, 4), dtype=torch.float32, device=dev) if closest
            else torch.empty(R, dtype=torch.uint8, device=dev))
     keys = perm = ws = None
@@ -541,7 +549,10 @@ def measure_variant(H, bvh, rays, v, opts, reps=5, closest=True, stats=True):
         if e:
             e[1].record()
         if mode != "nosort":
-            H.sort(keys, K, perm=perm, ws=ws)
+            if skip or tile:
+                H.sort_ex(keys, K, skip_bits=skip, tile=tile, perm=perm, ws=ws)
+            else:
+                H.sort(keys, K, perm=perm, ws=ws)
         if e:
             e[2].record()
         H.trace(bvh, rays, perm, closest=closest, out=out, opts=opts)
@@ -580,11 +591,16 @@ def measure_variant(H, bvh, rays, v, opts, reps=5, closest=True, stats=True):
 def run_method_grid(H, bvh, rays, opts, reps):
     """The frame workload's method grid: TwoPoint K in {32, 64}; HCC with the paper-exact cut
     (C = K) and with larger cuts C in {256 ... 4096} truncated to K bits; MLHCC16 (8+8) and
-    MLHCC32 (16+16); the regular-grid control at K in {32, 64}."""
+    MLHCC32 (16+16); the regular-grid control and the prefix path code at K in {32, 64}; and
+    HCC / TwoPoint with the shorter sorts (low bits skipped, or tile-local sorts)."""
     vs = [dict(mode="twopoint", K=k) for k in (32, 64)]
     vs += [dict(mode="hcc", C=c, K=k) for k in (32, 64) for c in (k, 256, 512, 1024, 2048, 4096)]
     vs += [dict(mode="mlhcc", top=8, low=8, K=16), dict(mode="mlhcc", top=16, low=16, K=32)]
     vs += [dict(mode="grid", K=k) for k in (32, 64)]
+    vs += [dict(mode="ppc", K=k) for k in (32, 64)]
+    vs += [dict(mode="hcc", C=32, K=32, skip=8), dict(mode="hcc", C=32, K=32, skip=16),
+           dict(mode="hcc", C=32, K=32, tile=1024), dict(mode="hcc", C=32, K=32, tile=4096),
+           dict(mode="twopoint", K=32, tile=4096), dict(mode="twopoint", K=32, skip=16)]
     rows = []
     for v in vs:
         rows.append(measure_variant(H, bvh, rays, v, opts, reps))

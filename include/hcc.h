@@ -49,7 +49,8 @@ typedef enum {
     HCC_KEY_NONE = 0,         /* no key: rays traced in generation order ("NoSort") */
     HCC_KEY_HCC = 1,          /* hierarchy cut code (Section 4.2, Algorithm 1) */
     HCC_KEY_TWOPOINT = 2,     /* origin + estimated end point 6-D Morton code (Section 3.2) */
-    HCC_KEY_MLHCC = 3         /* multi-level hierarchy cut code (Section 4.3), two-level cut */
+    HCC_KEY_MLHCC = 3,        /* multi-level hierarchy cut code (Section 4.3), two-level cut */
+    HCC_KEY_PPC = 4           /* prefix path code (Section 4.1): forced-order walk, one bit per box test */
 } hcc_key_mode;
 
 typedef enum { HCC_TRACE_CLOSEST = 0, HCC_TRACE_ANY = 1 } hcc_trace_mode;
@@ -179,6 +180,12 @@ hcc_status hcc_cut_export_low(hcc_cut cut, uint32_t* h_low_ids, float* h_low_box
  *     distance 0.25 x (largest scene extent) along the normalised direction (clipped to the
  *     segment); dimension d of (ox,oy,oz,ex,ey,ez) gets key_bits/6 bits plus one if
  *     d < key_bits % 6, interleaved from the top level down.  cut is ignored.
+ *   HCC_KEY_MLHCC (Section 4.3): needs a two-level cut (hcc_select_mlhcc_cut); see there.
+ *   HCC_KEY_PPC (Section 4.1): every ray walks the BVH in one forced order (expanding a node
+ *     tests child 0 then child 1; child 0's subtree first; only met internal children are
+ *     expanded) over its own segment; box test number j (from 0) sets bit (key_bits-1-j) when
+ *     met; the walk stops after key_bits tests, and bits of a walk that ends earlier stay 0.
+ *     A one-triangle BVH makes one test, of the root leaf's box.  cut is ignored.
  * key_bits in [1, 64]; d_keys: uint32[n] if key_bits <= 32 else uint64[n].  n may be 0.
  */
 hcc_status hcc_encode(hcc_bvh bvh, hcc_cut cut, hcc_key_mode mode, uint32_t key_bits, const hcc_ray* d_rays,
@@ -194,6 +201,18 @@ hcc_status hcc_encode(hcc_bvh bvh, hcc_cut cut, hcc_key_mode mode, uint32_t key_
 hcc_status hcc_sort_workspace(uint32_t n, uint32_t key_bits, size_t* bytes);
 hcc_status hcc_sort(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm, void* d_sorted_keys,
                     void* d_ws, size_t ws_bytes, hcc_stream stream);
+
+/* hcc_sort_ex -- shorter sorts for the reorder overhead (Section 6.7: rays within one warp need
+ * no order among themselves, so the sort may skip the key's last bits or stop early).
+ *   skip_bits: the low skip_bits bits take no part: stable ascending by key >> skip_bits, in
+ *              ceil((key_bits - skip_bits) / 8) passes.  0 <= skip_bits < key_bits.
+ *   tile:      0 = one sort over all n keys (workspace as for hcc_sort with the same n and
+ *              key_bits); else a power of two in [256, 4096]: consecutive groups of `tile` keys
+ *              (the last one ragged) are each sorted stably on their own, in one kernel with no
+ *              workspace (d_ws may be NULL), and no index leaves its group.
+ * d_perm and d_sorted_keys as for hcc_sort (sorted keys keep their skipped bits). */
+hcc_status hcc_sort_ex(const void* d_keys, uint32_t key_bits, uint32_t skip_bits, uint32_t tile, uint32_t n,
+                       uint32_t* d_perm, void* d_sorted_keys, void* d_ws, size_t ws_bytes, hcc_stream stream);
 
 /* ---------------------------------------------------------------------------------------
  * hcc_trace -- BVH traversal of n rays taken in the order d_perm (NULL = 0..n-1), Section 5.

@@ -226,6 +226,7 @@ def select_cut(bvh: BVH, cut_size: int, lam: float = 0.125, stream=None) -> Cut:
 
 
 KEY_MLHCC = 3
+KEY_PPC = 4
 lib.hcc_select_mlhcc_cut.argtypes = [_H, _U32, _U32, C.c_double, _P, C.POINTER(_H)]
 lib.hcc_grid_cut.argtypes = [_H, _U32, _U32, _U32, _P, C.POINTER(_H)]
 lib.hcc_cut_shape.argtypes = [_H, C.POINTER(_U32), C.POINTER(_U32), C.POINTER(_U32)]
@@ -309,6 +310,24 @@ def sort(keys: torch.Tensor, key_bits: int, perm=None, sorted_keys=None, ws=None
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device=keys.device)
     _check(lib.hcc_sort(_dptr(keys), key_bits, n, _dptr(perm), _dptr(sorted_keys), _dptr(ws), ws.numel(),
                         _stream(stream)))
+    return perm
+
+
+lib.hcc_sort_ex.argtypes = [_P, _U32, _U32, _U32, _U32, _P, _P, _P, C.c_size_t, _P]
+lib.hcc_sort_ex.restype = C.c_int
+
+
+def sort_ex(keys: torch.Tensor, key_bits: int, skip_bits: int = 0, tile: int = 0, perm=None, sorted_keys=None,
+            ws=None, stream=None) -> torch.Tensor:
+    """Stable sort by the key's bits [skip_bits, key_bits), over all keys (tile 0) or within
+    consecutive tiles of `tile` keys (256 ... 4096, no workspace)."""
+    n = keys.shape[0]
+    if perm is None:
+        perm = torch.empty(n, dtype=torch.int32, device=keys.device)
+    if tile == 0 and ws is None:
+        ws = torch.empty(max(sort_workspace_bytes(n, key_bits), 256), dtype=torch.uint8, device=keys.device)
+    _check(lib.hcc_sort_ex(_dptr(keys), key_bits, skip_bits, tile, n, _dptr(perm), _dptr(sorted_keys), _dptr(ws),
+                           ws.numel() if ws is not None else 0, _stream(stream)))
     return perm
 
 

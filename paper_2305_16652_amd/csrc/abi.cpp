@@ -24,6 +24,8 @@ hcc_status encode_mlhcc(const hcc_cut_s* cut, uint32_t key_bits, const hcc_ray* 
                         hipStream_t stream);
 hcc_status encode_twopoint(const hcc_bvh_s* bvh, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n,
                            void* d_keys, hipStream_t stream);
+hcc_status encode_ppc(const hcc_bvh_s* bvh, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
+                      hipStream_t stream);
 hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
                  hcc_hit* hits, uint8_t* occ, const hcc_trace_opts& o, hipStream_t s);
 hcc_status trace_stats(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
@@ -346,8 +348,10 @@ __attribute__((visibility("default"))) hcc_status hcc_encode(hcc_bvh bvh, hcc_cu
             return encode_mlhcc(cut, key_bits, d_rays, n, d_keys, S(stream));
         case HCC_KEY_TWOPOINT:
             return encode_twopoint(bvh, key_bits, d_rays, n, d_keys, S(stream));
+        case HCC_KEY_PPC:
+            return encode_ppc(bvh, key_bits, d_rays, n, d_keys, S(stream));
         default:
-            return fail(HCC_ERR_INVALID, "hcc_encode: mode must be HCC_KEY_HCC, HCC_KEY_TWOPOINT or HCC_KEY_MLHCC");
+            return fail(HCC_ERR_INVALID, "hcc_encode: mode must be HCC_KEY_HCC, HCC_KEY_TWOPOINT, HCC_KEY_MLHCC or HCC_KEY_PPC");
     }
 }
 
@@ -363,6 +367,13 @@ __attribute__((visibility("default"))) hcc_status hcc_sort(const void* d_keys, u
                                                            uint32_t* d_perm, void* d_sorted_keys, void* d_ws,
                                                            size_t ws_bytes, hcc_stream stream) {
     return radix_sort(d_keys, key_bits, n, d_perm, d_sorted_keys, nullptr, d_ws, ws_bytes, S(stream));
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_sort_ex(const void* d_keys, uint32_t key_bits,
+                                                              uint32_t skip_bits, uint32_t tile, uint32_t n,
+                                                              uint32_t* d_perm, void* d_sorted_keys, void* d_ws,
+                                                              size_t ws_bytes, hcc_stream stream) {
+    return radix_sort_ex(d_keys, key_bits, skip_bits, tile, n, d_perm, d_sorted_keys, d_ws, ws_bytes, S(stream));
 }
 
 static hcc_status check_trace(hcc_bvh bvh, const hcc_ray* d_rays, uint32_t n, hcc_trace_mode mode, hcc_hit* d_hits,

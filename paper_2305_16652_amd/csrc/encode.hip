@@ -130,6 +130,53 @@ __global__ __launch_bounds__(kBlock) void k_encode_mlhcc(const float4* __restric
     }
 }
 
+// PPC (Section 4.1): each lane walks the BVH in the one forced order shared by all rays
+// (expanding a node tests child 0 then child 1; child 0's subtree first; only met internal
+// children are expanded) and appends one bit per box test until key_bits tests are made.
+// Every expansion uses up to two bits and pushes at most one net entry, so the walk never
+// holds more than key_bits / 2 + 1 <= 33 nodes.
+constexpr uint32_t kPpcStack = 34;
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_encode_ppc(const float4* __restrict__ rays, uint32_t n,
+                                                       const Node* __restrict__ nodes, uint32_t n_int,
+                                                       const float* __restrict__ root_box, uint32_t key_bits,
+                                                       K* __restrict__ keys) {
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+        const float4 a = rays[2 * (size_t)r];
+        const float4 b = rays[2 * (size_t)r + 1];
+        const float ix = 1.0f / b.x, iy = 1.0f / b.y, iz = 1.0f / b.z;
+        K key = 0;
+        float tn;
+        if (n_int == 0) {
+            if (slab(a.x, a.y, a.z, ix, iy, iz, a.w, b.w, root_box[0], root_box[1], root_box[2], root_box[3],
+                     root_box[4], root_box[5], tn))
+                key = (K)1 << (key_bits - 1);
+        } else {
+            uint32_t stack[kPpcStack];
+            uint32_t sp = 0, bits = 0;
+            stack[sp++] = 0;
+            while (sp > 0 && bits < key_bits) {
+                const Node nd = nodes[stack[--sp]];
+                const bool m0 = slab(a.x, a.y, a.z, ix, iy, iz, a.w, b.w, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x,
+                                     nd.b.y, tn);
+                key |= (K)m0 << (key_bits - 1 - bits);
+                ++bits;
+                bool m1 = false;
+                if (bits < key_bits) {
+                    m1 = slab(a.x, a.y, a.z, ix, iy, iz, a.w, b.w, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w,
+                              tn);
+                    key |= (K)m1 << (key_bits - 1 - bits);
+                    ++bits;
+                }
+                if (m1 && nd.d.y < n_int && sp < kPpcStack) stack[sp++] = nd.d.y;
+                if (m0 && nd.d.x < n_int && sp < kPpcStack) stack[sp++] = nd.d.x;
+            }
+        }
+        keys[r] = key;
+    }
+}
+
 inline unsigned grid_for(uint32_t n) {
     // enough blocks to fill 256 CUs several times over; a grid-stride loop covers the rest
     const uint32_t want = (n + kBlock - 1) / kBlock;
@@ -161,6 +208,18 @@ hcc_status encode_mlhcc(const hcc_cut_s* cut, uint32_t key_bits, const hcc_ray* 
         k_encode_mlhcc<uint64_t><<<grid_for(n), kBlock, 0, stream>>>((const float4*)d_rays, n, cut->d_boxes,
                                                                      cut->c_eff, cut->low, key_bits,
                                                                      (uint64_t*)d_keys);
+    HCC_HIP(hipGetLastError());
+    return HCC_OK;
+}
+
+hcc_status encode_ppc(const hcc_bvh_s* bvh, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
+                      hipStream_t stream) {
+    if (key_bits <= 32)
+        k_encode_ppc<uint32_t><<<grid_for(n), kBlock, 0, stream>>>((const float4*)d_rays, n, bvh->nodes, bvh->n_int,
+                                                                   bvh->boxes, key_bits, (uint32_t*)d_keys);
+    else
+        k_encode_ppc<uint64_t><<<grid_for(n), kBlock, 0, stream>>>((const float4*)d_rays, n, bvh->nodes, bvh->n_int,
+                                                                   bvh->boxes, key_bits, (uint64_t*)d_keys);
     HCC_HIP(hipGetLastError());
     return HCC_OK;
 }

@@ -70,7 +70,7 @@ __global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
 
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint32_t n, uint32_t key_bits,
-                                                 uint32_t passes, uint32_t* __restrict__ hist) {
+                                                 uint32_t skip, uint32_t passes, uint32_t* __restrict__ hist) {
     __shared__ uint32_t s_h[kMaxPasses * kRadix];
     const uint32_t t = threadIdx.x;
     for (uint32_t i = t; i < passes * kRadix; i += kBlock) s_h[i] = 0;
@@ -81,8 +81,8 @@ __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uin
         const bool valid = idx < n;
         const K k = valid ? keys[idx] : K(0);
         for (uint32_t p = 0; p < passes; ++p) {
-            const uint32_t nb = min(8u, key_bits - 8u * p);
-            const uint32_t d = (uint32_t)(k >> (8u * p)) & ((1u << nb) - 1u);
+            const uint32_t nb = min(8u, key_bits - skip - 8u * p);
+            const uint32_t d = (uint32_t)(k >> (skip + 8u * p)) & ((1u << nb) - 1u);
             const uint64_t m = match_digit(d, nb, valid);
             if (valid && (m & lt) == 0) atomicAdd(&s_h[p * kRadix + d], (uint32_t)__popcll(m));
         }
@@ -199,15 +199,93 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ kin, c
     }
 }
 
+// Tile-local sort: block b sorts keys [b*T, b*T + T) on its own (T = 256 x kTItems) with
+// the same wavefront-ballot ranking, one LDS exchange per 8-bit pass, and writes the
+// permutation of its tile (global ray indices) and optionally the sorted keys.  Elements past
+// n take the largest key; they sit after every real key of the tile and stay behind them
+// (stable), so the first count outputs are the tile's sorted real keys.
+template <typename K, uint32_t kTItems>
+__global__ __launch_bounds__(kBlock) void k_tile_sort(const K* __restrict__ kin, uint32_t n, uint32_t skip,
+                                                      uint32_t passes, uint32_t key_bits, uint32_t* __restrict__ perm,
+                                                      K* __restrict__ kout) {
+    constexpr uint32_t T = kBlock * kTItems;
+    __shared__ uint32_t s_whist[4 * kRadix];
+    __shared__ uint32_t s_dexcl[kRadix];
+    __shared__ uint32_t s_scan[4];
+    __shared__ K s_keys[T];
+    __shared__ uint32_t s_vals[T];
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    const uint32_t tile0 = blockIdx.x * T;
+    const uint32_t seg = w * (64u * kTItems) + lane;     // this lane's first element in the tile
+    const uint64_t lt = lanemask_lt();
+    uint32_t* wh = s_whist + w * kRadix;
+    K k[kTItems];
+    uint32_t v[kTItems];
+#pragma unroll
+    for (uint32_t i = 0; i < kTItems; ++i) {
+        const uint32_t e = seg + i * 64u;
+        k[i] = tile0 + e < n ? kin[tile0 + e] : ~K(0);
+        v[i] = e;
+    }
+    for (uint32_t p = 0; p < passes; ++p) {
+        const uint32_t shift = skip + 8u * p;
+        const uint32_t nb = min(8u, key_bits - shift);
+        const uint32_t mask = (1u << nb) - 1u;
+        for (uint32_t i = t; i < 4 * kRadix; i += kBlock) s_whist[i] = 0;
+        __syncthreads();
+        uint32_t r[kTItems];
+#pragma unroll
+        for (uint32_t i = 0; i < kTItems; ++i) {
+            const uint32_t d = (uint32_t)(k[i] >> shift) & mask;
+            const uint64_t m = match_digit(d, nb, true);
+            const uint32_t below = (uint32_t)__popcll(m & lt);
+            const uint32_t prev = wh[d];
+            r[i] = prev + below;
+            if (below == 0) wh[d] = prev + (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        const uint32_t c0 = s_whist[t], c1 = s_whist[kRadix + t], c2 = s_whist[2 * kRadix + t],
+                       c3 = s_whist[3 * kRadix + t];
+        s_whist[t] = 0;
+        s_whist[kRadix + t] = c0;
+        s_whist[2 * kRadix + t] = c0 + c1;
+        s_whist[3 * kRadix + t] = c0 + c1 + c2;
+        s_dexcl[t] = block_excl_scan256(c0 + c1 + c2 + c3, s_scan);
+        __syncthreads();
+#pragma unroll
+        for (uint32_t i = 0; i < kTItems; ++i) {
+            const uint32_t d = (uint32_t)(k[i] >> shift) & mask;
+            const uint32_t pos = s_dexcl[d] + wh[d] + r[i];
+            s_keys[pos] = k[i];
+            s_vals[pos] = v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t i = 0; i < kTItems; ++i) {
+            k[i] = s_keys[seg + i * 64u];
+            v[i] = s_vals[seg + i * 64u];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < kTItems; ++i) {
+        const uint32_t e = seg + i * 64u;
+        if (tile0 + e < n) {
+            perm[tile0 + e] = tile0 + v[i];
+            if (kout) kout[tile0 + e] = k[i];
+        }
+    }
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t keys_a, keys_b, vals, hist, counters, lookback, total;
 };
 
-Layout layout(uint32_t n, uint32_t key_bits) {
+Layout layout(uint32_t n, uint32_t key_bits, uint32_t skip = 0) {
     const size_t ks = key_bits <= 32 ? 4 : 8;
-    const uint32_t passes = (key_bits + 7) / 8;
+    const uint32_t passes = (key_bits - skip + 7) / 8;
     const size_t tiles = ((size_t)n + kTile - 1) / kTile;
     Layout L{};
     size_t off = 0;
@@ -222,10 +300,10 @@ Layout layout(uint32_t n, uint32_t key_bits) {
 }
 
 template <typename K>
-hcc_status run_sort(const K* keys, uint32_t key_bits, uint32_t n, uint32_t* perm, K* sorted_keys, char* ws,
-                    hipStream_t stream) {
-    const uint32_t passes = (key_bits + 7) / 8;
-    const Layout L = layout(n, key_bits);
+hcc_status run_sort(const K* keys, uint32_t key_bits, uint32_t skip, uint32_t n, uint32_t* perm, K* sorted_keys,
+                    char* ws, hipStream_t stream) {
+    const uint32_t passes = (key_bits - skip + 7) / 8;
+    const Layout L = layout(n, key_bits, skip);
     const uint32_t tiles = (n + kTile - 1) / kTile;
     uint32_t* hist = (uint32_t*)(ws + L.hist);
     uint32_t* counters = (uint32_t*)(ws + L.counters);
@@ -235,7 +313,7 @@ hcc_status run_sort(const K* keys, uint32_t key_bits, uint32_t n, uint32_t* perm
     k_fill_u32<<<dim3((unsigned)std::min<size_t>(1024, (zero_words + 255) / 256)), dim3(256), 0, stream>>>(
         hist, zero_words, 0u);
     const uint32_t hist_blocks = std::min<uint32_t>(2048u, (n + kBlock - 1) / kBlock);
-    k_hist<K><<<dim3(hist_blocks), dim3(kBlock), 0, stream>>>(keys, n, key_bits, passes, hist);
+    k_hist<K><<<dim3(hist_blocks), dim3(kBlock), 0, stream>>>(keys, n, key_bits, skip, passes, hist);
 
     K* final_keys = sorted_keys ? sorted_keys : (K*)(ws + L.keys_a);
     K* other_keys = (K*)(ws + L.keys_b);
@@ -247,24 +325,41 @@ hcc_status run_sort(const K* keys, uint32_t key_bits, uint32_t n, uint32_t* perm
         K* kout = to_final ? final_keys : other_keys;
         uint32_t* vout = to_final ? perm : vals_tmp;
         const bool last = p + 1 == passes;
-        const uint32_t nb = std::min<uint32_t>(8u, key_bits - 8u * p);
+        const uint32_t shift = skip + 8u * p;
+        const uint32_t nb = std::min<uint32_t>(8u, key_bits - shift);
         const uint32_t* h = hist + p * kRadix;
         uint32_t* lb = lookback + (size_t)p * tiles * kRadix;
         uint32_t* ctr = counters + p;
         dim3 grid(tiles), block(kBlock);
         if (p == 0) {
             if (last && !sorted_keys)
-                k_scatter<K, true, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, 0, nb, h, lb, ctr);
+                k_scatter<K, true, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, h, lb, ctr);
             else
-                k_scatter<K, true, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, 0, nb, h, lb, ctr);
+                k_scatter<K, true, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, h, lb, ctr);
         } else {
             if (last && !sorted_keys)
-                k_scatter<K, false, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, 8u * p, nb, h, lb, ctr);
+                k_scatter<K, false, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, h, lb, ctr);
             else
-                k_scatter<K, false, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, 8u * p, nb, h, lb, ctr);
+                k_scatter<K, false, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, h, lb, ctr);
         }
         kin = kout;
         vin = vout;
+    }
+    HCC_HIP(hipGetLastError());
+    return HCC_OK;
+}
+
+template <typename K>
+hcc_status run_tile_sort(const K* keys, uint32_t key_bits, uint32_t skip, uint32_t tile, uint32_t n, uint32_t* perm,
+                         K* sorted_keys, hipStream_t stream) {
+    const uint32_t passes = (key_bits - skip + 7) / 8;
+    const dim3 grid((n + tile - 1) / tile), block(kBlock);
+    switch (tile) {
+        case 256: k_tile_sort<K, 1><<<grid, block, 0, stream>>>(keys, n, skip, passes, key_bits, perm, sorted_keys); break;
+        case 512: k_tile_sort<K, 2><<<grid, block, 0, stream>>>(keys, n, skip, passes, key_bits, perm, sorted_keys); break;
+        case 1024: k_tile_sort<K, 4><<<grid, block, 0, stream>>>(keys, n, skip, passes, key_bits, perm, sorted_keys); break;
+        case 2048: k_tile_sort<K, 8><<<grid, block, 0, stream>>>(keys, n, skip, passes, key_bits, perm, sorted_keys); break;
+        default: k_tile_sort<K, 16><<<grid, block, 0, stream>>>(keys, n, skip, passes, key_bits, perm, sorted_keys); break;
     }
     HCC_HIP(hipGetLastError());
     return HCC_OK;
@@ -282,20 +377,38 @@ hcc_status fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
     return HCC_OK;
 }
 
-hcc_status radix_sort(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm, void* d_sorted_keys,
-                      const uint32_t* /*d_vals_in*/, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+// skip: the low bits left out of the order; tile: 0 for one sort over all n keys, else the
+// size of the independently sorted groups (256 ... 4096, a power of two).
+hcc_status radix_sort_ex(const void* d_keys, uint32_t key_bits, uint32_t skip, uint32_t tile, uint32_t n,
+                         uint32_t* d_perm, void* d_sorted_keys, void* d_ws, size_t ws_bytes, hipStream_t stream) {
     if (key_bits < 1 || key_bits > 64) return fail(HCC_ERR_INVALID, "hcc_sort: key_bits must be in [1, 64]");
+    if (skip >= key_bits) return fail(HCC_ERR_INVALID, "hcc_sort_ex: skip_bits must be below key_bits");
+    if (tile != 0 && (tile < 256 || tile > 4096 || (tile & (tile - 1)) != 0))
+        return fail(HCC_ERR_INVALID, "hcc_sort_ex: tile must be 0 or a power of two in [256, 4096]");
     if (n >= (1u << 30)) return fail(HCC_ERR_INVALID, "hcc_sort: n must be below 2^30");
     if (n == 0) return HCC_OK;
-    if (!d_keys || !d_perm || !d_ws) return fail(HCC_ERR_INVALID, "hcc_sort: null pointer");
+    if (!d_keys || !d_perm) return fail(HCC_ERR_INVALID, "hcc_sort: null pointer");
+    if (tile != 0) {
+        if (key_bits <= 32)
+            return run_tile_sort<uint32_t>((const uint32_t*)d_keys, key_bits, skip, tile, n, d_perm,
+                                           (uint32_t*)d_sorted_keys, stream);
+        return run_tile_sort<uint64_t>((const uint64_t*)d_keys, key_bits, skip, tile, n, d_perm,
+                                       (uint64_t*)d_sorted_keys, stream);
+    }
+    if (!d_ws) return fail(HCC_ERR_INVALID, "hcc_sort: null workspace");
     if (((uintptr_t)d_ws & 255u) != 0) return fail(HCC_ERR_INVALID, "hcc_sort: workspace must be 256-byte aligned");
-    if (ws_bytes < sort_workspace_bytes(n, key_bits))
+    if (ws_bytes < layout(n, key_bits, skip).total)
         return fail(HCC_ERR_INVALID, "hcc_sort: workspace too small (see hcc_sort_workspace)");
     if (key_bits <= 32)
-        return run_sort<uint32_t>((const uint32_t*)d_keys, key_bits, n, d_perm, (uint32_t*)d_sorted_keys,
+        return run_sort<uint32_t>((const uint32_t*)d_keys, key_bits, skip, n, d_perm, (uint32_t*)d_sorted_keys,
                                   (char*)d_ws, stream);
-    return run_sort<uint64_t>((const uint64_t*)d_keys, key_bits, n, d_perm, (uint64_t*)d_sorted_keys, (char*)d_ws,
-                              stream);
+    return run_sort<uint64_t>((const uint64_t*)d_keys, key_bits, skip, n, d_perm, (uint64_t*)d_sorted_keys,
+                              (char*)d_ws, stream);
+}
+
+hcc_status radix_sort(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm, void* d_sorted_keys,
+                      const uint32_t* /*d_vals_in*/, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+    return radix_sort_ex(d_keys, key_bits, 0, 0, n, d_perm, d_sorted_keys, d_ws, ws_bytes, stream);
 }
 
 }  // namespace hcc
