@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 
 METRIC = "secondary Mrays/s incl. encode+sort vs NoSort; serve p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-NODE_BYTES, TRI_BYTES = 64, 48
+NODE_BYTES, WIDE_NODE_BYTES, TRI_BYTES = 64, 128, 48
 RAY_BYTES, PERM_BYTES, HIT_BYTES = 32, 4, 16
 
 
@@ -646,13 +646,15 @@ def run_drift(H, args):
     return out
 
 
-def measured_traffic():
-    """HBM bytes per trace launch from the committed PMC summary, if it still describes the
-    current trace kernel sources (else None)."""
+def measured_traffic(kernel: str):
+    """HBM bytes per trace launch from the committed PMC summary, if it was taken for this
+    kernel and still describes the current trace kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "trace_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    if kv.get("kernel") != kernel:
+        return None
     src = b"".join(open(os.path.join(ROOT, "paper_2305_16652_amd", "csrc", f), "rb").read()
                    for f in ("trace.hip", "hcc_internal.h"))
     if hashlib.sha256(src).hexdigest()[:16] != kv.get("kernel_sha256_16"):
@@ -661,27 +663,34 @@ def measured_traffic():
 
 
 def roofline_of(H, bvh, rays, perm, R, trace_ms_mean, opts):
-    """Roofline of the trace kernel.  Algorithmic bytes per launch: for each wavefront of 64
-    consecutive rays in trace order and each lockstep iteration, every distinct node (64 B) and
-    triangle (48 B) fetched, plus each ray's record, permutation entry and hit record."""
+    """Roofline of the trace kernel.  Algorithmic bytes per launch: for each wavefront and each
+    lockstep iteration of the launch as configured, every distinct node (64 B BVH2 node, or
+    128 B 4-wide node) and triangle (48 B) fetched, counted by the kernel itself
+    (hcc_trace_count), plus each ray's record, permutation entry and hit record."""
     import torch
-    _, nn, nt, wn, wt = H.trace_stats(bvh, rays, perm)
-    wn_sum = int(wn.to(torch.int64).sum().item())
-    wt_sum = int(wt.to(torch.int64).sum().item())
-    _, _, _, wn0, _ = H.trace_stats(bvh, rays, None)
-    fetch_nosort = int(wn0.to(torch.int64).sum().item())
-    bytes_per_launch = NODE_BYTES * wn_sum + TRI_BYTES * wt_sum + R * (RAY_BYTES + PERM_BYTES + HIT_BYTES)
+    wide = bool(opts.flags & H.TRACE_WIDE)
+    if wide or opts.persistent:
+        _, nodes, tris = H.trace_count(bvh, rays, perm, opts=opts)
+        _, nodes0, _ = H.trace_count(bvh, rays, None, opts=opts)
+    else:   # one-ray-per-lane launch: its own per-wavefront counters
+        def wave_counts(p):
+            _, _, _, wn, wt = H.trace_stats(bvh, rays, p)
+            return int(wn.to(torch.int64).sum().item()), int(wt.to(torch.int64).sum().item())
+        nodes, tris = wave_counts(perm)
+        nodes0, _ = wave_counts(None)
+    node_bytes = WIDE_NODE_BYTES if wide else NODE_BYTES
+    bytes_per_launch = node_bytes * nodes + TRI_BYTES * tris + R * (RAY_BYTES + PERM_BYTES + HIT_BYTES)
     achieved = bytes_per_launch / (trace_ms_mean * 1e-3) / 1e9
+    kernel = "k_trace_wide" if wide else ("k_trace_persistent" if opts.persistent else "k_trace")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
-                    kernel=("k_trace_persistent" if opts.persistent else "k_trace") + "<closest> on HCC-sorted rays",
-                    bytes_per_ray=round(bytes_per_launch / R, 1),
-                    node_fetches_per_ray=round(wn_sum / R, 3), tri_fetches_per_ray=round(wt_sum / R, 3),
-                    node_fetches_per_ray_nosort=round(fetch_nosort / R, 3),
-                    lane_node_visits_per_ray=round(float(nn.to(torch.float64).mean().item()), 2),
-                    lane_tri_tests_per_ray=round(float(nt.to(torch.float64).mean().item()), 2))
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kernel),
+                    kernel=kernel + "<closest> on HCC-sorted rays",
+                    bytes_per_ray=round(bytes_per_launch / R, 1), node_bytes=node_bytes,
+                    node_fetches_per_ray=round(nodes / R, 3), tri_fetches_per_ray=round(tris / R, 3),
+                    node_fetches_per_ray_nosort=round(nodes0 / R, 3))
     log(f"roofline: {achieved:.0f} GB/s of algorithmic traffic ({roofline['frac']:.3f} of HBM peak), "
-        f"wave node fetches/ray {roofline['node_fetches_per_ray']} vs NoSort {roofline['node_fetches_per_ray_nosort']}")
+        f"wave node fetches/ray {roofline['node_fetches_per_ray']} ({node_bytes} B) vs NoSort "
+        f"{roofline['node_fetches_per_ray_nosort']}")
     return roofline
 
 

@@ -96,8 +96,14 @@ typedef struct hcc_trace_opts {
     uint32_t refill;          /* persistent: refill when at least this many lanes are idle, 1..64 (0 = 16) */
     uint32_t chunk;           /* persistent: consecutive rays a wavefront owns at a time, >= 64 (0 = 256) */
     uint32_t waves;           /* persistent: wavefronts launched (0 = 8192) */
-    uint32_t flags;           /* persistent: bit 0 = keep descending while one leaf is postponed */
+    uint32_t flags;           /* HCC_TRACE_SPECULATE | HCC_TRACE_WIDE */
 } hcc_trace_opts;
+
+/* hcc_trace_opts.flags */
+#define HCC_TRACE_SPECULATE 1u  /* persistent BVH2: keep descending while one leaf is postponed */
+#define HCC_TRACE_WIDE 2u       /* traverse the 4-wide nodes (the BVH2 collapsed two levels at a time,
+                                   built by hcc_build_bvh) with persistent wavefronts; refill, chunk
+                                   and waves apply, block, stack and xcd_remap do not */
 
 /* ---------------------------------------------------------------------------------------
  * hcc_build_bvh -- linear BVH over n_tris triangles (Section 3.1: the acceleration structure
@@ -226,6 +232,16 @@ hcc_status hcc_trace(hcc_bvh bvh, const hcc_ray* d_rays, const uint32_t* d_perm,
                      hcc_hit* d_hits, uint8_t* d_occluded, hcc_stream stream);
 hcc_status hcc_trace_ex(hcc_bvh bvh, const hcc_ray* d_rays, const uint32_t* d_perm, uint32_t n, hcc_trace_mode mode,
                         hcc_hit* d_hits, uint8_t* d_occluded, const hcc_trace_opts* opts, hcc_stream stream);
+
+/* hcc_trace_count -- hcc_trace_ex plus fetch counting, for the roofline's algorithmic bytes.
+ * The same launch (persistent or HCC_TRACE_WIDE options only, scratch stack; other options
+ * give HCC_ERR_UNSUPPORTED) also counts, at each lockstep iteration of each wavefront, the
+ * distinct nodes fetched by its stepping lanes, and at each leaf batch the distinct triangles
+ * fetched; it ADDS the totals to d_counts[0] (node fetches) and d_counts[1] (triangle fetches),
+ * device uint64, zeroed by the caller.  Results are those of hcc_trace_ex; it runs slower. */
+hcc_status hcc_trace_count(hcc_bvh bvh, const hcc_ray* d_rays, const uint32_t* d_perm, uint32_t n, hcc_trace_mode mode,
+                           hcc_hit* d_hits, uint8_t* d_occluded, const hcc_trace_opts* opts, uint64_t* d_counts,
+                           hcc_stream stream);
 
 /* Measurement variant of hcc_trace (same results, slower): also counts, per ray, the BVH nodes
  * fetched (d_nodes, nullable) and triangles tested (d_tris, nullable), and per wavefront of 64

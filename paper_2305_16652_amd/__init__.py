@@ -344,6 +344,29 @@ def trace(bvh: BVH, rays: torch.Tensor, perm=None, closest: bool = True, out=Non
     return out
 
 
+TRACE_SPECULATE, TRACE_WIDE = 1, 2
+lib.hcc_trace_count.argtypes = [_H, _P, _P, _U32, C.c_int, _P, _P, C.POINTER(TraceOpts), _P, _P]
+lib.hcc_trace_count.restype = C.c_int
+
+
+def trace_count(bvh: BVH, rays: torch.Tensor, perm=None, closest: bool = True, opts: TraceOpts | None = None,
+                out=None, stream=None):
+    """Trace with a persistent or 4-wide launch that also counts the wavefront-distinct node and
+    triangle fetches.  Returns (results, node_fetches, triangle_fetches)."""
+    _check_rays(rays)
+    n = rays.shape[0]
+    if out is None:
+        out = (torch.empty((n, 4), dtype=torch.float32, device=rays.device) if closest
+               else torch.empty(n, dtype=torch.uint8, device=rays.device))
+    hits, occ = (out, None) if closest else (None, out)
+    counts = torch.zeros(2, dtype=torch.int64, device=rays.device)
+    _check(lib.hcc_trace_count(bvh.handle, _dptr(rays), _dptr(perm), n, CLOSEST if closest else ANY, _dptr(hits),
+                               _dptr(occ), C.byref(opts) if opts is not None else None, _dptr(counts),
+                               _stream(stream)))
+    c = counts.cpu().tolist()
+    return out, int(c[0]), int(c[1])
+
+
 def trace_stats(bvh: BVH, rays: torch.Tensor, perm=None, closest: bool = True, stream=None):
     """Trace with per-ray and per-wavefront fetch counters (measurement only)."""
     _check_rays(rays)
@@ -500,6 +523,7 @@ class Server:
         if self._h is not None and self._h.value and lib is not None:
             lib.hcc_server_destroy(self._h)
             self._h = C.c_void_p(0)
+        self._keep = {}
 
     def __del__(self):
         self.close()

@@ -31,6 +31,9 @@ hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, 
 hcc_status trace_stats(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
                        hcc_hit* hits, uint8_t* occ, uint32_t* cn, uint32_t* ct, uint32_t* wn, uint32_t* wt,
                        hipStream_t s);
+hcc_status trace_count(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
+                       hcc_hit* hits, uint8_t* occ, const hcc_trace_opts& o, unsigned long long* counts,
+                       hipStream_t s);
 hcc_status fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hcc_status batch_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, size_t* bytes);
 hcc_status batch_run(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, const hcc_batch_opts& o,
@@ -396,6 +399,20 @@ __attribute__((visibility("default"))) hcc_status hcc_trace_ex(hcc_bvh bvh, cons
     hcc_trace_opts o{};
     if (opts) o = *opts;
     return trace(bvh, d_rays, d_perm, n, mode == HCC_TRACE_CLOSEST, d_hits, d_occluded, o, S(stream));
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_trace_count(hcc_bvh bvh, const hcc_ray* d_rays,
+                                                                  const uint32_t* d_perm, uint32_t n,
+                                                                  hcc_trace_mode mode, hcc_hit* d_hits,
+                                                                  uint8_t* d_occluded, const hcc_trace_opts* opts,
+                                                                  uint64_t* d_counts, hcc_stream stream) {
+    hcc_status st = check_trace(bvh, d_rays, n, mode, d_hits, d_occluded);
+    if (st != HCC_OK || n == 0) return st;
+    if (!d_counts) return fail(HCC_ERR_INVALID, "hcc_trace_count: null d_counts");
+    hcc_trace_opts o{};
+    if (opts) o = *opts;
+    return trace_count(bvh, d_rays, d_perm, n, mode == HCC_TRACE_CLOSEST, d_hits, d_occluded, o,
+                       (unsigned long long*)d_counts, S(stream));
 }
 
 __attribute__((visibility("default"))) hcc_status hcc_trace(hcc_bvh bvh, const hcc_ray* d_rays, const uint32_t* d_perm,

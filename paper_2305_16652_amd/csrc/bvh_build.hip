@@ -240,6 +240,52 @@ __global__ __launch_bounds__(256) void k_refit(uint32_t n, const uint32_t* __res
     }
 }
 
+// 4-wide nodes: an internal node at even depth (found by walking its parent chain) gathers
+// its children, replacing an internal child by that child's two children.
+__global__ __launch_bounds__(256) void k_wide(uint32_t n_int, const uint32_t* __restrict__ child,
+                                              const uint32_t* __restrict__ parent, const float* __restrict__ boxes,
+                                              Node4* __restrict__ wide) {
+    const uint32_t x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= n_int) return;
+    uint32_t depth = 0;
+    for (uint32_t y = x; parent[y] != kNone; y = parent[y]) ++depth;
+    if (depth & 1u) return;
+    float lo[3][4], hi[3][4];
+    uint32_t ref[4];
+    uint32_t m = 0;
+    auto put = [&](uint32_t u) {
+        const float* b = boxes + 6 * (size_t)u;
+        for (int a = 0; a < 3; ++a) {
+            lo[a][m] = b[a];
+            hi[a][m] = b[3 + a];
+        }
+        ref[m++] = u >= n_int ? (kWideLeaf | (u - n_int)) : u;
+    };
+    for (int c = 0; c < 2; ++c) {
+        const uint32_t u = child[2 * x + c];
+        if (u >= n_int) {
+            put(u);
+        } else {
+            put(child[2 * u]);
+            put(child[2 * u + 1]);
+        }
+    }
+    for (; m < 4; ++m) {
+        for (int a = 0; a < 3; ++a) lo[a][m] = hi[a][m] = 0.0f;
+        ref[m] = kWideEmpty;
+    }
+    Node4 w;
+    w.lox = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
+    w.loy = make_float4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
+    w.loz = make_float4(lo[2][0], lo[2][1], lo[2][2], lo[2][3]);
+    w.hix = make_float4(hi[0][0], hi[0][1], hi[0][2], hi[0][3]);
+    w.hiy = make_float4(hi[1][0], hi[1][1], hi[1][2], hi[1][3]);
+    w.hiz = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
+    w.ref = make_uint4(ref[0], ref[1], ref[2], ref[3]);
+    w.pad = make_uint4(0, 0, 0, 0);
+    wide[x] = w;
+}
+
 __global__ void k_fill(uint32_t* p, size_t n, uint32_t v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -270,6 +316,7 @@ void free_bvh(hcc_bvh_s* b) {
     if (!b) return;
     const Allocator& A = b->alloc;
     A.put(b->nodes, nullptr);
+    A.put(b->wnodes, nullptr);
     A.put(b->tris, nullptr);
     A.put(b->boxes, nullptr);
     A.put(b->had, nullptr);
@@ -299,6 +346,7 @@ hcc_status build_bvh(const float* d_tris, uint32_t n, hipStream_t stream, hcc_bv
         }                           \
     } while (0)
     TRY(dalloc(A, stream, &b->nodes, b->n_int, bytes));
+    TRY(dalloc(A, stream, &b->wnodes, b->n_int, bytes));
     TRY(dalloc(A, stream, &b->tris, n, bytes));
     TRY(dalloc(A, stream, &b->boxes, nn * 6, bytes));
     TRY(dalloc(A, stream, &b->had, nn, bytes));
@@ -358,6 +406,8 @@ hcc_status build_bvh(const float* d_tris, uint32_t n, hipStream_t stream, hcc_bv
     if (b->n_int > 0)
         k_refit<true><<<blocks_for(n), 256, 0, stream>>>(n, b->child, b->parent, flags, b->boxes, b->had, b->nodes,
                                                         0.125);
+    if (b->n_int > 0)
+        k_wide<<<blocks_for(b->n_int), 256, 0, stream>>>(b->n_int, b->child, b->parent, b->boxes, b->wnodes);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(b->scene_box, d_box, 6 * sizeof(float), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);

@@ -24,6 +24,20 @@ struct alignas(64) Node {
     uint4 d;
 };
 
+// 4-wide node for traversal, 128 bytes (two cache lines): the BVH2 collapsed two levels at a
+// time.  Node X (a BVH2 internal node at even depth) holds X's children, with each internal
+// child replaced by its own two children (child 0's expansion first).  Slot j: box
+// (lox[j], loy[j], loz[j]) - (hix[j], hiy[j], hiz[j]); ref[j] = BVH2 id of an internal child
+// (whose 4-wide node is at the same index), kWideLeaf | triangle slot, or kWideEmpty.
+struct alignas(64) Node4 {
+    float4 lox, loy, loz, hix, hiy, hiz;
+    uint4 ref;
+    uint4 pad;
+};
+constexpr uint32_t kWideLeaf = 0x80000000u;
+constexpr uint32_t kWideEmpty = 0xFFFFFFFFu;
+constexpr int kWideStack = 96;    // 3 pushes per level, at most 32 levels of 4-wide nodes
+
 // Triangle in Morton order, 48 bytes: v0, e1 = v1 - v0, e2 = v2 - v0 (float32,
 // rounded exactly as the Moller-Trumbore test computes them), original index.
 //   p = (v0.x, v0.y, v0.z, e1.x)  q = (e1.y, e1.z, e2.x, e2.y)  r = (e2.z, prim bits, 0, 0)
@@ -137,6 +151,7 @@ struct hcc_bvh_s {
     uint32_t n = 0;                 // triangles
     uint32_t n_int = 0;             // internal nodes = n - 1
     hcc::Node* nodes = nullptr;     // n_int
+    hcc::Node4* wnodes = nullptr;   // n_int slots, filled at even-depth internal ids
     hcc::Tri* tris = nullptr;       // n (Morton order)
     float* boxes = nullptr;         // (2n-1) x 6
     double* had = nullptr;          // 2n-1

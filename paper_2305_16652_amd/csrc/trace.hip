@@ -173,6 +173,31 @@ __global__ __launch_bounds__(kBlock) void k_trace(const Node* __restrict__ nodes
     }
 }
 
+// Distinct values of x among the lanes with `on` set; every lane gets the count.  Called
+// with the whole wavefront active (measurement only).
+__device__ __forceinline__ uint32_t wave_distinct_on(uint32_t x, bool on) {
+    uint64_t rem = __ballot(on);
+    uint32_t count = 0;
+    while (rem) {
+        const int src = __ffsll((unsigned long long)rem) - 1;
+        const uint32_t id = __shfl(x, src, 64);
+        rem &= ~__ballot(on && x == id);
+        ++count;
+    }
+    return count;
+}
+
+__device__ __forceinline__ void cswap(float& ka, uint32_t& ia, float& kb, uint32_t& ib) {
+    if (kb < ka) {
+        const float k = ka;
+        ka = kb;
+        kb = k;
+        const uint32_t i = ia;
+        ia = ib;
+        ib = i;
+    }
+}
+
 __device__ __forceinline__ uint64_t lanes_below() {
     const uint32_t lane = __lane_id();
     return lane == 0 ? 0ull : (~0ull >> (64u - lane));
@@ -190,12 +215,13 @@ __device__ __forceinline__ uint64_t lanes_below() {
 // code runs with most lanes active instead of in a branch taken by a few.  Every wave-level
 // decision is taken on ballots (uniform values); the loop ends once the wavefront's chunks
 // are exhausted and all lanes are idle.
-template <bool kClosest, int kStack, bool kSpec>
+template <bool kClosest, int kStack, bool kSpec, bool kStats>
 __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict__ nodes, const Tri* __restrict__ tris,
                                                          uint32_t n_int, const float4* __restrict__ rays,
                                                          const uint32_t* __restrict__ perm, uint32_t n,
                                                          float4* __restrict__ hits, uint8_t* __restrict__ occ,
-                                                         uint32_t refill, uint32_t chunk) {
+                                                         uint32_t refill, uint32_t chunk,
+                                                         unsigned long long* __restrict__ counts) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     __shared__ uint32_t s_stack[lds_entries<kStack>() * 64];
     const uint32_t nchunks = (n + chunk - 1) / chunk;
@@ -212,6 +238,7 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
     float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0, tmin = 0, tmax = 0;
     float best_t = 0, best_u = 0, best_v = 0;
     bool found = false;
+    uint32_t c_nodes = 0, c_tris = 0;
 
     auto test_tri = [&](uint32_t slot) {
         const Tri tr = tris[slot];
@@ -266,7 +293,9 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
 
         // ---- one node step for lanes with a node and room for two more postponed leaves
         // (kSpec: a lane keeps descending while it holds one postponed leaf)
-        if (has && node != kNone && (kSpec ? pend1 == kNone : pend0 == kNone)) {
+        const bool step = has && node != kNone && (kSpec ? pend1 == kNone : pend0 == kNone);
+        if (kStats) c_nodes += wave_distinct_on(node, step);
+        if (step) {
             const Node nd = nodes[node];
             const float lim = kClosest ? best_t : tmax;
             float tn0, tn1;
@@ -312,6 +341,12 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
         const uint64_t waiting = __ballot(has && pend0 != kNone && !can_step);
         const uint64_t stepping = __ballot(can_step);
         if (waiting != 0 && (2 * __popcll(waiting) >= __popcll(busy) || stepping == 0)) {
+            if (kStats) {
+                const bool mine = has && pend0 != kNone;
+                c_tris += wave_distinct_on(pend0, mine);
+                c_tris += wave_distinct_on(pend1, mine && pend1 != kNone);
+                c_tris += wave_distinct_on(pend2, kSpec && mine && pend2 != kNone);
+            }
             if (has && pend0 != kNone) {
                 test_tri(pend0);
                 if (pend1 != kNone && (kClosest || !found)) test_tri(pend1);
@@ -330,6 +365,177 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
                 occ[rid] = found ? 1 : 0;
             has = false;
         }
+    }
+    if (kStats && __lane_id() == 0) {
+        atomicAdd(counts, (unsigned long long)c_nodes);
+        atomicAdd(counts + 1, (unsigned long long)c_tris);
+    }
+}
+
+// Persistent wavefronts over the 4-wide nodes (same refill and batched-leaf scheme as
+// k_trace_persistent).  A node step tests the four child boxes, records the hit leaf slots of
+// the node as pending (node index + 4-bit mask), orders the hit internal children by entry
+// distance with a 5-comparator network, descends into the nearest and pushes the others
+// farthest first.  kStats: counts, per lockstep iteration, the distinct 4-wide nodes fetched
+// by the stepping lanes and the distinct triangles fetched by a leaf batch (summed over the
+// wavefront into counts[0] and counts[1]).
+template <bool kClosest, bool kStats>
+__global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn, const Tri* __restrict__ tris,
+                                                   uint32_t n_int, const float4* __restrict__ rays,
+                                                   const uint32_t* __restrict__ perm, uint32_t n,
+                                                   float4* __restrict__ hits, uint8_t* __restrict__ occ,
+                                                   uint32_t refill, uint32_t chunk,
+                                                   unsigned long long* __restrict__ counts) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    const uint32_t nchunks = (n + chunk - 1) / chunk;
+    uint32_t cidx = blockIdx.x;
+    if (cidx >= nchunks) return;
+    uint32_t next = cidx * chunk;
+    uint32_t end = min(next + chunk, n);
+    const uint64_t below = lanes_below();
+    uint32_t stack[kWideStack];
+    bool has = false;
+    uint32_t rid = 0, node = kNone, sp = 0, best_prim = kMissPrim;
+    uint32_t pnode = 0, pmask = 0;
+    float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0, tmin = 0, tmax = 0;
+    float best_t = 0, best_u = 0, best_v = 0;
+    bool found = false;
+    uint32_t c_nodes = 0, c_tris = 0;
+
+    auto test_tri = [&](uint32_t slot) {
+        const Tri tr = tris[slot];
+        const uint32_t prim = __float_as_uint(tr.r.y);
+        float t, u, v;
+        if (tri_test(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v)) {
+            if (!kClosest) {
+                found = true;
+            } else if (t < best_t || (t == best_t && prim < best_prim)) {
+                best_t = t; best_u = u; best_v = v; best_prim = prim;
+                found = true;
+            }
+        }
+    };
+
+    while (true) {
+        // ---- refill idle lanes from the current chunk
+        const uint64_t idle = __ballot(!has);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (nidle >= refill) {
+            while (next >= end && cidx < nchunks) {
+                cidx += gridDim.x;
+                if (cidx < nchunks) {
+                    next = cidx * chunk;
+                    end = min(next + chunk, n);
+                }
+            }
+            if (next < end) {
+                const uint32_t k = next + (uint32_t)__popcll(idle & below);
+                if (!has && k < end) {
+                    rid = perm ? perm[k] : k;
+                    if (rid < n) {
+                        const float4 ra = rays[2 * (size_t)rid];
+                        const float4 rb = rays[2 * (size_t)rid + 1];
+                        ox = ra.x; oy = ra.y; oz = ra.z; tmin = ra.w;
+                        dx = rb.x; dy = rb.y; dz = rb.z; tmax = rb.w;
+                        ix = 1.0f / dx; iy = 1.0f / dy; iz = 1.0f / dz;
+                        best_t = tmax; best_u = 0.0f; best_v = 0.0f;
+                        best_prim = kMissPrim;
+                        found = false;
+                        node = 0;
+                        sp = 0;
+                        pmask = 0;
+                        has = true;
+                    }
+                }
+                next = min(next + nidle, end);
+            } else if (nidle == 64) {
+                break;
+            }
+        }
+
+        // ---- one 4-wide node step for lanes with a node and no pending leaves
+        const bool step = has && node != kNone && pmask == 0;
+        if (kStats) c_nodes += wave_distinct_on(node, step);
+        if (step) {
+            const Node4 nd = wn[node];
+            const float lim = kClosest ? best_t : tmax;
+            const uint4 r = nd.ref;
+            float t0, t1, t2, t3;
+            const bool h0 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.x, nd.loy.x, nd.loz.x, nd.hix.x, nd.hiy.x,
+                                 nd.hiz.x, t0) && r.x != kWideEmpty;
+            const bool h1 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.y, nd.loy.y, nd.loz.y, nd.hix.y, nd.hiy.y,
+                                 nd.hiz.y, t1) && r.y != kWideEmpty;
+            const bool h2 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.z, nd.loy.z, nd.loz.z, nd.hix.z, nd.hiy.z,
+                                 nd.hiz.z, t2) && r.z != kWideEmpty;
+            const bool h3 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.w, nd.loy.w, nd.loz.w, nd.hix.w, nd.hiy.w,
+                                 nd.hiz.w, t3) && r.w != kWideEmpty;
+            const bool l0 = h0 && (r.x & kWideLeaf), l1 = h1 && (r.y & kWideLeaf);
+            const bool l2 = h2 && (r.z & kWideLeaf), l3 = h3 && (r.w & kWideLeaf);
+            const uint32_t lm = (l0 ? 1u : 0u) | (l1 ? 2u : 0u) | (l2 ? 4u : 0u) | (l3 ? 8u : 0u);
+            if (lm) {
+                pnode = node;
+                pmask = lm;
+            }
+            // hit internal children, nearest first (a missed or leaf slot sorts last as kNone)
+            float k0 = (h0 && !l0) ? t0 : INFINITY, k1 = (h1 && !l1) ? t1 : INFINITY;
+            float k2 = (h2 && !l2) ? t2 : INFINITY, k3 = (h3 && !l3) ? t3 : INFINITY;
+            uint32_t i0 = (h0 && !l0) ? r.x : kNone, i1 = (h1 && !l1) ? r.y : kNone;
+            uint32_t i2 = (h2 && !l2) ? r.z : kNone, i3 = (h3 && !l3) ? r.w : kNone;
+            cswap(k0, i0, k1, i1);
+            cswap(k2, i2, k3, i3);
+            cswap(k0, i0, k2, i2);
+            cswap(k1, i1, k3, i3);
+            cswap(k1, i1, k2, i2);
+            if (i3 < n_int && sp < kWideStack) stack[sp++] = i3;
+            if (i2 < n_int && sp < kWideStack) stack[sp++] = i2;
+            if (i1 < n_int && sp < kWideStack) stack[sp++] = i1;
+            if (i0 < n_int) {
+                node = i0;
+            } else if (sp == 0) {
+                node = kNone;
+            } else {
+                node = stack[--sp];
+            }
+        }
+
+        // ---- batched leaf tests
+        const uint64_t busy = __ballot(has);
+        const bool can_step = has && node != kNone && pmask == 0;
+        const uint64_t waiting = __ballot(has && pmask != 0);
+        const uint64_t stepping = __ballot(can_step);
+        if (waiting != 0 && (2 * __popcll(waiting) >= __popcll(busy) || stepping == 0)) {
+            const bool mine = has && pmask != 0;
+            uint4 r = make_uint4(kNone, kNone, kNone, kNone);
+            if (mine) r = wn[pnode].ref;
+            if (kStats) {
+                c_tris += wave_distinct_on(r.x, mine && (pmask & 1u));
+                c_tris += wave_distinct_on(r.y, mine && (pmask & 2u));
+                c_tris += wave_distinct_on(r.z, mine && (pmask & 4u));
+                c_tris += wave_distinct_on(r.w, mine && (pmask & 8u));
+            }
+            if (mine) {
+                if (pmask & 1u) test_tri(r.x & ~kWideLeaf);
+                if ((pmask & 2u) && (kClosest || !found)) test_tri(r.y & ~kWideLeaf);
+                if ((pmask & 4u) && (kClosest || !found)) test_tri(r.z & ~kWideLeaf);
+                if ((pmask & 8u) && (kClosest || !found)) test_tri(r.w & ~kWideLeaf);
+                pmask = 0;
+                if (!kClosest && found) node = kNone;
+            }
+        }
+
+        // ---- finished rays
+        if (has && node == kNone && pmask == 0) {
+            if (kClosest)
+                hits[rid] = make_float4(found ? best_t : INFINITY, __uint_as_float(found ? best_prim : kMissPrim),
+                                        found ? best_u : 0.0f, found ? best_v : 0.0f);
+            else
+                occ[rid] = found ? 1 : 0;
+            has = false;
+        }
+    }
+    if (kStats && __lane_id() == 0) {
+        atomicAdd(counts, (unsigned long long)c_nodes);
+        atomicAdd(counts + 1, (unsigned long long)c_tris);
     }
 }
 
@@ -363,48 +569,82 @@ hcc_status dispatch_stack(uint32_t stack, uint32_t block, const hcc_bvh_s* b, co
     return HCC_OK;
 }
 
+
+// Persistent launches (BVH2 or 4-wide), optionally counting wavefront-distinct fetches.
+template <bool kStats>
+hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
+                            hcc_hit* hits, uint8_t* occ, const hcc_trace_opts& o, unsigned long long* counts,
+                            hipStream_t s) {
+    const uint32_t refill = std::min<uint32_t>(64u, std::max<uint32_t>(1u, o.refill ? o.refill : 16u));
+    const uint32_t chunk = std::max<uint32_t>(64u, o.chunk ? o.chunk : 256u);
+    const uint32_t nchunks = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
+    const uint32_t waves = std::min<uint32_t>(nchunks, o.waves ? o.waves : 8192u);
+    const float4* r = (const float4*)rays;
+    float4* h = (float4*)hits;
+    if (o.flags & HCC_TRACE_WIDE) {
+        if (closest)
+            k_trace_wide<true, kStats><<<waves, 64, 0, s>>>(b->wnodes, b->tris, b->n_int, r, perm, n, h, occ, refill,
+                                                            chunk, counts);
+        else
+            k_trace_wide<false, kStats><<<waves, 64, 0, s>>>(b->wnodes, b->tris, b->n_int, r, perm, n, h, occ, refill,
+                                                             chunk, counts);
+        HCC_HIP(hipGetLastError());
+        return HCC_OK;
+    }
+#define HCC_PERSIST(CL, STK)                                                                                  \
+    do {                                                                                                      \
+        if (o.flags & HCC_TRACE_SPECULATE)                                                                    \
+            k_trace_persistent<CL, STK, true, kStats><<<waves, 64, 0, s>>>(b->nodes, b->tris, b->n_int, r, perm, \
+                                                                           n, h, occ, refill, chunk, counts);  \
+        else                                                                                                  \
+            k_trace_persistent<CL, STK, false, kStats><<<waves, 64, 0, s>>>(b->nodes, b->tris, b->n_int, r,      \
+                                                                            perm, n, h, occ, refill, chunk,     \
+                                                                            counts);                            \
+    } while (0)
+    if (kStats && o.stack != HCC_STACK_SCRATCH)
+        return fail(HCC_ERR_UNSUPPORTED, "hcc_trace_count: counting runs with the scratch stack only");
+    switch (o.stack) {
+        case HCC_STACK_SCRATCH:
+            if (closest) HCC_PERSIST(true, HCC_STACK_SCRATCH); else HCC_PERSIST(false, HCC_STACK_SCRATCH);
+            break;
+        case HCC_STACK_LDS:
+            if constexpr (!kStats) {
+                if (closest) HCC_PERSIST(true, HCC_STACK_LDS); else HCC_PERSIST(false, HCC_STACK_LDS);
+            }
+            break;
+        case HCC_STACK_SHORT:
+            if constexpr (!kStats) {
+                if (closest) HCC_PERSIST(true, HCC_STACK_SHORT); else HCC_PERSIST(false, HCC_STACK_SHORT);
+            }
+            break;
+        default:
+            return fail(HCC_ERR_INVALID, "hcc_trace: unknown stack mode");
+    }
+#undef HCC_PERSIST
+    HCC_HIP(hipGetLastError());
+    return HCC_OK;
+}
+
 }  // namespace
 
 hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
                  hcc_hit* hits, uint8_t* occ, const hcc_trace_opts& o, hipStream_t s) {
-    if (o.persistent && b->n_int > 0) {
-        const uint32_t refill = std::min<uint32_t>(64u, std::max<uint32_t>(1u, o.refill ? o.refill : 16u));
-        const uint32_t chunk = std::max<uint32_t>(64u, o.chunk ? o.chunk : 256u);
-        const uint32_t nchunks = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
-        const uint32_t waves = std::min<uint32_t>(nchunks, o.waves ? o.waves : 8192u);
-        const float4* r = (const float4*)rays;
-#define HCC_PERSIST(CL, STK)                                                                                  \
-    do {                                                                                                      \
-        if (o.flags & 1u)                                                                                  \
-            k_trace_persistent<CL, STK, true><<<waves, 64, 0, s>>>(b->nodes, b->tris, b->n_int, r, perm, n,     \
-                                                                   (float4*)hits, occ, refill, chunk);        \
-        else                                                                                                  \
-            k_trace_persistent<CL, STK, false><<<waves, 64, 0, s>>>(b->nodes, b->tris, b->n_int, r, perm, n,    \
-                                                                    (float4*)hits, occ, refill, chunk);       \
-    } while (0)
-        switch (o.stack) {
-            case HCC_STACK_SCRATCH:
-                if (closest) HCC_PERSIST(true, HCC_STACK_SCRATCH); else HCC_PERSIST(false, HCC_STACK_SCRATCH);
-                break;
-            case HCC_STACK_LDS:
-                if (closest) HCC_PERSIST(true, HCC_STACK_LDS); else HCC_PERSIST(false, HCC_STACK_LDS);
-                break;
-            case HCC_STACK_SHORT:
-                if (closest) HCC_PERSIST(true, HCC_STACK_SHORT); else HCC_PERSIST(false, HCC_STACK_SHORT);
-                break;
-            default:
-                return fail(HCC_ERR_INVALID, "hcc_trace: unknown stack mode");
-        }
-#undef HCC_PERSIST
-        HCC_HIP(hipGetLastError());
-        return HCC_OK;
-    }
+    if ((o.persistent || (o.flags & HCC_TRACE_WIDE)) && b->n_int > 0)
+        return trace_persistent<false>(b, rays, perm, n, closest, hits, occ, o, nullptr, s);
     const uint32_t block = o.block ? o.block : 64;
     if (closest)
         return dispatch_stack<true, false>(o.stack, block, b, rays, perm, n, hits, occ, o.xcd_remap, nullptr, nullptr,
                                            nullptr, nullptr, s);
     return dispatch_stack<false, false>(o.stack, block, b, rays, perm, n, hits, occ, o.xcd_remap, nullptr, nullptr,
                                         nullptr, nullptr, s);
+}
+
+hcc_status trace_count(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
+                       hcc_hit* hits, uint8_t* occ, const hcc_trace_opts& o, unsigned long long* counts,
+                       hipStream_t s) {
+    if (!(o.persistent || (o.flags & HCC_TRACE_WIDE)) || b->n_int == 0)
+        return fail(HCC_ERR_UNSUPPORTED, "hcc_trace_count: counts the persistent launches only");
+    return trace_persistent<true>(b, rays, perm, n, closest, hits, occ, o, counts, s);
 }
 
 hcc_status trace_stats(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,

@@ -171,7 +171,11 @@ def test_sort_empty(H):
 OPTS = [(128, 1, 0, 0, 0, 0, 0), (64, 1, 1, 0, 0, 0, 0), (256, 1, 0, 0, 0, 0, 0), (64, 0, 0, 0, 0, 0, 0),
         (128, 0, 1, 0, 0, 0, 0), (256, 2, 0, 0, 0, 0, 0), (128, 2, 1, 0, 0, 0, 0),
         (0, 0, 0, 1, 16, 256, 0), (0, 1, 0, 1, 1, 64, 3), (0, 2, 0, 1, 64, 1000, 7), (0, 0, 0, 1, 33, 4096, 1),
-        (0, 0, 0, 1, 32, 64, 0, 1), (0, 2, 0, 1, 5, 128, 11, 1)]
+        (0, 0, 0, 1, 32, 64, 0, 1), (0, 2, 0, 1, 5, 128, 11, 1),
+        # 4-wide nodes (flags bit 1), with and without the persistent field, odd chunk / refill / waves
+        (0, 0, 0, 1, 16, 256, 0, 2), (64, 1, 1, 0, 32, 64, 0, 2), (0, 0, 0, 1, 1, 64, 3, 2),
+        (0, 2, 0, 1, 64, 1000, 7, 3)]
+WIDE = (0, 0, 0, 1, 32, 64, 0, 2)
 
 
 @pytest.mark.parametrize("opt", OPTS)
@@ -223,6 +227,23 @@ def test_trace_stats_same_results(H, gpu_bvh, tiny):
     assert_any(occ.cpu().numpy(), O.trace(tiny["ob"], tiny["shadow"], closest=False))
 
 
+@pytest.mark.parametrize("opt", [(0, 0, 0, 1, 32, 64, 0, 1), (0, 0, 0, 1, 16, 256, 0, 0), WIDE,
+                                 (0, 0, 0, 1, 1, 64, 5, 2)])
+def test_trace_count_same_results(H, gpu_bvh, tiny, opt):
+    o = H.TraceOpts(*opt)
+    for name, closest in (("secondary", True), ("shadow", False)):
+        d = _dev(tiny[name])
+        n = d.shape[0]
+        plain = H.trace(gpu_bvh, d, closest=closest, opts=o).cpu().numpy()
+        out, nodes, tris = H.trace_count(gpu_bvh, d, closest=closest, opts=o)
+        assert np.array_equal(out.cpu().numpy().view(np.uint8), plain.view(np.uint8))
+        again = H.trace_count(gpu_bvh, d, closest=closest, opts=o)
+        assert (nodes, tris) == again[1:]                 # static chunk assignment: deterministic counts
+        assert n / 64 <= nodes and 0 < tris <= nodes * 64 * 4
+    with pytest.raises(H.HCCError):
+        H.trace_count(gpu_bvh, _dev(tiny["secondary"]), opts=H.TraceOpts(64, 0, 0, 0, 0, 0, 0, 0))
+
+
 # ----------------------------------------------------------------------------- edge cases
 
 def test_single_and_two_triangle_scenes(H):
@@ -237,9 +258,10 @@ def test_single_and_two_triangle_scenes(H):
             assert np.array_equal(H.select_cut(b, c).export()[0], O.select_cut(ob, O.had(ob), c))
         rays = np.array([[0.2, 0.2, 0, 0, 0, 0, 1, np.inf], [2, 2, 0, 0, 0, 0, 1, np.inf],
                          [0.2, 0.2, 0, 1.5, 0, 0, 1, np.inf], [0.2, 0.2, 0, 0, 0, 0, 1, 0.5]], np.float32)
-        hits = H.trace(b, _dev(rays)).cpu().numpy()
-        assert_closest(hits, O.trace(ob, rays), rays, tris)
-        assert_any(H.trace(b, _dev(rays), closest=False).cpu().numpy(), O.trace(ob, rays, closest=False))
+        for o in (None, H.TraceOpts(*WIDE)):
+            hits = H.trace(b, _dev(rays), opts=o).cpu().numpy()
+            assert_closest(hits, O.trace(ob, rays), rays, tris)
+            assert_any(H.trace(b, _dev(rays), closest=False, opts=o).cpu().numpy(), O.trace(ob, rays, closest=False))
 
 
 def test_degenerate_rays(H, gpu_bvh, tiny):
@@ -259,8 +281,10 @@ def test_degenerate_rays(H, gpu_bvh, tiny):
     rays[4::7, 7] = 0.0          # zero-length segments
     rays[5::11, 4:7] = 0.0       # zero direction
     tris = tiny["spec"].tris
-    assert_closest(H.trace(gpu_bvh, _dev(rays)).cpu().numpy(), O.trace(tiny["ob"], rays), rays, tris)
-    assert_any(H.trace(gpu_bvh, _dev(rays), closest=False).cpu().numpy(), O.trace(tiny["ob"], rays, closest=False))
+    for o in (None, H.TraceOpts(*WIDE), H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 1)):
+        assert_closest(H.trace(gpu_bvh, _dev(rays), opts=o).cpu().numpy(), O.trace(tiny["ob"], rays), rays, tris)
+        assert_any(H.trace(gpu_bvh, _dev(rays), closest=False, opts=o).cpu().numpy(),
+                   O.trace(tiny["ob"], rays, closest=False))
     cut = H.select_cut(gpu_bvh, 64)
     cb = O.cut_boxes(tiny["ob"], O.select_cut(tiny["ob"], tiny["had"], 64))
     for kb in (32, 64):
