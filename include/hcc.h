@@ -273,7 +273,7 @@ typedef struct hcc_batch_opts {
     uint32_t chunk;           /* rays per trace item (>= 64; 0 = 256) */
     uint32_t refill;          /* lane refill threshold 1..64 (0 = 32) */
     uint32_t waves;           /* persistent wavefronts launched (0 = 8192) */
-    uint32_t reserved;        /* must be 0 */
+    uint32_t flags;           /* HCC_TRACE_WIDE: trace over the 4-wide nodes; other bits must be 0 */
 } hcc_batch_opts;
 
 /* Device workspace needed by hcc_batch_run for this batch list, key mode and key length. */

@@ -398,8 +398,8 @@ class BatchDesc(C.Structure):
 
 
 class BatchOpts(C.Structure):
-    """hcc_batch_opts: chunk (rays per trace item), refill, waves (0 = default)."""
-    _fields_ = [("chunk", C.c_uint32), ("refill", C.c_uint32), ("waves", C.c_uint32), ("reserved", C.c_uint32)]
+    """hcc_batch_opts: chunk (rays per trace item), refill, waves (0 = default), flags (TRACE_WIDE)."""
+    _fields_ = [("chunk", C.c_uint32), ("refill", C.c_uint32), ("waves", C.c_uint32), ("flags", C.c_uint32)]
 
 
 lib.hcc_batch_workspace.argtypes = [C.c_void_p, C.c_uint32, C.c_int, C.c_uint32, C.POINTER(C.c_size_t)]

@@ -482,7 +482,7 @@ __attribute__((visibility("default"))) hcc_status hcc_batch_run(const hcc_batch_
     if (!d_ws || ((uintptr_t)d_ws & 255u)) return fail(HCC_ERR_INVALID, "hcc_batch_run: workspace must be 256-byte aligned");
     hcc_batch_opts o{};
     if (opts) o = *opts;
-    if (o.reserved != 0) return fail(HCC_ERR_INVALID, "hcc_batch_run: opts.reserved must be 0");
+    if ((o.flags & ~HCC_TRACE_WIDE) != 0) return fail(HCC_ERR_INVALID, "hcc_batch_run: unknown opts.flags bits");
     return batch_run(batches, nb, mode, key_bits, o, d_ws, ws_bytes, S(stream));
 }
 

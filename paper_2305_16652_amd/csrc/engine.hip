@@ -24,6 +24,7 @@ namespace hcc {
 
 struct EngScene {
     const Node* nodes;
+    const Node4* wnodes;
     const Tri* tris;
     const CutBox* cut;
     uint32_t n_int;
@@ -375,7 +376,133 @@ __device__ void trace_range(const EngScene& sc, const EngBatch& bt, const uint32
     }
 }
 
-template <typename K>
+__device__ __forceinline__ void cswap4(float& ka, uint32_t& ia, float& kb, uint32_t& ib) {
+    if (kb < ka) {
+        const float k = ka;
+        ka = kb;
+        kb = k;
+        const uint32_t i = ia;
+        ia = ib;
+        ib = i;
+    }
+}
+
+// ---- T over the 4-wide nodes (the persistent 4-wide trace kernel's step, for rays
+// [begin, end) of the batch's order; the scene has at least one internal node)
+__device__ void trace_range_wide(const EngScene& sc, const EngBatch& bt, const uint32_t* perm, uint32_t begin,
+                                 uint32_t end, uint32_t refill) {
+    const bool closest = bt.closest != 0;
+    const uint64_t below = below_mask();
+    uint32_t stk[kWideStack];
+    uint32_t next = begin;
+    bool has = false;
+    uint32_t rid = 0, node = kNone, sp = 0, best_prim = kMissPrim, pnode = 0, pmask = 0;
+    float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0, tmin = 0, tmax = 0;
+    float best_t = 0, best_u = 0, best_v = 0;
+    bool found = false;
+    const uint32_t n_int = sc.n_int;
+    auto test_tri = [&](uint32_t slot) {
+        const Tri tr = sc.tris[slot];
+        const uint32_t prim = __float_as_uint(tr.r.y);
+        float t, u, v;
+        if (tri_test(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v)) {
+            if (!closest) {
+                found = true;
+            } else if (t < best_t || (t == best_t && prim < best_prim)) {
+                best_t = t; best_u = u; best_v = v; best_prim = prim;
+                found = true;
+            }
+        }
+    };
+    while (true) {
+        const uint64_t idle = __ballot(!has);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (nidle >= refill || nidle == 64) {
+            if (next < end) {
+                const uint32_t k = next + (uint32_t)__popcll(idle & below);
+                if (!has && k < end) {
+                    rid = perm ? perm[k] : k;
+                    if (rid < bt.n) {
+                        const float4 ra = bt.rays[2 * (size_t)rid], rb = bt.rays[2 * (size_t)rid + 1];
+                        ox = ra.x; oy = ra.y; oz = ra.z; tmin = ra.w;
+                        dx = rb.x; dy = rb.y; dz = rb.z; tmax = rb.w;
+                        ix = 1.0f / dx; iy = 1.0f / dy; iz = 1.0f / dz;
+                        best_t = tmax; best_u = 0.0f; best_v = 0.0f; best_prim = kMissPrim;
+                        found = false;
+                        sp = 0;
+                        pmask = 0;
+                        node = 0;
+                        has = true;
+                    }
+                }
+                next = min(next + nidle, end);
+            } else if (nidle == 64) {
+                break;
+            }
+        }
+        if (has && node != kNone && pmask == 0) {
+            const Node4 nd = sc.wnodes[node];
+            const float lim = closest ? best_t : tmax;
+            const uint4 r = nd.ref;
+            float t0, t1, t2, t3;
+            const bool h0 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.x, nd.loy.x, nd.loz.x, nd.hix.x, nd.hiy.x,
+                                 nd.hiz.x, t0) && r.x != kWideEmpty;
+            const bool h1 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.y, nd.loy.y, nd.loz.y, nd.hix.y, nd.hiy.y,
+                                 nd.hiz.y, t1) && r.y != kWideEmpty;
+            const bool h2 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.z, nd.loy.z, nd.loz.z, nd.hix.z, nd.hiy.z,
+                                 nd.hiz.z, t2) && r.z != kWideEmpty;
+            const bool h3 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.w, nd.loy.w, nd.loz.w, nd.hix.w, nd.hiy.w,
+                                 nd.hiz.w, t3) && r.w != kWideEmpty;
+            const bool l0 = h0 && (r.x & kWideLeaf), l1 = h1 && (r.y & kWideLeaf);
+            const bool l2 = h2 && (r.z & kWideLeaf), l3 = h3 && (r.w & kWideLeaf);
+            const uint32_t lm = (l0 ? 1u : 0u) | (l1 ? 2u : 0u) | (l2 ? 4u : 0u) | (l3 ? 8u : 0u);
+            if (lm) {
+                pnode = node;
+                pmask = lm;
+            }
+            float k0 = (h0 && !l0) ? t0 : INFINITY, k1 = (h1 && !l1) ? t1 : INFINITY;
+            float k2 = (h2 && !l2) ? t2 : INFINITY, k3 = (h3 && !l3) ? t3 : INFINITY;
+            uint32_t i0 = (h0 && !l0) ? r.x : kNone, i1 = (h1 && !l1) ? r.y : kNone;
+            uint32_t i2 = (h2 && !l2) ? r.z : kNone, i3 = (h3 && !l3) ? r.w : kNone;
+            cswap4(k0, i0, k1, i1);
+            cswap4(k2, i2, k3, i3);
+            cswap4(k0, i0, k2, i2);
+            cswap4(k1, i1, k3, i3);
+            cswap4(k1, i1, k2, i2);
+            if (i3 < n_int && sp < kWideStack) stk[sp++] = i3;
+            if (i2 < n_int && sp < kWideStack) stk[sp++] = i2;
+            if (i1 < n_int && sp < kWideStack) stk[sp++] = i1;
+            if (i0 < n_int) node = i0;
+            else if (sp == 0) node = kNone;
+            else node = stk[--sp];
+        }
+        const bool can_step = has && node != kNone && pmask == 0;
+        const uint64_t busy = __ballot(has);
+        const uint64_t waiting = __ballot(has && pmask != 0);
+        const uint64_t stepping = __ballot(can_step);
+        if (waiting != 0 && (2 * __popcll(waiting) >= __popcll(busy) || stepping == 0)) {
+            if (has && pmask != 0) {
+                const uint4 r = sc.wnodes[pnode].ref;
+                if (pmask & 1u) test_tri(r.x & ~kWideLeaf);
+                if ((pmask & 2u) && (closest || !found)) test_tri(r.y & ~kWideLeaf);
+                if ((pmask & 4u) && (closest || !found)) test_tri(r.z & ~kWideLeaf);
+                if ((pmask & 8u) && (closest || !found)) test_tri(r.w & ~kWideLeaf);
+                pmask = 0;
+                if (!closest && found) node = kNone;
+            }
+        }
+        if (has && node == kNone && pmask == 0) {
+            if (closest)
+                bt.hits[rid] = make_float4(found ? best_t : INFINITY, __uint_as_float(found ? best_prim : kMissPrim),
+                                           found ? best_u : 0.0f, found ? best_v : 0.0f);
+            else
+                bt.occ[rid] = found ? 1 : 0;
+            has = false;
+        }
+    }
+}
+
+template <typename K, bool kWide>
 __global__ __launch_bounds__(64) void k_engine(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
                                                uint32_t nb, uint32_t total_items, uint32_t* queue, uint32_t mode,
                                                uint32_t key_bits, uint32_t passes, uint32_t chunk, uint32_t refill) {
@@ -399,7 +526,10 @@ __global__ __launch_bounds__(64) void k_engine(const EngScene* __restrict__ scen
         const EngScene& sc = scenes[bt.scene];
         const uint32_t j = item - bt.item0;
         if (mode == HCC_KEY_NONE) {
-            trace_range(sc, bt, nullptr, j * chunk, min(bt.n, (j + 1) * chunk), refill);
+            if (kWide && sc.n_int > 0)
+                trace_range_wide(sc, bt, nullptr, j * chunk, min(bt.n, (j + 1) * chunk), refill);
+            else
+                trace_range(sc, bt, nullptr, j * chunk, min(bt.n, (j + 1) * chunk), refill);
             continue;
         }
         const uint32_t tiles = bt.tiles;
@@ -415,7 +545,10 @@ __global__ __launch_bounds__(64) void k_engine(const EngScene* __restrict__ scen
             const uint32_t c = j - tiles * (1 + passes);
             wait_count(bt.done + passes, tiles, queue + 1);
             const uint32_t* perm = ((passes - 1) & 1) ? bt.vals_a : bt.vals_b;
-            trace_range(sc, bt, perm, c * chunk, min(bt.n, (c + 1) * chunk), refill);
+            if (kWide && sc.n_int > 0)
+                trace_range_wide(sc, bt, perm, c * chunk, min(bt.n, (c + 1) * chunk), refill);
+            else
+                trace_range(sc, bt, perm, c * chunk, min(bt.n, (c + 1) * chunk), refill);
         }
     }
 }
@@ -508,6 +641,7 @@ hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uin
     std::vector<EngScene> hs(sb.size());
     for (size_t s = 0; s < sb.size(); ++s) {
         hs[s].nodes = sb[s]->nodes;
+        hs[s].wnodes = sb[s]->wnodes;
         hs[s].tris = sb[s]->tris;
         hs[s].n_int = sb[s]->n_int;
         hs[s].cut = sc[s] ? sc[s]->d_boxes : nullptr;
@@ -565,10 +699,22 @@ hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uin
     const EngBatch* dbt = (const EngBatch*)(ws + P.batches_off);
     uint32_t* queue = (uint32_t*)(ws + P.zero_off);
     const unsigned grid = std::max(1u, std::min(waves, item));
-    if (key_bits <= 32)
-        k_engine<uint32_t><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes, chunk, refill);
-    else
-        k_engine<uint64_t><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes, chunk, refill);
+    const bool wide = (o.flags & HCC_TRACE_WIDE) != 0;
+    if (key_bits <= 32) {
+        if (wide)
+            k_engine<uint32_t, true><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes, chunk,
+                                                              refill);
+        else
+            k_engine<uint32_t, false><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes,
+                                                               chunk, refill);
+    } else {
+        if (wide)
+            k_engine<uint64_t, true><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes, chunk,
+                                                              refill);
+        else
+            k_engine<uint64_t, false><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes,
+                                                               chunk, refill);
+    }
     HCC_HIP(hipGetLastError());
     return HCC_OK;
 }

@@ -186,7 +186,7 @@ bool run_plain(hcc_server_s* s, const hcc_batch_desc& d) {
     to.persistent = 1;
     to.refill = 32;
     to.chunk = 64;
-    to.flags = 1;
+    to.flags = (s->opts.batch.flags & HCC_TRACE_WIDE) ? HCC_TRACE_WIDE : HCC_TRACE_SPECULATE;
     if (ok && d.n > 0)
         ok = hcc::trace(d.bvh, d.d_rays, perm, d.n, d.mode == HCC_TRACE_CLOSEST, d.d_hits, d.d_occluded, to, st) ==
              HCC_OK;
@@ -298,7 +298,7 @@ __attribute__((visibility("default"))) hcc_status hcc_server_create(const hcc_se
     if (o.max_group == 0) o.max_group = 16;
     if (o.streams == 0) o.streams = 4;
     if (o.key_bits == 0) o.key_bits = 32;
-    if (o.key_bits > 64 || o.streams > 32 || o.key_mode > HCC_KEY_TWOPOINT)
+    if (o.key_bits > 64 || o.streams > 32 || o.key_mode > HCC_KEY_TWOPOINT || (o.batch.flags & ~HCC_TRACE_WIDE))
         return fail(HCC_ERR_INVALID, "hcc_server_create: bad options");
     hcc_server_s* s = new hcc_server_s();
     s->opts = o;
