@@ -308,6 +308,8 @@ typedef struct hcc_server_opts {
     uint32_t key_mode;        /* hcc_key_mode for every request */
     uint32_t key_bits;        /* 1..64 (0 = 32) */
     uint32_t plain;           /* 1 = one request at a time through encode / sort / trace */
+    uint32_t graphs;          /* 1 = launch each group through a captured HIP graph (table copy,
+                                 counter clear, engine) kept per launch slot; 0 = three calls */
     hcc_batch_opts batch;     /* engine options */
 } hcc_server_opts;
 

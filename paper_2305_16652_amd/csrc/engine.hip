@@ -32,6 +32,13 @@ struct EngScene {
     float lo[3], hi[3];    // scene box (TwoPoint)
 };
 
+struct EngHeader {
+    uint32_t nb, total_items, mode, key_bits, passes, chunk, refill, pad;
+    uint32_t* zero;        // region cleared before the engine runs (starts with the queue counter)
+    uint32_t* queue;
+    uint64_t zero_words;
+};
+
 struct EngBatch {
     const float4* rays;
     float4* hits;
@@ -503,9 +510,9 @@ __device__ void trace_range_wide(const EngScene& sc, const EngBatch& bt, const u
 }
 
 template <typename K, bool kWide>
-__global__ __launch_bounds__(64) void k_engine(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
-                                               uint32_t nb, uint32_t total_items, uint32_t* queue, uint32_t mode,
-                                               uint32_t key_bits, uint32_t passes, uint32_t chunk, uint32_t refill) {
+__device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
+                                            uint32_t nb, uint32_t total_items, uint32_t* queue, uint32_t mode,
+                                            uint32_t key_bits, uint32_t passes, uint32_t chunk, uint32_t refill) {
     __shared__ CutBox s_cut[64];
     __shared__ uint32_t s_whist[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
@@ -553,7 +560,30 @@ __global__ __launch_bounds__(64) void k_engine(const EngScene* __restrict__ scen
     }
 }
 
+template <typename K, bool kWide>
+__global__ __launch_bounds__(64) void k_engine(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
+                                               uint32_t nb, uint32_t total_items, uint32_t* queue, uint32_t mode,
+                                               uint32_t key_bits, uint32_t passes, uint32_t chunk, uint32_t refill) {
+    engine_loop<K, kWide>(scenes, batches, nb, total_items, queue, mode, key_bits, passes, chunk, refill);
+}
+
 __global__ void k_zero(uint32_t* p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Graph-launched form: the launch parameters that change from group to group come from a
+// header the same graph copies to the device first, so one captured graph (copy, clear,
+// engine) serves every group.
+template <typename K, bool kWide>
+__global__ __launch_bounds__(64) void k_engine_hdr(const EngHeader* __restrict__ h, const EngScene* __restrict__ scenes,
+                                                   const EngBatch* __restrict__ batches) {
+    engine_loop<K, kWide>(scenes, batches, h->nb, h->total_items, h->queue, h->mode, h->key_bits, h->passes,
+                          h->chunk, h->refill);
+}
+
+__global__ void k_zero_hdr(const EngHeader* __restrict__ h) {
+    uint32_t* p = h->zero;
+    const size_t n = h->zero_words;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
@@ -612,15 +642,18 @@ size_t batch_table_bytes(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, ui
     return plan_batches(d, nb, nb, mode, key_bits, 0).tables;
 }
 
-// Launch a batch list.  With 'pinned' (page-locked host memory of at least
-// batch_table_bytes, kept alive by the caller until the stream has passed this launch) the
-// descriptor copy is asynchronous; without it a private buffer is used and the copy waited for.
-hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
-                        const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, hipStream_t stream, void* pinned,
-                        size_t pinned_bytes) {
+// Device descriptor tables of a batch list whose workspace is d_ws.
+struct Tables {
+    Plan P;
+    std::vector<EngScene> hs;
+    std::vector<EngBatch> hb;
+    EngHeader hdr{};
+};
+
+static hcc_status fill_tables(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
+                              const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, Tables& T) {
     const uint32_t chunk = std::max<uint32_t>(64u, o.chunk ? o.chunk : 256u);
     const uint32_t refill = std::min<uint32_t>(64u, std::max<uint32_t>(1u, o.refill ? o.refill : 32u));
-    const uint32_t waves = o.waves ? o.waves : 8192u;
     // scenes: distinct (bvh, cut) pairs
     std::vector<const hcc_bvh_s*> sb;
     std::vector<const hcc_cut_s*> sc;
@@ -634,27 +667,29 @@ hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uin
         }
         scene_of[b] = s;
     }
-    const Plan P = plan_batches(d, nb, (uint32_t)sb.size(), mode, key_bits, chunk);
+    T.P = plan_batches(d, nb, (uint32_t)sb.size(), mode, key_bits, chunk);
+    const Plan& P = T.P;
     if (ws_bytes < P.total) return fail(HCC_ERR_INVALID, "hcc_batch_run: workspace too small (see hcc_batch_workspace)");
     const uint32_t passes = mode == HCC_KEY_NONE ? 0 : (key_bits + 7) / 8;
     char* ws = (char*)d_ws;
-    std::vector<EngScene> hs(sb.size());
+    T.hs.assign(sb.size(), EngScene{});
     for (size_t s = 0; s < sb.size(); ++s) {
-        hs[s].nodes = sb[s]->nodes;
-        hs[s].wnodes = sb[s]->wnodes;
-        hs[s].tris = sb[s]->tris;
-        hs[s].n_int = sb[s]->n_int;
-        hs[s].cut = sc[s] ? sc[s]->d_boxes : nullptr;
-        hs[s].m = (mode == HCC_KEY_HCC && sc[s]) ? std::min(sc[s]->c_eff, key_bits) : 0;
+        EngScene& e = T.hs[s];
+        e.nodes = sb[s]->nodes;
+        e.wnodes = sb[s]->wnodes;
+        e.tris = sb[s]->tris;
+        e.n_int = sb[s]->n_int;
+        e.cut = sc[s] ? sc[s]->d_boxes : nullptr;
+        e.m = (mode == HCC_KEY_HCC && sc[s]) ? std::min(sc[s]->c_eff, key_bits) : 0;
         for (int a = 0; a < 3; ++a) {
-            hs[s].lo[a] = sb[s]->scene_box[a];
-            hs[s].hi[a] = sb[s]->scene_box[3 + a];
+            e.lo[a] = sb[s]->scene_box[a];
+            e.hi[a] = sb[s]->scene_box[3 + a];
         }
     }
-    std::vector<EngBatch> hb(nb);
+    T.hb.assign(nb, EngBatch{});
     uint32_t item = 0;
     for (uint32_t b = 0; b < nb; ++b) {
-        EngBatch& e = hb[b];
+        EngBatch& e = T.hb[b];
         e.rays = (const float4*)d[b].d_rays;
         e.hits = (float4*)d[b].d_hits;
         e.occ = d[b].d_occluded;
@@ -679,6 +714,32 @@ hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uin
         e.items = mode == HCC_KEY_NONE ? e.trace_items : e.tiles * (1 + passes) + e.trace_items;
         item += e.items;
     }
+    EngHeader& h = T.hdr;
+    h.nb = nb;
+    h.total_items = item;
+    h.mode = mode;
+    h.key_bits = key_bits;
+    h.passes = passes;
+    h.chunk = chunk;
+    h.refill = refill;
+    h.zero = (uint32_t*)(ws + P.zero_off);
+    h.queue = (uint32_t*)(ws + P.zero_off);
+    h.zero_words = P.zero_bytes / 4;
+    return HCC_OK;
+}
+
+// Launch a batch list.  With 'pinned' (page-locked host memory of at least
+// batch_table_bytes, kept alive by the caller until the stream has passed this launch) the
+// descriptor copy is asynchronous; without it a private buffer is used and the copy waited for.
+hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
+                        const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, hipStream_t stream, void* pinned,
+                        size_t pinned_bytes) {
+    Tables T;
+    hcc_status st = fill_tables(d, nb, mode, key_bits, o, d_ws, ws_bytes, T);
+    if (st != HCC_OK) return st;
+    const Plan& P = T.P;
+    const EngHeader& h = T.hdr;
+    char* ws = (char*)d_ws;
     // the descriptor tables travel with the launch on the stream; the host copies are kept
     // alive until the stream has consumed them
     static thread_local std::vector<char> staging;
@@ -689,33 +750,90 @@ hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uin
         staging.assign(P.tables, 0);
         host = staging.data();
     }
-    std::memcpy(host + P.scenes_off, hs.data(), sizeof(EngScene) * hs.size());
-    std::memcpy(host + P.batches_off, hb.data(), sizeof(EngBatch) * hb.size());
+    std::memcpy(host + P.scenes_off, T.hs.data(), sizeof(EngScene) * T.hs.size());
+    std::memcpy(host + P.batches_off, T.hb.data(), sizeof(EngBatch) * T.hb.size());
     HCC_HIP(hipMemcpyAsync(ws, host, P.tables, hipMemcpyHostToDevice, stream));
     if (!pinned) HCC_HIP(hipStreamSynchronize(stream));
-    const size_t zw = P.zero_bytes / 4;
-    k_zero<<<(unsigned)std::min<size_t>(2048, (zw + 255) / 256), 256, 0, stream>>>((uint32_t*)(ws + P.zero_off), zw);
+    const size_t zw = h.zero_words;
+    k_zero<<<(unsigned)std::min<size_t>(2048, (zw + 255) / 256), 256, 0, stream>>>(h.zero, zw);
     const EngScene* dsc = (const EngScene*)(ws + P.scenes_off);
     const EngBatch* dbt = (const EngBatch*)(ws + P.batches_off);
-    uint32_t* queue = (uint32_t*)(ws + P.zero_off);
-    const unsigned grid = std::max(1u, std::min(waves, item));
+    const uint32_t waves = o.waves ? o.waves : 8192u;
+    const unsigned grid = std::max(1u, std::min(waves, h.total_items));
     const bool wide = (o.flags & HCC_TRACE_WIDE) != 0;
+#define HCC_ENGINE(KT, WD)                                                                                        \
+    k_engine<KT, WD><<<grid, 64, 0, stream>>>(dsc, dbt, nb, h.total_items, h.queue, mode, key_bits, h.passes,   \
+                                              h.chunk, h.refill)
     if (key_bits <= 32) {
-        if (wide)
-            k_engine<uint32_t, true><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes, chunk,
-                                                              refill);
-        else
-            k_engine<uint32_t, false><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes,
-                                                               chunk, refill);
+        if (wide) HCC_ENGINE(uint32_t, true); else HCC_ENGINE(uint32_t, false);
     } else {
-        if (wide)
-            k_engine<uint64_t, true><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes, chunk,
-                                                              refill);
-        else
-            k_engine<uint64_t, false><<<grid, 64, 0, stream>>>(dsc, dbt, nb, item, queue, mode, key_bits, passes,
-                                                               chunk, refill);
+        if (wide) HCC_ENGINE(uint64_t, true); else HCC_ENGINE(uint64_t, false);
     }
+#undef HCC_ENGINE
     HCC_HIP(hipGetLastError());
+    return HCC_OK;
+}
+
+// ---- graph-launched groups (the request server's continuous mode)
+//
+// A slot owns a pinned staging buffer, a device table buffer of fixed capacity (header,
+// scenes, batches) and a graph captured once: copy staging -> device tables, clear the
+// group's counters (k_zero_hdr), run the engine (k_engine_hdr) on a fixed grid.  Launching a
+// group = writing its tables into the slot's staging buffer + one hipGraphLaunch.  The slot
+// stays with the group until the group's completion event has fired.
+size_t graph_table_bytes(uint32_t max_batches) {
+    return al(sizeof(EngHeader)) + al(sizeof(EngScene) * max_batches) + al(sizeof(EngBatch) * max_batches);
+}
+
+hcc_status graph_capture(uint32_t max_batches, uint32_t key_bits, const hcc_batch_opts& o, void* pinned,
+                         void* d_tables, hipStream_t capture_stream, hipGraphExec_t* exec) {
+    const size_t bytes = graph_table_bytes(max_batches);
+    char* dt = (char*)d_tables;
+    const EngHeader* dh = (const EngHeader*)dt;
+    const EngScene* dsc = (const EngScene*)(dt + al(sizeof(EngHeader)));
+    const EngBatch* dbt = (const EngBatch*)(dt + al(sizeof(EngHeader)) + al(sizeof(EngScene) * max_batches));
+    const unsigned grid = o.waves ? o.waves : 8192u;
+    const bool wide = (o.flags & HCC_TRACE_WIDE) != 0;
+    HCC_HIP(hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipMemcpyAsync(dt, pinned, bytes, hipMemcpyHostToDevice, capture_stream);
+    if (e == hipSuccess) {
+        k_zero_hdr<<<512, 256, 0, capture_stream>>>(dh);
+        if (key_bits <= 32) {
+            if (wide) k_engine_hdr<uint32_t, true><<<grid, 64, 0, capture_stream>>>(dh, dsc, dbt);
+            else k_engine_hdr<uint32_t, false><<<grid, 64, 0, capture_stream>>>(dh, dsc, dbt);
+        } else {
+            if (wide) k_engine_hdr<uint64_t, true><<<grid, 64, 0, capture_stream>>>(dh, dsc, dbt);
+            else k_engine_hdr<uint64_t, false><<<grid, 64, 0, capture_stream>>>(dh, dsc, dbt);
+        }
+        e = hipGetLastError();
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(capture_stream, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "engine graph capture");
+    return HCC_OK;
+}
+
+// Write a group's tables into a slot's staging buffer (the workspace d_ws holds the group's
+// counters and sort buffers) and launch the slot's graph.
+hcc_status graph_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
+                        const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, uint32_t max_batches, void* pinned,
+                        void* d_tables, hipGraphExec_t exec, hipStream_t stream) {
+    if (nb > max_batches) return fail(HCC_ERR_INVALID, "graph launch: more batches than the slot holds");
+    Tables T;
+    hcc_status st = fill_tables(d, nb, mode, key_bits, o, d_ws, ws_bytes, T);
+    if (st != HCC_OK) return st;
+    // the scenes' and batches' addresses inside the slot's device table
+    char* host = (char*)pinned;
+    char* dt = (char*)d_tables;
+    const size_t soff = al(sizeof(EngHeader)), boff = soff + al(sizeof(EngScene) * max_batches);
+    (void)dt;
+    std::memcpy(host, &T.hdr, sizeof(EngHeader));
+    std::memcpy(host + soff, T.hs.data(), sizeof(EngScene) * T.hs.size());
+    std::memcpy(host + boff, T.hb.data(), sizeof(EngBatch) * T.hb.size());
+    HCC_HIP(hipGraphLaunch(exec, stream));
     return HCC_OK;
 }
 

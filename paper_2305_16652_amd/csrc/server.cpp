@@ -31,6 +31,12 @@ hcc_status batch_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, 
 hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
                         const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, hipStream_t stream, void* pinned,
                         size_t pinned_bytes);
+size_t graph_table_bytes(uint32_t max_batches);
+hcc_status graph_capture(uint32_t max_batches, uint32_t key_bits, const hcc_batch_opts& o, void* pinned,
+                         void* d_tables, hipStream_t capture_stream, hipGraphExec_t* exec);
+hcc_status graph_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
+                        const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, uint32_t max_batches, void* pinned,
+                        void* d_tables, hipGraphExec_t exec, hipStream_t stream);
 hcc_status encode_hcc(const hcc_cut_s* cut, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
                       hipStream_t stream);
 hcc_status encode_twopoint(const hcc_bvh_s* bvh, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n,
@@ -52,8 +58,16 @@ struct Req {
     Clock::time_point t_submit, t_start, t_done;
 };
 
+// A captured launch graph with its staging and device table buffers (graph mode).
+struct Slot {
+    void* pinned = nullptr;
+    void* d_tables = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct Group {
     std::vector<uint64_t> ids;
+    int slot = -1;
     hipEvent_t done = nullptr;
     void* ws = nullptr;
     void* pinned = nullptr;
@@ -78,6 +92,8 @@ struct hcc_server_s {
     // and completion events; allocating either per launch costs more than a small launch
     std::vector<std::pair<size_t, void*>> pinned_free;
     std::vector<hipEvent_t> events_free;
+    std::vector<Slot> slots;        // graph mode: every slot ever made
+    std::vector<int> slots_free;
     hcc::Allocator alloc;           // hooks at creation; without hooks, stream-ordered hipMallocAsync
     uint64_t next_id = 1;
     size_t used_bytes = 0;
@@ -130,6 +146,7 @@ void finish_group(hcc_server_s* s, Group& g, bool ok) {
     if (g.ws) dev_put(s, g.ws, g.stream);
     if (g.pinned) s->pinned_free.emplace_back(g.pinned_bytes, g.pinned);
     if (g.done) s->events_free.push_back(g.done);
+    if (g.slot >= 0) s->slots_free.push_back(g.slot);
     g = Group();
 }
 
@@ -151,6 +168,32 @@ void* take_pinned(hcc_server_s* s, size_t bytes, size_t* got) {
     if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) return nullptr;
     *got = sz;
     return p;
+}
+
+// A free graph slot, capturing a new one when none is free (-1 on failure).
+int take_slot(hcc_server_s* s) {
+    if (!s->slots_free.empty()) {
+        const int i = s->slots_free.back();
+        s->slots_free.pop_back();
+        return i;
+    }
+    Slot sl;
+    const size_t bytes = hcc::graph_table_bytes(s->opts.max_group);
+    if (hipHostMalloc(&sl.pinned, bytes, hipHostMallocDefault) != hipSuccess) return -1;
+    std::memset(sl.pinned, 0, bytes);
+    sl.d_tables = s->alloc.get(bytes, s->streams[0]);
+    hipStream_t cap = nullptr;
+    bool ok = sl.d_tables && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hcc::graph_capture(s->opts.max_group, s->opts.key_bits, s->opts.batch, sl.pinned, sl.d_tables, cap,
+                                  &sl.exec) == HCC_OK;
+    if (cap) (void)hipStreamDestroy(cap);
+    if (!ok) {
+        if (sl.d_tables) s->alloc.put(sl.d_tables, s->streams[0]);
+        (void)hipHostFree(sl.pinned);
+        return -1;
+    }
+    s->slots.push_back(sl);
+    return (int)s->slots.size() - 1;
 }
 
 hipEvent_t take_event(hcc_server_s* s) {
@@ -257,9 +300,17 @@ void worker_loop(hcc_server_s* s) {
             const size_t tb = hcc::batch_table_bytes(ds.data(), (uint32_t)ds.size(), s->opts.key_mode,
                                                      s->opts.key_bits);
             ok = ok && (g.ws = dev_get(s, g.bytes, g.stream)) != nullptr;
-            ok = ok && (g.pinned = take_pinned(s, tb, &g.pinned_bytes)) != nullptr;
-            ok = ok && hcc::batch_launch(ds.data(), (uint32_t)ds.size(), s->opts.key_mode, s->opts.key_bits,
-                                         s->opts.batch, g.ws, g.bytes, g.stream, g.pinned, tb) == HCC_OK;
+            if (s->opts.graphs) {
+                ok = ok && (g.slot = take_slot(s)) >= 0;
+                ok = ok && hcc::graph_launch(ds.data(), (uint32_t)ds.size(), s->opts.key_mode, s->opts.key_bits,
+                                             s->opts.batch, g.ws, g.bytes, s->opts.max_group,
+                                             s->slots[g.slot].pinned, s->slots[g.slot].d_tables,
+                                             s->slots[g.slot].exec, g.stream) == HCC_OK;
+            } else {
+                ok = ok && (g.pinned = take_pinned(s, tb, &g.pinned_bytes)) != nullptr;
+                ok = ok && hcc::batch_launch(ds.data(), (uint32_t)ds.size(), s->opts.key_mode, s->opts.key_bits,
+                                             s->opts.batch, g.ws, g.bytes, g.stream, g.pinned, tb) == HCC_OK;
+            }
             ok = ok && (g.done = take_event(s)) != nullptr;
             ok = ok && hipEventRecord(g.done, g.stream) == hipSuccess;
             s->launches += 1;
@@ -413,6 +464,11 @@ __attribute__((visibility("default"))) void hcc_server_destroy(hcc_server s) {
     s->worker.join();
     for (auto st : s->streams) (void)hipStreamDestroy(st);
     for (auto& p : s->pinned_free) (void)hipHostFree(p.second);
+    for (auto& sl : s->slots) {
+        (void)hipGraphExecDestroy(sl.exec);
+        s->alloc.put(sl.d_tables, nullptr);
+        (void)hipHostFree(sl.pinned);
+    }
     for (auto e : s->events_free) (void)hipEventDestroy(e);
     s->magic = 0;
     delete s;

@@ -68,8 +68,9 @@ def test_hooked_allocations_balance_and_results_match(H):
         srv = H.Server(key_mode=H.KEY_HCC, key_bits=32, max_group=4, streams=2)
         batches = [H.Batch(b1, rays[i * 400:(i + 1) * 400], True, cut=c1) for i in range(4)]
         before = counts["alloc"]
-        for b in batches:
-            srv.submit(b)
+        for batch in batches:
+            srv.submit(batch)
+        del batch
         srv.drain()
         srv.close()
         assert counts["alloc"] > before and len(live) == 11

@@ -23,6 +23,7 @@ THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
 # bench.py's default launch configuration (block, stack, remap, persistent, refill, chunk, waves, flags);
 # the autotuner picks among these and the one-ray-per-lane launch, which test_gpu_parity covers
 BENCH_OPTS = (64, 0, 0, 1, 32, 64, 8192, 1)
+WIDE_OPTS = (64, 0, 0, 1, 24, 128, 8192, 2)       # the 4-wide traversal
 
 
 def _say(msg):
@@ -63,9 +64,10 @@ def test_fullsize_bvh_and_cut(frame):
         assert np.array_equal(H.select_cut(bvh, c).export()[0], O.select_cut(ob, had, c))
 
 
-def test_fullsize_primary_hits_all_rays(frame):
+@pytest.mark.parametrize("opts", [BENCH_OPTS, WIDE_OPTS])
+def test_fullsize_primary_hits_all_rays(frame, opts):
     H = frame["H"]
-    hits = H.trace(frame["bvh"], torch.from_numpy(frame["prim"]).cuda(), opts=_opts(H)).cpu().numpy()
+    hits = H.trace(frame["bvh"], torch.from_numpy(frame["prim"]).cuda(), opts=H.TraceOpts(*opts)).cpu().numpy()
     assert_closest(hits, frame["ph"], frame["prim"], frame["spec"].tris)
 
 
@@ -88,6 +90,9 @@ def test_fullsize_hcc_keys_sort_trace(frame, cut_size, key_bits):
     sample = np.arange(0, sec.shape[0], 997)
     oh = O.trace(ob, sec, subset=sample, threads=THREADS)
     assert_closest(hits, oh, sec, frame["spec"].tris, idx=sample)
+    # the 4-wide traversal returns the same closest hits on every ray
+    wide = H.trace(bvh, rays, perm, opts=H.TraceOpts(*WIDE_OPTS)).cpu().numpy()
+    assert np.array_equal(wide.view(np.uint32), hits.view(np.uint32))
 
 
 def test_fullsize_twopoint_keys(frame):
@@ -106,3 +111,5 @@ def test_fullsize_shadow_any_hit(frame):
     sample = np.arange(0, shd.shape[0], 1999)
     ref = O.trace(ob, shd, subset=sample, closest=False, threads=THREADS)
     assert_any(occ, ref, idx=sample)
+    wide = H.trace(bvh, rays, perm, closest=False, opts=H.TraceOpts(*WIDE_OPTS)).cpu().numpy()
+    assert np.array_equal(wide, occ)

@@ -55,11 +55,24 @@ def _lone(H, s, b, key_mode):
     return H.trace(s["bvh"], b.rays, perm, closest=b.closest).cpu().numpy()
 
 
-@pytest.mark.parametrize("plain", [False, True])
+VARIANTS = {"graph": dict(plain=False, graphs=True), "eager": dict(plain=False, graphs=False),
+            "graph-wide": dict(plain=False, graphs=True, wide=True), "plain": dict(plain=True),
+            "plain-wide": dict(plain=True, wide=True)}
+
+
+def _server(H, key_mode, variant, **kw):
+    v = dict(VARIANTS[variant])
+    wide = v.pop("wide", False)
+    batch = H.BatchOpts(0, 0, 0, H.TRACE_WIDE) if wide else None
+    return H.Server(key_mode=key_mode, key_bits=32, batch=batch, **v, **kw)
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
 @pytest.mark.parametrize("key_mode", [1, 2, 0])
-def test_server_results_equal_lone_requests(H, scenes, plain, key_mode):
+def test_server_results_equal_lone_requests(H, scenes, variant, key_mode):
+    plain = VARIANTS[variant]["plain"]
     reqs = _requests(H, scenes, 40, seed=key_mode * 7 + plain)
-    srv = H.Server(key_mode=key_mode, key_bits=32, plain=plain, max_group=8, streams=3)
+    srv = _server(H, key_mode, variant, max_group=8, streams=3)
     ids = [srv.submit(b) for _, b, _ in reqs]
     srv.drain()
     for rid, (s, b, rays) in zip(ids, reqs):
@@ -80,6 +93,24 @@ def test_server_results_equal_lone_requests(H, scenes, plain, key_mode):
             assert_any(got, O.trace(s["ob"], rays, closest=False))
     c = srv.counters()
     assert c["completed"] == len(reqs) and c["running"] == 0 and c["used_bytes"] == 0
+    srv.close()
+
+
+def test_server_graph_replays_match_eager(H, scenes):
+    """The captured launch graphs are replayed group after group; between rounds the test runs
+    its own eager work (the lone path) and synchronises, and checks every round's results."""
+    srv = _server(H, 1, "graph", max_group=4, streams=2)
+    for rnd in range(4):
+        reqs = _requests(H, scenes, 12, seed=100 + rnd)
+        ids = [srv.submit(b) for _, b, _ in reqs]
+        srv.drain()
+        torch.cuda.synchronize()
+        for rid, (s, b, rays) in zip(ids, reqs):
+            assert srv.poll(rid)[0] == H.REQ_DONE
+            ref = _lone(H, s, b, 1)
+            got = b.out.cpu().numpy()
+            assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), f"round {rnd}"
+    assert srv.counters()["launches"] >= 4 * 3
     srv.close()
 
 
