@@ -50,7 +50,7 @@ struct EngBatch {
     uint32_t* hist;        // passes x 256
     uint32_t* lookback;    // passes x tiles x 256
     uint32_t* done;        // passes + 1 completion counters
-    uint32_t scene, n, closest, tiles, trace_items, item0, items, pad;
+    uint32_t scene, n, closest, tiles, trace_items, item0, items, chunk;   // chunk: rays per trace item
 };
 
 namespace {
@@ -183,9 +183,12 @@ __device__ void encode_tile(const EngScene& sc, const EngBatch& bt, uint32_t til
 }
 
 // ---- S_p: one tile of one pass
+// Register budget: the 1,024 ranks wait in LDS (16-bit) across the look-back; keys are read
+// once to rank them and once more (from L2) to scatter them, so the engine kernel keeps the
+// trace phase's register count and occupancy.
 template <typename K>
 __device__ void scatter_tile(const EngBatch& bt, uint32_t tile, uint32_t p, uint32_t key_bits, uint32_t* s_whist,
-                             uint32_t* s_gbase, uint32_t* err) {
+                             uint32_t* s_gbase, uint16_t* s_rank, uint32_t* err) {
     const uint32_t lane = __lane_id();
     const K* kin = (const K*)((p & 1) ? bt.keys_b : bt.keys_a);
     K* kout = (K*)((p & 1) ? bt.keys_a : bt.keys_b);
@@ -195,23 +198,17 @@ __device__ void scatter_tile(const EngBatch& bt, uint32_t tile, uint32_t p, uint
     for (uint32_t j = 0; j < 4; ++j) s_whist[lane * 4 + j] = 0;
     __syncthreads();
     const uint64_t lt = below_mask();
-    K k[kPerLane];
-    uint32_t v[kPerLane], r[kPerLane];
-#pragma unroll
+    const uint32_t base_idx = tile * kTile + lane;
+#pragma unroll 4
     for (uint32_t i = 0; i < kPerLane; ++i) {
-        const uint32_t idx = tile * kTile + i * 64 + lane;
+        const uint32_t idx = base_idx + i * 64;
         const bool valid = idx < bt.n;
-        k[i] = valid ? kin[idx] : K(0);
-        v[i] = p == 0 ? idx : (valid ? vin[idx] : 0u);
-    }
-#pragma unroll
-    for (uint32_t i = 0; i < kPerLane; ++i) {
-        const bool valid = tile * kTile + i * 64 + lane < bt.n;
-        const uint32_t d = (uint32_t)(k[i] >> shift) & mask;
+        const K key = valid ? kin[idx] : K(0);
+        const uint32_t d = (uint32_t)(key >> shift) & mask;
         const uint64_t m = same_digit(d, nbits, valid);
         const uint32_t below = (uint32_t)__popcll(m & lt);
         const uint32_t prev = valid ? s_whist[d] : 0u;
-        r[i] = prev + below;
+        s_rank[i * 64 + lane] = (uint16_t)(prev + below);
         if (valid && below == 0) s_whist[d] = prev + (uint32_t)__popcll(m);
     }
     __syncthreads();
@@ -260,14 +257,17 @@ __device__ void scatter_tile(const EngBatch& bt, uint32_t tile, uint32_t p, uint
         base += h[j];
     }
     __syncthreads();
-#pragma unroll
+#pragma unroll 4
     for (uint32_t i = 0; i < kPerLane; ++i) {
-        if (tile * kTile + i * 64 + lane < bt.n) {
-            const uint32_t d = (uint32_t)(k[i] >> shift) & mask;
-            const uint32_t pos = s_gbase[d] + r[i];
+        const uint32_t idx = base_idx + i * 64;
+        if (idx < bt.n) {
+            const K key = kin[idx];
+            const uint32_t val = p == 0 ? idx : vin[idx];
+            const uint32_t d = (uint32_t)(key >> shift) & mask;
+            const uint32_t pos = s_gbase[d] + s_rank[i * 64 + lane];
             if (pos < bt.n) {   // always true unless a dependency failed (then 'err' is set)
-                kout[pos] = k[i];
-                vout[pos] = v[i];
+                kout[pos] = key;
+                vout[pos] = val;
             }
         }
     }
@@ -395,7 +395,7 @@ __device__ __forceinline__ void cswap4(float& ka, uint32_t& ia, float& kb, uint3
 }
 
 // ---- T over the 4-wide nodes (the persistent 4-wide trace kernel's step, for rays
-// [begin, end) of the batch's order; the scene has at least one internal node)
+// [begin, end) of the batch's order)
 __device__ void trace_range_wide(const EngScene& sc, const EngBatch& bt, const uint32_t* perm, uint32_t begin,
                                  uint32_t end, uint32_t refill) {
     const bool closest = bt.closest != 0;
@@ -439,6 +439,10 @@ __device__ void trace_range_wide(const EngScene& sc, const EngBatch& bt, const u
                         sp = 0;
                         pmask = 0;
                         node = 0;
+                        if (n_int == 0) {          // single-triangle scene: test its triangle now
+                            node = kNone;
+                            test_tri(0);
+                        }
                         has = true;
                     }
                 }
@@ -516,11 +520,12 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
     __shared__ CutBox s_cut[64];
     __shared__ uint32_t s_whist[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint16_t s_rank[kTile];
     __shared__ uint32_t s_item;
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
         __syncthreads();
-        const uint32_t item = s_item;
+        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);   // wave-uniform: scalar from here
         __syncthreads();
         if (item >= total_items) break;
         // batch owning this item (item0 ascending)
@@ -533,10 +538,10 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
         const EngScene& sc = scenes[bt.scene];
         const uint32_t j = item - bt.item0;
         if (mode == HCC_KEY_NONE) {
-            if (kWide && sc.n_int > 0)
-                trace_range_wide(sc, bt, nullptr, j * chunk, min(bt.n, (j + 1) * chunk), refill);
+            if (kWide)
+                trace_range_wide(sc, bt, nullptr, j * bt.chunk, min(bt.n, (j + 1) * bt.chunk), refill);
             else
-                trace_range(sc, bt, nullptr, j * chunk, min(bt.n, (j + 1) * chunk), refill);
+                trace_range(sc, bt, nullptr, j * bt.chunk, min(bt.n, (j + 1) * bt.chunk), refill);
             continue;
         }
         const uint32_t tiles = bt.tiles;
@@ -546,16 +551,16 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
         } else if (j < tiles * (1 + passes)) {
             const uint32_t p = (j - tiles) / tiles, tile = (j - tiles) % tiles;
             wait_count(bt.done + p, tiles, queue + 1);
-            scatter_tile<K>(bt, tile, p, key_bits, s_whist, s_gbase, queue + 1);
+            scatter_tile<K>(bt, tile, p, key_bits, s_whist, s_gbase, s_rank, queue + 1);
             signal(bt.done + p + 1);
         } else {
             const uint32_t c = j - tiles * (1 + passes);
             wait_count(bt.done + passes, tiles, queue + 1);
             const uint32_t* perm = ((passes - 1) & 1) ? bt.vals_a : bt.vals_b;
-            if (kWide && sc.n_int > 0)
-                trace_range_wide(sc, bt, perm, c * chunk, min(bt.n, (c + 1) * chunk), refill);
+            if (kWide)
+                trace_range_wide(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill);
             else
-                trace_range(sc, bt, perm, c * chunk, min(bt.n, (c + 1) * chunk), refill);
+                trace_range(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill);
         }
     }
 }
@@ -697,7 +702,10 @@ static hcc_status fill_tables(const hcc_batch_desc* d, uint32_t nb, uint32_t mod
         e.n = d[b].n;
         e.closest = d[b].mode == HCC_TRACE_CLOSEST ? 1u : 0u;
         e.tiles = (d[b].n + kTile - 1) / kTile;
-        e.trace_items = (d[b].n + chunk - 1) / chunk;
+        // a batch too small to give every wavefront a full chunk gets smaller chunks (down to one
+        // wavefront's worth), so its rays spread over ~2,048 wavefronts instead of a few
+        e.chunk = std::max<uint32_t>(64u, std::min<uint32_t>(chunk, d[b].n / 2048u));
+        e.trace_items = (d[b].n + e.chunk - 1) / e.chunk;
         e.hist = (uint32_t*)(ws + P.hist[b]);
         e.lookback = (uint32_t*)(ws + P.lookback[b]);
         e.done = (uint32_t*)(ws + P.done[b]);
