@@ -290,9 +290,10 @@ hcc_status hcc_batch_run(const hcc_batch_desc* batches, uint32_t nb, hcc_key_mod
 /* ---------------------------------------------------------------------------------------
  * Request server with continuous batching (not in the paper: serving around its path).
  * A worker thread admits queued requests in arrival order while the device ray-state budget
- * and the slot limit allow, launches each set of newly admitted requests as one engine batch on
- * the next of its streams (so later requests overlap with earlier ones still running), and
- * retires groups when their completion events fire.  A request's budget charge is its rays and
+ * and the slot limit allow, launches each set of newly admitted requests on the next of its
+ * streams (so later requests overlap with earlier ones still running) -- the small ones together
+ * as one engine batch, each large one (direct_min) through the full-device kernels -- and
+ * retires them when their completion events fire.  A request's budget charge is its rays and
  * results plus the engine workspace for its size.  Results are exactly those of a lone
  * hcc_encode + hcc_sort + hcc_trace of the request.  plain = 1 runs one request at a time
  * through those three calls instead (the baseline).  Buffers named in a request stay owned by
@@ -310,6 +311,9 @@ typedef struct hcc_server_opts {
     uint32_t plain;           /* 1 = one request at a time through encode / sort / trace */
     uint32_t graphs;          /* 1 = launch each group through a captured HIP graph (table copy,
                                  counter clear, engine) kept per launch slot; 0 = three calls */
+    uint32_t direct_min;      /* continuous mode: a request of at least this many rays runs through
+                                 the full-device encode / sort / trace kernels on its own stream
+                                 instead of the engine (0 = 65536; 0xFFFFFFFF = never) */
     hcc_batch_opts batch;     /* engine options */
 } hcc_server_opts;
 

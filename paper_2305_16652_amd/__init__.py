@@ -460,7 +460,7 @@ def batch_run(batches, mode: int, key_bits: int = 32, opts: BatchOpts | None = N
 class ServerOpts(C.Structure):
     _fields_ = [("budget_bytes", C.c_uint64), ("max_inflight", C.c_uint32), ("max_group", C.c_uint32),
                 ("streams", C.c_uint32), ("key_mode", C.c_uint32), ("key_bits", C.c_uint32), ("plain", C.c_uint32),
-                ("graphs", C.c_uint32), ("batch", BatchOpts)]
+                ("graphs", C.c_uint32), ("direct_min", C.c_uint32), ("batch", BatchOpts)]
 
 
 class ServerCounters(C.Structure):
@@ -488,9 +488,9 @@ class Server:
 
     def __init__(self, key_mode: int = KEY_HCC, key_bits: int = 32, budget_bytes: int = 64 << 30,
                  max_inflight: int = 64, max_group: int = 16, streams: int = 4, plain: bool = False,
-                 batch: BatchOpts | None = None, graphs: bool = True):
+                 batch: BatchOpts | None = None, graphs: bool = True, direct_min: int = 0):
         o = ServerOpts(budget_bytes, max_inflight, max_group, streams, key_mode, key_bits, 1 if plain else 0,
-                       1 if graphs else 0, batch if batch is not None else BatchOpts())
+                       1 if graphs else 0, direct_min, batch if batch is not None else BatchOpts())
         h = C.c_void_p()
         _check(lib.hcc_server_create(C.byref(o), C.byref(h)))
         self._h = h

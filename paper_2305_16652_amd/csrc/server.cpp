@@ -68,6 +68,7 @@ struct Slot {
 struct Group {
     std::vector<uint64_t> ids;
     int slot = -1;
+    void* direct[3] = {nullptr, nullptr, nullptr};   // a large request's own keys / perm / sort workspace
     hipEvent_t done = nullptr;
     void* ws = nullptr;
     void* pinned = nullptr;
@@ -144,6 +145,7 @@ void finish_group(hcc_server_s* s, Group& g, bool ok) {
         s->completed += 1;
     }
     if (g.ws) dev_put(s, g.ws, g.stream);
+    for (void* b : g.direct) dev_put(s, b, g.stream);
     if (g.pinned) s->pinned_free.emplace_back(g.pinned_bytes, g.pinned);
     if (g.done) s->events_free.push_back(g.done);
     if (g.slot >= 0) s->slots_free.push_back(g.slot);
@@ -208,22 +210,21 @@ hipEvent_t take_event(hcc_server_s* s) {
 }
 
 // Plain mode: one request through encode / sort / trace, waited for before the next.
-bool run_plain(hcc_server_s* s, const hcc_batch_desc& d) {
-    hipStream_t st = s->streams[0];
+// One request through hcc_encode, hcc_sort and hcc_trace's kernels, enqueued on st; the
+// buffers it takes (keys, permutation, sort workspace) are returned in bufs for the caller
+// to release once the stream has passed them.
+bool enqueue_direct(hcc_server_s* s, const hcc_batch_desc& d, hipStream_t st, void* bufs[3]) {
     const uint32_t mode = s->opts.key_mode, kb = s->opts.key_bits;
-    uint32_t* perm = nullptr;
-    void* keys = nullptr;
-    void* ws = nullptr;
+    bufs[0] = bufs[1] = bufs[2] = nullptr;
     bool ok = true;
     if (mode != HCC_KEY_NONE && d.n > 0) {
         const size_t ks = kb <= 32 ? 4 : 8;
         const size_t wsb = hcc::sort_workspace_bytes(d.n, kb);
-        ok = (keys = dev_get(s, (size_t)d.n * ks, st)) != nullptr &&
-             (perm = (uint32_t*)dev_get(s, (size_t)d.n * 4, st)) != nullptr &&
-             (ws = dev_get(s, wsb, st)) != nullptr;
-        if (ok) ok = (mode == HCC_KEY_HCC ? hcc::encode_hcc(d.cut, kb, d.d_rays, d.n, keys, st)
-                                          : hcc::encode_twopoint(d.bvh, kb, d.d_rays, d.n, keys, st)) == HCC_OK;
-        if (ok) ok = hcc::radix_sort(keys, kb, d.n, perm, nullptr, nullptr, ws, wsb, st) == HCC_OK;
+        ok = (bufs[0] = dev_get(s, (size_t)d.n * ks, st)) != nullptr &&
+             (bufs[1] = dev_get(s, (size_t)d.n * 4, st)) != nullptr && (bufs[2] = dev_get(s, wsb, st)) != nullptr;
+        if (ok) ok = (mode == HCC_KEY_HCC ? hcc::encode_hcc(d.cut, kb, d.d_rays, d.n, bufs[0], st)
+                                          : hcc::encode_twopoint(d.bvh, kb, d.d_rays, d.n, bufs[0], st)) == HCC_OK;
+        if (ok) ok = hcc::radix_sort(bufs[0], kb, d.n, (uint32_t*)bufs[1], nullptr, nullptr, bufs[2], wsb, st) == HCC_OK;
     }
     hcc_trace_opts to{};
     to.persistent = 1;
@@ -231,12 +232,18 @@ bool run_plain(hcc_server_s* s, const hcc_batch_desc& d) {
     to.chunk = 64;
     to.flags = (s->opts.batch.flags & HCC_TRACE_WIDE) ? HCC_TRACE_WIDE : HCC_TRACE_SPECULATE;
     if (ok && d.n > 0)
-        ok = hcc::trace(d.bvh, d.d_rays, perm, d.n, d.mode == HCC_TRACE_CLOSEST, d.d_hits, d.d_occluded, to, st) ==
-             HCC_OK;
+        ok = hcc::trace(d.bvh, d.d_rays, (const uint32_t*)bufs[1], d.n, d.mode == HCC_TRACE_CLOSEST, d.d_hits,
+                        d.d_occluded, to, st) == HCC_OK;
+    return ok;
+}
+
+// Plain mode: one request, waited for before the next.
+bool run_plain(hcc_server_s* s, const hcc_batch_desc& d) {
+    hipStream_t st = s->streams[0];
+    void* bufs[3];
+    const bool ok = enqueue_direct(s, d, st, bufs);
     const bool synced = hipStreamSynchronize(st) == hipSuccess;
-    dev_put(s, keys, st);
-    dev_put(s, perm, st);
-    dev_put(s, ws, st);
+    for (void* b : bufs) dev_put(s, b, st);
     return synced && ok;
 }
 
@@ -290,10 +297,34 @@ void worker_loop(hcc_server_s* s) {
                 s->launches += 1;
                 continue;
             }
+            // large requests run through the full-device kernels, each on the next stream; the
+            // rest go together into one engine launch
+            std::vector<uint64_t> small;
+            for (uint64_t id : admit) {
+                if (s->reqs[id].desc.n < s->opts.direct_min) {
+                    small.push_back(id);
+                    continue;
+                }
+                Group g;
+                g.ids = {id};
+                g.stream = s->streams[s->next_stream++ % s->streams.size()];
+                bool ok = enqueue_direct(s, s->reqs[id].desc, g.stream, g.direct);
+                ok = ok && (g.done = take_event(s)) != nullptr;
+                ok = ok && hipEventRecord(g.done, g.stream) == hipSuccess;
+                s->launches += 1;
+                if (!ok) {
+                    s->error = "launch failed: " + std::string(hcc_last_error());
+                    (void)hipStreamSynchronize(g.stream);
+                    finish_group(s, g, false);
+                } else {
+                    s->inflight.push_back(std::move(g));
+                }
+            }
+            if (small.empty()) continue;
             std::vector<hcc_batch_desc> ds;
-            for (uint64_t id : admit) ds.push_back(s->reqs[id].desc);
+            for (uint64_t id : small) ds.push_back(s->reqs[id].desc);
             Group g;
-            g.ids = admit;
+            g.ids = small;
             g.stream = s->streams[s->next_stream++ % s->streams.size()];
             bool ok = hcc::batch_workspace(ds.data(), (uint32_t)ds.size(), s->opts.key_mode, s->opts.key_bits,
                                            &g.bytes) == HCC_OK;
@@ -347,6 +378,7 @@ __attribute__((visibility("default"))) hcc_status hcc_server_create(const hcc_se
     if (o.budget_bytes == 0) o.budget_bytes = 64ull << 30;
     if (o.max_inflight == 0) o.max_inflight = 64;
     if (o.max_group == 0) o.max_group = 16;
+    if (o.direct_min == 0) o.direct_min = 65536;
     if (o.streams == 0) o.streams = 4;
     if (o.key_bits == 0) o.key_bits = 32;
     if (o.key_bits > 64 || o.streams > 32 || o.key_mode > HCC_KEY_TWOPOINT || (o.batch.flags & ~HCC_TRACE_WIDE))

@@ -55,7 +55,10 @@ def _lone(H, s, b, key_mode):
     return H.trace(s["bvh"], b.rays, perm, closest=b.closest).cpu().numpy()
 
 
-VARIANTS = {"graph": dict(plain=False, graphs=True), "eager": dict(plain=False, graphs=False),
+# "graph" routes requests of 3,000+ rays through the full-device kernels, the rest through the
+# engine; "engine-only" sends everything through the engine
+VARIANTS = {"graph": dict(plain=False, graphs=True, direct_min=3000), "engine-only": dict(plain=False, direct_min=0xFFFFFFFF),
+            "eager": dict(plain=False, graphs=False),
             "graph-wide": dict(plain=False, graphs=True, wide=True), "plain": dict(plain=True),
             "plain-wide": dict(plain=True, wide=True)}
 
