@@ -240,39 +240,58 @@ __global__ __launch_bounds__(256) void k_refit(uint32_t n, const uint32_t* __res
     }
 }
 
-// 4-wide nodes: an internal node at even depth (found by walking its parent chain) gathers
-// its children, replacing an internal child by that child's two children.
-__global__ __launch_bounds__(256) void k_wide(uint32_t n_int, const uint32_t* __restrict__ child,
-                                              const uint32_t* __restrict__ parent, const float* __restrict__ boxes,
-                                              Node4* __restrict__ wide) {
-    const uint32_t x = blockIdx.x * 256 + threadIdx.x;
-    if (x >= n_int) return;
-    uint32_t depth = 0;
-    for (uint32_t y = x; parent[y] != kNone; y = parent[y]) ++depth;
-    if (depth & 1u) return;
+// 4-wide nodes, one level of the wide tree per launch: a frontier node starts from its two
+// children and, while it has fewer than four and one of them is internal, replaces the
+// internal child of largest surface area by that child's two children (greedy SAH-style
+// collapse).  Internal members become the next level's frontier.  Each BVH2 node is a member
+// of exactly one wide node, so the output (indexed by BVH2 id) does not depend on the order
+// in which the frontier is appended.
+__global__ __launch_bounds__(256) void k_wide_level(const uint32_t* __restrict__ frontier, uint32_t count,
+                                                    uint32_t n_int, const uint32_t* __restrict__ child,
+                                                    const float* __restrict__ boxes, Node4* __restrict__ wide,
+                                                    uint32_t* __restrict__ next, uint32_t* __restrict__ next_count) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const uint32_t x = frontier[i];
+    uint32_t list[4] = {child[2 * (size_t)x], child[2 * (size_t)x + 1], kNone, kNone};
+    uint32_t m = 2;
+    while (m < 4) {
+        int best = -1;
+        float best_sa = -1.0f;
+        for (uint32_t j = 0; j < m; ++j) {
+            const uint32_t u = list[j];
+            if (u >= n_int) continue;
+            const float* bx = boxes + 6 * (size_t)u;
+            const float ex = bx[3] - bx[0], ey = bx[4] - bx[1], ez = bx[5] - bx[2];
+            const float sa = (ex * ey + ey * ez) + ez * ex;
+            if (sa > best_sa) {
+                best_sa = sa;
+                best = (int)j;
+            }
+        }
+        if (best < 0) break;
+        const uint32_t u = list[best];
+        for (uint32_t j = m; j > (uint32_t)best + 1; --j) list[j] = list[j - 1];
+        list[best] = child[2 * (size_t)u];
+        list[best + 1] = child[2 * (size_t)u + 1];
+        ++m;
+    }
     float lo[3][4], hi[3][4];
     uint32_t ref[4];
-    uint32_t m = 0;
-    auto put = [&](uint32_t u) {
-        const float* b = boxes + 6 * (size_t)u;
-        for (int a = 0; a < 3; ++a) {
-            lo[a][m] = b[a];
-            hi[a][m] = b[3 + a];
-        }
-        ref[m++] = u >= n_int ? (kWideLeaf | (u - n_int)) : u;
-    };
-    for (int c = 0; c < 2; ++c) {
-        const uint32_t u = child[2 * x + c];
-        if (u >= n_int) {
-            put(u);
+    for (uint32_t j = 0; j < 4; ++j) {
+        if (j < m) {
+            const uint32_t u = list[j];
+            const float* bx = boxes + 6 * (size_t)u;
+            for (int a = 0; a < 3; ++a) {
+                lo[a][j] = bx[a];
+                hi[a][j] = bx[3 + a];
+            }
+            ref[j] = u >= n_int ? (kWideLeaf | (u - n_int)) : u;
+            if (u < n_int) next[atomicAdd(next_count, 1u)] = u;
         } else {
-            put(child[2 * u]);
-            put(child[2 * u + 1]);
+            for (int a = 0; a < 3; ++a) lo[a][j] = hi[a][j] = 0.0f;
+            ref[j] = kWideEmpty;
         }
-    }
-    for (; m < 4; ++m) {
-        for (int a = 0; a < 3; ++a) lo[a][m] = hi[a][m] = 0.0f;
-        ref[m] = kWideEmpty;
     }
     Node4 w;
     w.lox = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
@@ -406,9 +425,29 @@ hcc_status build_bvh(const float* d_tris, uint32_t n, hipStream_t stream, hcc_bv
     if (b->n_int > 0)
         k_refit<true><<<blocks_for(n), 256, 0, stream>>>(n, b->child, b->parent, flags, b->boxes, b->had, b->nodes,
                                                         0.125);
-    if (b->n_int > 0)
-        k_wide<<<blocks_for(b->n_int), 256, 0, stream>>>(b->n_int, b->child, b->parent, b->boxes, b->wnodes);
     hipError_t e = hipGetLastError();
+    // 4-wide nodes, level by level from the root (codes / codes_sorted are free again and serve
+    // as the frontier ping-pong buffers, flags[0] as the next level's counter)
+    if (e == hipSuccess && b->n_int > 0) {
+        uint32_t* cur = codes;
+        uint32_t* nxt = codes_sorted;
+        uint32_t count = 1;
+        k_fill<<<1, 256, 0, stream>>>(cur, 1, 0u);
+        for (int level = 0; count > 0 && level < 256 && e == hipSuccess; ++level) {
+            k_fill<<<1, 256, 0, stream>>>(flags, 1, 0u);
+            k_wide_level<<<blocks_for(count), 256, 0, stream>>>(cur, count, b->n_int, b->child, b->boxes, b->wnodes,
+                                                                nxt, flags);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipMemcpyAsync(&count, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            std::swap(cur, nxt);
+        }
+        if (e == hipSuccess && count > 0) {   // deeper than any radix tree over 62-bit keys can be
+            cleanup();
+            free_bvh(b);
+            return fail(HCC_ERR_DEVICE, "hcc_build_bvh: 4-wide collapse did not finish");
+        }
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(b->scene_box, d_box, 6 * sizeof(float), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     cleanup();

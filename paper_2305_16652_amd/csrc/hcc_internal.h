@@ -24,11 +24,11 @@ struct alignas(64) Node {
     uint4 d;
 };
 
-// 4-wide node for traversal, 128 bytes (two cache lines): the BVH2 collapsed two levels at a
-// time.  Node X (a BVH2 internal node at even depth) holds X's children, with each internal
-// child replaced by its own two children (child 0's expansion first).  Slot j: box
-// (lox[j], loy[j], loz[j]) - (hix[j], hiy[j], hiz[j]); ref[j] = BVH2 id of an internal child
-// (whose 4-wide node is at the same index), kWideLeaf | triangle slot, or kWideEmpty.
+// 4-wide node for traversal, 128 bytes (two cache lines): the BVH2 collapsed top down.  The
+// wide node of BVH2 node X holds up to four BVH2 descendants of X that together cover its
+// subtree (X's children, internal ones replaced by their children, largest surface area first).
+// Slot j: box (lox[j], loy[j], loz[j]) - (hix[j], hiy[j], hiz[j]); ref[j] = BVH2 id of an internal
+// member (whose wide node is stored at that same index), kWideLeaf | triangle slot, or kWideEmpty.
 struct alignas(64) Node4 {
     float4 lox, loy, loz, hix, hiy, hiz;
     uint4 ref;
@@ -36,7 +36,7 @@ struct alignas(64) Node4 {
 };
 constexpr uint32_t kWideLeaf = 0x80000000u;
 constexpr uint32_t kWideEmpty = 0xFFFFFFFFu;
-constexpr int kWideStack = 96;    // 3 pushes per level, at most 32 levels of 4-wide nodes
+constexpr int kWideStack = 192;   // <= 3 pushes per wide level, at most 63 levels (BVH2 depth over 62-bit keys)
 
 // Triangle in Morton order, 48 bytes: v0, e1 = v1 - v0, e2 = v2 - v0 (float32,
 // rounded exactly as the Moller-Trumbore test computes them), original index.
