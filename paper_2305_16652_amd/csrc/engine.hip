@@ -33,7 +33,7 @@ struct EngScene {
 };
 
 struct EngHeader {
-    uint32_t nb, total_items, mode, key_bits, passes, chunk, refill, pad;
+    uint32_t nb, total_items, mode, key_bits, passes, refill, pad0, pad1;
     uint32_t* zero;        // region cleared before the engine runs (starts with the queue counter)
     uint32_t* queue;
     uint64_t zero_words;
@@ -516,7 +516,7 @@ __device__ void trace_range_wide(const EngScene& sc, const EngBatch& bt, const u
 template <typename K, bool kWide>
 __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
                                             uint32_t nb, uint32_t total_items, uint32_t* queue, uint32_t mode,
-                                            uint32_t key_bits, uint32_t passes, uint32_t chunk, uint32_t refill) {
+                                            uint32_t key_bits, uint32_t passes, uint32_t refill) {
     __shared__ CutBox s_cut[64];
     __shared__ uint32_t s_whist[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
@@ -568,8 +568,8 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
 template <typename K, bool kWide>
 __global__ __launch_bounds__(64) void k_engine(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
                                                uint32_t nb, uint32_t total_items, uint32_t* queue, uint32_t mode,
-                                               uint32_t key_bits, uint32_t passes, uint32_t chunk, uint32_t refill) {
-    engine_loop<K, kWide>(scenes, batches, nb, total_items, queue, mode, key_bits, passes, chunk, refill);
+                                               uint32_t key_bits, uint32_t passes, uint32_t refill) {
+    engine_loop<K, kWide>(scenes, batches, nb, total_items, queue, mode, key_bits, passes, refill);
 }
 
 __global__ void k_zero(uint32_t* p, size_t n) {
@@ -583,7 +583,7 @@ template <typename K, bool kWide>
 __global__ __launch_bounds__(64) void k_engine_hdr(const EngHeader* __restrict__ h, const EngScene* __restrict__ scenes,
                                                    const EngBatch* __restrict__ batches) {
     engine_loop<K, kWide>(scenes, batches, h->nb, h->total_items, h->queue, h->mode, h->key_bits, h->passes,
-                          h->chunk, h->refill);
+                          h->refill);
 }
 
 __global__ void k_zero_hdr(const EngHeader* __restrict__ h) {
@@ -728,7 +728,6 @@ static hcc_status fill_tables(const hcc_batch_desc* d, uint32_t nb, uint32_t mod
     h.mode = mode;
     h.key_bits = key_bits;
     h.passes = passes;
-    h.chunk = chunk;
     h.refill = refill;
     h.zero = (uint32_t*)(ws + P.zero_off);
     h.queue = (uint32_t*)(ws + P.zero_off);
@@ -771,7 +770,7 @@ hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uin
     const bool wide = (o.flags & HCC_TRACE_WIDE) != 0;
 #define HCC_ENGINE(KT, WD)                                                                                        \
     k_engine<KT, WD><<<grid, 64, 0, stream>>>(dsc, dbt, nb, h.total_items, h.queue, mode, key_bits, h.passes,   \
-                                              h.chunk, h.refill)
+                                              h.refill)
     if (key_bits <= 32) {
         if (wide) HCC_ENGINE(uint32_t, true); else HCC_ENGINE(uint32_t, false);
     } else {
@@ -835,9 +834,8 @@ hcc_status graph_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uin
     if (st != HCC_OK) return st;
     // the scenes' and batches' addresses inside the slot's device table
     char* host = (char*)pinned;
-    char* dt = (char*)d_tables;
+    (void)d_tables;   // the slot's graph copies the staging buffer there
     const size_t soff = al(sizeof(EngHeader)), boff = soff + al(sizeof(EngScene) * max_batches);
-    (void)dt;
     std::memcpy(host, &T.hdr, sizeof(EngHeader));
     std::memcpy(host + soff, T.hs.data(), sizeof(EngScene) * T.hs.size());
     std::memcpy(host + boff, T.hb.data(), sizeof(EngBatch) * T.hb.size());
