@@ -379,7 +379,34 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
 // farthest first.  kStats: counts, per lockstep iteration, the distinct 4-wide nodes fetched
 // by the stepping lanes and the distinct triangles fetched by a leaf batch (summed over the
 // wavefront into counts[0] and counts[1]).
-template <bool kClosest, bool kStats>
+// Per-lane stack of the 4-wide traversal: the first kWideShort entries in LDS (lane-interleaved,
+// conflict free), deeper ones in scratch; or all of it in scratch.
+constexpr int kWideShort = 12;
+
+template <bool kLds>
+struct WideStack;
+
+template <>
+struct WideStack<false> {
+    uint32_t s[kWideStack];
+    __device__ void init(uint32_t*) {}
+    __device__ void push(uint32_t sp, uint32_t x) { s[sp] = x; }
+    __device__ uint32_t pop(uint32_t sp) { return s[sp]; }
+};
+
+template <>
+struct WideStack<true> {
+    uint32_t* lds;
+    uint32_t deep[kWideStack - kWideShort];
+    __device__ void init(uint32_t* l) { lds = l + __lane_id(); }
+    __device__ void push(uint32_t sp, uint32_t x) {
+        if (sp < (uint32_t)kWideShort) lds[sp * 64] = x;
+        else deep[sp - kWideShort] = x;
+    }
+    __device__ uint32_t pop(uint32_t sp) { return sp < (uint32_t)kWideShort ? lds[sp * 64] : deep[sp - kWideShort]; }
+};
+
+template <bool kClosest, bool kStats, bool kLds>
 __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn, const Tri* __restrict__ tris,
                                                    uint32_t n_int, const float4* __restrict__ rays,
                                                    const uint32_t* __restrict__ perm, uint32_t n,
@@ -393,7 +420,9 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
     uint32_t next = cidx * chunk;
     uint32_t end = min(next + chunk, n);
     const uint64_t below = lanes_below();
-    uint32_t stack[kWideStack];
+    __shared__ uint32_t s_stack[kLds ? kWideShort * 64 : 1];
+    WideStack<kLds> stack;
+    stack.init(s_stack);
     bool has = false;
     uint32_t rid = 0, node = kNone, sp = 0, best_prim = kMissPrim;
     uint32_t pnode = 0, pmask = 0;
@@ -486,15 +515,15 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
             cswap(k0, i0, k2, i2);
             cswap(k1, i1, k3, i3);
             cswap(k1, i1, k2, i2);
-            if (i3 < n_int && sp < kWideStack) stack[sp++] = i3;
-            if (i2 < n_int && sp < kWideStack) stack[sp++] = i2;
-            if (i1 < n_int && sp < kWideStack) stack[sp++] = i1;
+            if (i3 < n_int && sp < kWideStack) stack.push(sp++, i3);
+            if (i2 < n_int && sp < kWideStack) stack.push(sp++, i2);
+            if (i1 < n_int && sp < kWideStack) stack.push(sp++, i1);
             if (i0 < n_int) {
                 node = i0;
             } else if (sp == 0) {
                 node = kNone;
             } else {
-                node = stack[--sp];
+                node = stack.pop(--sp);
             }
         }
 
@@ -582,12 +611,17 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
     const float4* r = (const float4*)rays;
     float4* h = (float4*)hits;
     if (o.flags & HCC_TRACE_WIDE) {
-        if (closest)
-            k_trace_wide<true, kStats><<<waves, 64, 0, s>>>(b->wnodes, b->tris, b->n_int, r, perm, n, h, occ, refill,
-                                                            chunk, counts);
-        else
-            k_trace_wide<false, kStats><<<waves, 64, 0, s>>>(b->wnodes, b->tris, b->n_int, r, perm, n, h, occ, refill,
-                                                             chunk, counts);
+        // stack: scratch (HCC_STACK_SCRATCH) or the first entries in LDS (HCC_STACK_SHORT / _LDS)
+        const bool lds = o.stack != HCC_STACK_SCRATCH && !kStats;
+#define HCC_WIDE(CL, LD)                                                                                       \
+    k_trace_wide<CL, kStats, LD><<<waves, 64, 0, s>>>(b->wnodes, b->tris, b->n_int, r, perm, n, h, occ, refill, \
+                                                      chunk, counts)
+        if (closest) {
+            if (lds) HCC_WIDE(true, true); else HCC_WIDE(true, false);
+        } else {
+            if (lds) HCC_WIDE(false, true); else HCC_WIDE(false, false);
+        }
+#undef HCC_WIDE
         HCC_HIP(hipGetLastError());
         return HCC_OK;
     }
