@@ -4,18 +4,15 @@
 // The launch works through a queue of items in batch-major order; for every batch:
 //   E   tiles of 1024 rays: sorting keys (HCC of the batch's scene, or TwoPoint) and the
 //       batch's digit histograms for every sort pass (wavefront-aggregated atomics);
-//   per 8-bit pass p: C_p count tiles (the tile's digit counts; for p = 0 the encode tiles
-//       produce them), Q_p digit scans (each turns one or more digits' per-tile counts into
-//       output offsets: an exclusive scan over tiles on top of the digit's start), X_p scatter
-//       tiles (stable ranking with wavefront ballots, then the tile's keys go to their offsets);
+//   S_p for each 8-bit pass p, tiles of 1024 keys: stable ranking with wavefront ballots,
+//       decoupled look-back over the batch's earlier tiles, scatter to the pass's output;
 //   T   chunks of rays traced through the batch's final permutation with lane refill and
 //       batched leaf tests (as the persistent trace kernel).
 // A wavefront takes the next item from a global counter.  Before an item of phase q it waits
-// until every item of phase q-1 of the same batch has signalled completion.  Everything waited
-// on sits earlier in the queue and is therefore already held by a running wavefront that waits
-// only on still earlier items, so the launch always drains.  (Reduce-then-scan instead of a
-// decoupled look-back: the tiles of a pass are all released at once when the previous phase
-// completes, and a look-back chain would then serialise them.)  Completion is signalled with a release fence + counter increment
+// until every item of phase q-1 of the same batch has signalled completion; look-back waits
+// only on earlier tiles of the same pass.  Everything waited on sits earlier in the queue and
+// is therefore already held by a running wavefront that waits only on still earlier items, so
+// the launch always drains.  Completion is signalled with a release fence + counter increment
 // and observed with an agent-scope load + acquire fence.
 #include <algorithm>
 #include <cstring>
@@ -50,11 +47,10 @@ struct EngBatch {
     void* keys_b;
     uint32_t* vals_a;
     uint32_t* vals_b;
-    uint32_t* hist;        // passes x 256: digit totals of each pass
-    uint32_t* counts;      // passes x 256 x tiles: per-tile digit counts, then output offsets
-    uint32_t* done;        // 1 + 3 passes completion counters
+    uint32_t* hist;        // passes x 256
+    uint32_t* lookback;    // passes x tiles x 256
+    uint32_t* done;        // passes + 1 completion counters
     uint32_t scene, n, closest, tiles, trace_items, item0, items, chunk;   // chunk: rays per trace item
-    uint32_t scan_items, pad0, pad1, pad2;                                 // digit scans per pass
 };
 
 namespace {
@@ -62,6 +58,7 @@ namespace {
 constexpr uint32_t kTile = 1024;      // keys per encode / sort tile (64 lanes x 16)
 constexpr uint32_t kPerLane = 16;
 constexpr uint32_t kRadix = 256;
+constexpr uint32_t kFlagAgg = 1u << 30, kFlagIncl = 2u << 30, kCountMask = (1u << 30) - 1u;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint64_t below_mask() {
@@ -98,8 +95,7 @@ constexpr uint32_t kSpinLimit = 1u << 24;
 __device__ __forceinline__ void wait_count(const uint32_t* p, uint32_t target, uint32_t* err) {
     uint32_t spins = 0;
     while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (spins < 64) __builtin_amdgcn_s_sleep(2);   // back off: many waves may poll one counter
-        else __builtin_amdgcn_s_sleep(20);
+        __builtin_amdgcn_s_sleep(2);
         if (++spins == kSpinLimit) {
             if (__lane_id() == 0) atomicOr(err, 1u);
             break;
@@ -159,13 +155,12 @@ __device__ K twopoint_key(const EngScene& sc, uint32_t key_bits, float4 a, float
 // ---- E: keys of one tile + histogram of every pass
 template <typename K>
 __device__ void encode_tile(const EngScene& sc, const EngBatch& bt, uint32_t tile, uint32_t mode, uint32_t key_bits,
-                            uint32_t passes, CutBox* s_cut, uint32_t* s_whist) {
+                            uint32_t passes, CutBox* s_cut) {
     const uint32_t lane = __lane_id();
-    for (uint32_t j = 0; j < 4; ++j) s_whist[lane * 4 + j] = 0;
     if (mode == HCC_KEY_HCC) {
         for (uint32_t i = lane; i < sc.m; i += 64) s_cut[i] = sc.cut[i];
+        __syncthreads();
     }
-    __syncthreads();
     const uint64_t lt = below_mask();
     K* keys = (K*)bt.keys_a;
     for (uint32_t i = 0; i < kPerLane; ++i) {
@@ -181,73 +176,19 @@ __device__ void encode_tile(const EngScene& sc, const EngBatch& bt, uint32_t til
             const uint32_t nb = min(8u, key_bits - 8u * p);
             const uint32_t d = (uint32_t)(key >> (8u * p)) & ((1u << nb) - 1u);
             const uint64_t m = same_digit(d, nb, valid);
-            if (valid && (m & lt) == 0) {
-                atomicAdd(&bt.hist[p * kRadix + d], (uint32_t)__popcll(m));
-                if (p == 0) s_whist[d] += (uint32_t)__popcll(m);
-            }
+            if (valid && (m & lt) == 0) atomicAdd(&bt.hist[p * kRadix + d], (uint32_t)__popcll(m));
         }
     }
     __syncthreads();
-    // pass 0's digit counts of this tile
-    for (uint32_t j = 0; j < 4; ++j) bt.counts[(size_t)(lane * 4 + j) * bt.tiles + tile] = s_whist[lane * 4 + j];
-    __syncthreads();
 }
 
-// ---- C_p (p >= 1): digit counts of one tile of pass p's input
-template <typename K>
-__device__ void count_tile(const EngBatch& bt, uint32_t tile, uint32_t p, uint32_t key_bits, uint32_t* s_whist) {
-    const uint32_t lane = __lane_id();
-    const K* kin = (const K*)((p & 1) ? bt.keys_b : bt.keys_a);
-    const uint32_t shift = 8u * p, nbits = min(8u, key_bits - 8u * p), mask = (1u << nbits) - 1u;
-    for (uint32_t j = 0; j < 4; ++j) s_whist[lane * 4 + j] = 0;
-    __syncthreads();
-    const uint64_t lt = below_mask();
-#pragma unroll 4
-    for (uint32_t i = 0; i < kPerLane; ++i) {
-        const uint32_t idx = tile * kTile + i * 64 + lane;
-        const bool valid = idx < bt.n;
-        const uint32_t d = valid ? (uint32_t)(kin[idx] >> shift) & mask : 0u;
-        const uint64_t m = same_digit(d, nbits, valid);
-        if (valid && (m & lt) == 0) s_whist[d] += (uint32_t)__popcll(m);
-    }
-    __syncthreads();
-    uint32_t* c = bt.counts + (size_t)p * kRadix * bt.tiles;
-    for (uint32_t j = 0; j < 4; ++j) c[(size_t)(lane * 4 + j) * bt.tiles + tile] = s_whist[lane * 4 + j];
-    __syncthreads();
-}
-
-// ---- Q_p: per-tile output offsets of a group of digits: the digit's start (the digits below
-// it, from the pass totals) plus an exclusive scan of its per-tile counts in tile order
-__device__ void scan_digits(const EngBatch& bt, uint32_t q, uint32_t p) {
-    const uint32_t lane = __lane_id();
-    const uint32_t per = kRadix / bt.scan_items;
-    const uint32_t* h = bt.hist + p * kRadix;
-    uint32_t* c = bt.counts + (size_t)p * kRadix * bt.tiles;
-    for (uint32_t d = q * per; d < (q + 1) * per; ++d) {
-        uint32_t v = 0;
-        for (uint32_t j = 0; j < 4; ++j) v += (lane * 4 + j < d) ? h[lane * 4 + j] : 0u;
-        uint32_t total;
-        (void)wave_excl_scan(v, total);
-        uint32_t running = total;   // start of digit d
-        uint32_t* cd = c + (size_t)d * bt.tiles;
-        for (uint32_t t0 = 0; t0 < bt.tiles; t0 += 64) {
-            const uint32_t t = t0 + lane;
-            const uint32_t x = t < bt.tiles ? cd[t] : 0u;
-            uint32_t sum;
-            const uint32_t ex = wave_excl_scan(x, sum);
-            if (t < bt.tiles) cd[t] = running + ex;
-            running += sum;
-        }
-    }
-}
-
-// ---- X_p: one tile of one pass
-// Register budget: the 1,024 ranks wait in LDS (16-bit); keys are read once to rank them and
-// once more (from L2) to scatter them, so the engine kernel keeps the trace phase's register
-// count and occupancy.
+// ---- S_p: one tile of one pass
+// Register budget: the 1,024 ranks wait in LDS (16-bit) across the look-back; keys are read
+// once to rank them and once more (from L2) to scatter them, so the engine kernel keeps the
+// trace phase's register count and occupancy.
 template <typename K>
 __device__ void scatter_tile(const EngBatch& bt, uint32_t tile, uint32_t p, uint32_t key_bits, uint32_t* s_whist,
-                             uint32_t* s_gbase, uint16_t* s_rank) {
+                             uint32_t* s_gbase, uint16_t* s_rank, uint32_t* err) {
     const uint32_t lane = __lane_id();
     const K* kin = (const K*)((p & 1) ? bt.keys_b : bt.keys_a);
     K* kout = (K*)((p & 1) ? bt.keys_a : bt.keys_b);
@@ -271,9 +212,50 @@ __device__ void scatter_tile(const EngBatch& bt, uint32_t tile, uint32_t p, uint
         if (valid && below == 0) s_whist[d] = prev + (uint32_t)__popcll(m);
     }
     __syncthreads();
-    // output offsets of this tile's digits (from the digit scans)
-    const uint32_t* c = bt.counts + (size_t)p * kRadix * bt.tiles;
-    for (uint32_t j = 0; j < 4; ++j) s_gbase[lane * 4 + j] = c[(size_t)(lane * 4 + j) * bt.tiles + tile];
+    // lane owns digits 4 lane .. 4 lane + 3
+    uint32_t cnt[4], excl[4];
+    uint32_t* lb = bt.lookback + ((size_t)p * bt.tiles + tile) * kRadix;
+    for (uint32_t j = 0; j < 4; ++j) {
+        cnt[j] = s_whist[lane * 4 + j];
+        excl[j] = 0;
+        __hip_atomic_store(lb + lane * 4 + j, (tile == 0 ? kFlagIncl : kFlagAgg) | cnt[j], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tile > 0) {
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t d = lane * 4 + j;
+            int64_t t = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            while (true) {
+                const uint32_t x = __hip_atomic_load(bt.lookback + ((size_t)p * bt.tiles + t) * kRadix + d,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t f = x & ~kCountMask;
+                if (f == 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins == kSpinLimit) {
+                        atomicOr(err, 2u);
+                        break;
+                    }
+                    continue;
+                }
+                excl[j] += x & kCountMask;
+                if (f == kFlagIncl) break;
+                --t;
+            }
+            __hip_atomic_store(lb + d, kFlagIncl | (excl[j] + cnt[j]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // global start of each digit: exclusive scan of the pass histogram + earlier tiles
+    uint32_t h[4], hs = 0, total;
+    for (uint32_t j = 0; j < 4; ++j) {
+        h[j] = bt.hist[p * kRadix + lane * 4 + j];
+        hs += h[j];
+    }
+    uint32_t base = wave_excl_scan(hs, total);
+    for (uint32_t j = 0; j < 4; ++j) {
+        s_gbase[lane * 4 + j] = base + excl[j];
+        base += h[j];
+    }
     __syncthreads();
 #pragma unroll 4
     for (uint32_t i = 0; i < kPerLane; ++i) {
@@ -283,7 +265,7 @@ __device__ void scatter_tile(const EngBatch& bt, uint32_t tile, uint32_t p, uint
             const uint32_t val = p == 0 ? idx : vin[idx];
             const uint32_t d = (uint32_t)(key >> shift) & mask;
             const uint32_t pos = s_gbase[d] + s_rank[i * 64 + lane];
-            if (pos < bt.n) {   // always true unless a dependency failed (then queue[1] is set)
+            if (pos < bt.n) {   // always true unless a dependency failed (then 'err' is set)
                 kout[pos] = key;
                 vout[pos] = val;
             }
@@ -562,49 +544,18 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
                 trace_range(sc, bt, nullptr, j * bt.chunk, min(bt.n, (j + 1) * bt.chunk), refill);
             continue;
         }
-        // batch-major phases: E | per pass p: [C_p (p >= 1)] Q_p X_p | T.  done[0] counts E,
-        // done[1 + 3p + k] counts C_p, Q_p, X_p for k = 0, 1, 2.
-        const uint32_t tiles = bt.tiles, nq = bt.scan_items;
-        uint32_t r = j;
-        if (r < tiles) {
-            encode_tile<K>(sc, bt, r, mode, key_bits, passes, s_cut, s_whist);
+        const uint32_t tiles = bt.tiles;
+        if (j < tiles) {
+            encode_tile<K>(sc, bt, j, mode, key_bits, passes, s_cut);
             signal(bt.done);
-            continue;
-        }
-        r -= tiles;
-        bool handled = false;
-        for (uint32_t p = 0; p < passes && !handled; ++p) {
-            uint32_t* dn = bt.done + 1 + 3 * p;
-            if (p > 0) {
-                if (r < tiles) {
-                    wait_count(dn - 1, tiles, queue + 1);            // X_{p-1} complete
-                    count_tile<K>(bt, r, p, key_bits, s_whist);
-                    signal(dn);
-                    handled = true;
-                    break;
-                }
-                r -= tiles;
-            }
-            if (r < nq) {
-                wait_count(p > 0 ? dn : bt.done, tiles, queue + 1);  // C_p (or E) complete
-                scan_digits(bt, r, p);
-                signal(dn + 1);
-                handled = true;
-                break;
-            }
-            r -= nq;
-            if (r < tiles) {
-                wait_count(dn + 1, nq, queue + 1);                   // Q_p complete
-                scatter_tile<K>(bt, r, p, key_bits, s_whist, s_gbase, s_rank);
-                signal(dn + 2);
-                handled = true;
-                break;
-            }
-            r -= tiles;
-        }
-        if (!handled) {
-            const uint32_t c = r;
-            wait_count(bt.done + 3 * passes, tiles, queue + 1);      // X_{passes-1} complete
+        } else if (j < tiles * (1 + passes)) {
+            const uint32_t p = (j - tiles) / tiles, tile = (j - tiles) % tiles;
+            wait_count(bt.done + p, tiles, queue + 1);
+            scatter_tile<K>(bt, tile, p, key_bits, s_whist, s_gbase, s_rank, queue + 1);
+            signal(bt.done + p + 1);
+        } else {
+            const uint32_t c = j - tiles * (1 + passes);
+            wait_count(bt.done + passes, tiles, queue + 1);
             const uint32_t* perm = ((passes - 1) & 1) ? bt.vals_a : bt.vals_b;
             if (kWide)
                 trace_range_wide(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill);
@@ -645,7 +596,7 @@ inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan {
     size_t tables, scenes_off, batches_off, zero_off, zero_bytes, total;
-    std::vector<size_t> keys_a, keys_b, vals_a, vals_b, hist, counts, done;
+    std::vector<size_t> keys_a, keys_b, vals_a, vals_b, hist, lookback, done;
     uint32_t total_items = 0;
 };
 
@@ -664,16 +615,14 @@ static Plan plan_batches(const hcc_batch_desc* d, uint32_t nb, uint32_t n_scenes
     // zeroed region: queue counter, histograms, look-back, completion counters
     P.zero_off = off;
     off += 256;   // queue counter
-    P.hist.resize(nb); P.counts.resize(nb); P.done.resize(nb);
-    for (uint32_t b = 0; b < nb; ++b) {
-        P.hist[b] = off; off += al((size_t)passes * kRadix * 4);
-        P.done[b] = off; off += al((1 + 3 * passes) * 4);
-    }
-    P.zero_bytes = off - P.zero_off;   // counts need no clearing: every entry is written before use
+    P.hist.resize(nb); P.lookback.resize(nb); P.done.resize(nb);
     for (uint32_t b = 0; b < nb; ++b) {
         const size_t tiles = (d[b].n + kTile - 1) / kTile;
-        P.counts[b] = off; off += al((size_t)passes * tiles * kRadix * 4);
+        P.hist[b] = off; off += al((size_t)passes * kRadix * 4);
+        P.lookback[b] = off; off += al((size_t)passes * tiles * kRadix * 4);
+        P.done[b] = off; off += al((passes + 1) * 4);
     }
+    P.zero_bytes = off - P.zero_off;
     P.keys_a.resize(nb); P.keys_b.resize(nb); P.vals_a.resize(nb); P.vals_b.resize(nb);
     for (uint32_t b = 0; b < nb; ++b) {
         const size_t n = d[b].n;
@@ -758,11 +707,7 @@ static hcc_status fill_tables(const hcc_batch_desc* d, uint32_t nb, uint32_t mod
         e.chunk = std::max<uint32_t>(64u, std::min<uint32_t>(chunk, d[b].n / 2048u));
         e.trace_items = (d[b].n + e.chunk - 1) / e.chunk;
         e.hist = (uint32_t*)(ws + P.hist[b]);
-        e.counts = (uint32_t*)(ws + P.counts[b]);
-        // digit scans per pass: 16 (16 digits each) for small batches up to 256 (one digit each)
-        uint32_t q = 16;
-        while (q < 256 && q < e.tiles) q <<= 1;
-        e.scan_items = q;
+        e.lookback = (uint32_t*)(ws + P.lookback[b]);
         e.done = (uint32_t*)(ws + P.done[b]);
         if (mode != HCC_KEY_NONE) {
             e.keys_a = ws + P.keys_a[b];
@@ -774,9 +719,7 @@ static hcc_status fill_tables(const hcc_batch_desc* d, uint32_t nb, uint32_t mod
             e.vals_a = e.vals_b = nullptr;
         }
         e.item0 = item;
-        e.items = mode == HCC_KEY_NONE ? e.trace_items
-                                       : e.tiles + passes * (e.scan_items + e.tiles) + (passes > 0 ? passes - 1 : 0) * e.tiles +
-                                             e.trace_items;
+        e.items = mode == HCC_KEY_NONE ? e.trace_items : e.tiles * (1 + passes) + e.trace_items;
         item += e.items;
     }
     EngHeader& h = T.hdr;
