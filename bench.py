@@ -439,7 +439,7 @@ def run_batched(H, args):
             ts.append(a.elapsed_time(e))
         return float(np.median(ts))
 
-    topts = H.TraceOpts(64, 0, 0, 1, 32, 64, 8192, 1)
+    topts = H.TraceOpts(64, 2, 0, 1, 32, 64, 8192, H.TRACE_WIDE)
     bufs = {}
 
     def plain(mode, K):
@@ -470,30 +470,42 @@ def run_batched(H, args):
         ws = H.batch_run(batches, H.KEY_HCC, K)
         for chunk in (128, 256, 512):
             for refill in (24, 32):
-                o = H.BatchOpts(chunk, refill, 8192, 0)
-                ms = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws), reps=2)
-                table.append((ms, K, chunk, refill))
-                if best is None or ms < best[0]:
-                    best = (ms, K, chunk, refill)
-    _, K, chunk, refill = best
+                for flags in (0, H.TRACE_WIDE):
+                    o = H.BatchOpts(chunk, refill, 8192, flags)
+                    ms = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws), reps=2)
+                    table.append((ms, K, chunk, refill, flags))
+                    if best is None or ms < best[0]:
+                        best = (ms, K, chunk, refill, flags)
+    _, K, chunk, refill, flags = best
     for b, p in zip(batches, plan):
         b.cut = cuts[K][p["scene"]]
-    o = H.BatchOpts(chunk, refill, 8192, 0)
+    o = H.BatchOpts(chunk, refill, 8192, flags, 0)
     ws = H.batch_run(batches, H.KEY_HCC, K, opts=o)
     res["engine_hcc_ms"] = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws))
     wsn = H.batch_run(batches, 0, K, opts=o)
     res["engine_nosort_ms"] = timeit(lambda: H.batch_run(batches, 0, K, opts=o, ws=wsn))
+    # the same call with large batches sent through the full-device kernels (direct_min tuned)
+    hyb = []
+    for dmin in (65536, 262144, 1048576):
+        od = H.BatchOpts(chunk, refill, 8192, flags, dmin)
+        hyb.append((timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=od, ws=ws), reps=3), dmin))
+    res["hybrid_hcc_ms"], direct_min = min(hyb)
+    od = H.BatchOpts(chunk, refill, 8192, flags, direct_min)
+    res["hybrid_nosort_ms"] = timeit(lambda: H.batch_run(batches, 0, K, opts=od, ws=wsn))
     res["plain_hcc_ms"] = timeit(lambda: plain(H.KEY_HCC, K))
     res["plain_nosort_ms"] = timeit(lambda: plain(0, K))
     out = {k.replace("_ms", "_mrays_s"): round(total / (v * 1e-3) / 1e6, 1) for k, v in res.items()}
     out.update({k: round(v, 3) for k, v in res.items()})
-    out.update(dict(batches=len(plan), rays=total, key_bits=K, cut=K, engine_opts=dict(chunk=chunk, refill=refill),
+    out.update(dict(batches=len(plan), rays=total, key_bits=K, cut=K,
+                    engine_opts=dict(chunk=chunk, refill=refill, flags=flags), hybrid_direct_min=direct_min,
                     plain_trace_opts=AT.opts_dict(topts),
                     speedup_engine_vs_plain_hcc=round(res["plain_hcc_ms"] / res["engine_hcc_ms"], 3),
                     scenes="cluster 10K/100K/1M/2M triangles",
-                    tuning=[dict(ms=round(t[0], 3), key_bits=t[1], chunk=t[2], refill=t[3]) for t in sorted(table)[:5]]))
-    log(f"batched: engine HCC {out['engine_hcc_mrays_s']} Mrays/s vs plain {out['plain_hcc_mrays_s']}; "
-        f"NoSort engine {out['engine_nosort_mrays_s']} vs plain {out['plain_nosort_mrays_s']}")
+                    tuning=[dict(ms=round(t[0], 3), key_bits=t[1], chunk=t[2], refill=t[3], flags=t[4])
+                            for t in sorted(table)[:5]]))
+    log(f"batched: engine HCC {out['engine_hcc_mrays_s']} Mrays/s (with direct launches >= {direct_min} rays: "
+        f"{out['hybrid_hcc_mrays_s']}) vs plain {out['plain_hcc_mrays_s']}; NoSort engine "
+        f"{out['engine_nosort_mrays_s']} ({out['hybrid_nosort_mrays_s']}) vs plain {out['plain_nosort_mrays_s']}")
     return out
 
 
@@ -621,7 +633,7 @@ def run_drift(H, args):
     t0 = time.time()
     spec = W.cluster_scene(args.drift_tris, seed=90)
     bvh = H.build_bvh(torch.from_numpy(spec.tris).to(dev))
-    opts = H.TraceOpts(64, 0, 0, 1, 32, 64, 8192, 1)
+    opts = H.TraceOpts(64, 2, 0, 1, 32, 64, 8192, H.TRACE_WIDE)
     rays = W.pinhole_rays(spec, args.width, args.height, args.drift_spp, seed=91)
     log(f"drift scene: {spec.tris.shape[0]} triangles, {rays.shape[0]} primary rays ({time.time() - t0:.1f}s)")
     out = dict(triangles=int(spec.tris.shape[0]), camera=f"{args.width}x{args.height}x{args.drift_spp}",

@@ -274,9 +274,13 @@ typedef struct hcc_batch_opts {
     uint32_t refill;          /* lane refill threshold 1..64 (0 = 32) */
     uint32_t waves;           /* persistent wavefronts launched (0 = 8192) */
     uint32_t flags;           /* HCC_TRACE_WIDE: trace over the 4-wide nodes; other bits must be 0 */
+    uint32_t direct_min;      /* 0 = every batch in the one engine launch (default); else >= 65536:
+                                 batches of at least this many rays run afterwards through the
+                                 full-device encode / sort / trace kernels on the same stream */
 } hcc_batch_opts;
 
-/* Device workspace needed by hcc_batch_run for this batch list, key mode and key length. */
+/* Device workspace needed by hcc_batch_run for this batch list, key mode and key length (for
+ * any opts.direct_min). */
 hcc_status hcc_batch_workspace(const hcc_batch_desc* batches, uint32_t nb, hcc_key_mode mode, uint32_t key_bits,
                                size_t* bytes);
 

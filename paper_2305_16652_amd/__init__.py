@@ -398,8 +398,11 @@ class BatchDesc(C.Structure):
 
 
 class BatchOpts(C.Structure):
-    """hcc_batch_opts: chunk (rays per trace item), refill, waves (0 = default), flags (TRACE_WIDE)."""
-    _fields_ = [("chunk", C.c_uint32), ("refill", C.c_uint32), ("waves", C.c_uint32), ("flags", C.c_uint32)]
+    """hcc_batch_opts: chunk (rays per trace item), refill, waves (0 = default), flags (TRACE_WIDE),
+    direct_min (0 = one engine launch for all; else batches of at least this many rays, >= 65536,
+    run through the full-device kernels)."""
+    _fields_ = [("chunk", C.c_uint32), ("refill", C.c_uint32), ("waves", C.c_uint32), ("flags", C.c_uint32),
+                ("direct_min", C.c_uint32)]
 
 
 lib.hcc_batch_workspace.argtypes = [C.c_void_p, C.c_uint32, C.c_int, C.c_uint32, C.POINTER(C.c_size_t)]

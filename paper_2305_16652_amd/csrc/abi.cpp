@@ -483,6 +483,8 @@ __attribute__((visibility("default"))) hcc_status hcc_batch_run(const hcc_batch_
     hcc_batch_opts o{};
     if (opts) o = *opts;
     if ((o.flags & ~HCC_TRACE_WIDE) != 0) return fail(HCC_ERR_INVALID, "hcc_batch_run: unknown opts.flags bits");
+    if (o.direct_min != 0 && o.direct_min < 65536)
+        return fail(HCC_ERR_INVALID, "hcc_batch_run: opts.direct_min must be 0 or at least 65536");
     return batch_run(batches, nb, mode, key_bits, o, d_ws, ws_bytes, S(stream));
 }
 

@@ -22,6 +22,14 @@
 
 namespace hcc {
 
+// the full-device kernels (encode.hip, trace.hip) used for direct launches
+hcc_status encode_hcc(const hcc_cut_s* cut, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
+                      hipStream_t stream);
+hcc_status encode_twopoint(const hcc_bvh_s* bvh, uint32_t key_bits, const hcc_ray* d_rays, uint32_t n, void* d_keys,
+                           hipStream_t stream);
+hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
+                 hcc_hit* hits, uint8_t* occ, const hcc_trace_opts& o, hipStream_t s);
+
 struct EngScene {
     const Node* nodes;
     const Node4* wnodes;
@@ -56,6 +64,7 @@ struct EngBatch {
 namespace {
 
 constexpr uint32_t kTile = 1024;      // keys per encode / sort tile (64 lanes x 16)
+constexpr uint32_t kDirectFloor = 65536;   // smallest batch that may take a direct launch
 constexpr uint32_t kPerLane = 16;
 constexpr uint32_t kRadix = 256;
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagIncl = 2u << 30, kCountMask = (1u << 30) - 1u;
@@ -637,7 +646,25 @@ static Plan plan_batches(const hcc_batch_desc* d, uint32_t nb, uint32_t n_scenes
     return P;
 }
 
+// A batch run outside the engine (direct launch): its keys, permutation and sort workspace.
+static size_t direct_bytes(uint32_t n, uint32_t mode, uint32_t key_bits) {
+    if (mode == HCC_KEY_NONE) return 0;
+    const size_t ks = key_bits <= 32 ? 4 : 8;
+    return al((size_t)n * ks) + al((size_t)n * 4) + al(sort_workspace_bytes(n, key_bits));
+}
+
+// Engine layout of every batch, then room for a direct launch of every batch that could take
+// one (at least kDirectFloor rays), whatever opts.direct_min the run uses.
 hcc_status batch_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, size_t* bytes) {
+    size_t total = al(plan_batches(d, nb, nb, mode, key_bits, 0).total);
+    for (uint32_t b = 0; b < nb; ++b)
+        if (d[b].n >= kDirectFloor) total += direct_bytes(d[b].n, mode, key_bits);
+    *bytes = total;
+    return HCC_OK;
+}
+
+// The engine part alone (the request server runs its large requests itself).
+hcc_status engine_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, size_t* bytes) {
     *bytes = plan_batches(d, nb, nb, mode, key_bits, 0).total;
     return HCC_OK;
 }
@@ -735,12 +762,67 @@ static hcc_status fill_tables(const hcc_batch_desc* d, uint32_t nb, uint32_t mod
     return HCC_OK;
 }
 
+// One batch through the full-device kernels (encode, radix sort, persistent 4-wide trace) on
+// the stream, with its buffers at ws.
+static hcc_status run_direct(const hcc_batch_desc& d, uint32_t mode, uint32_t key_bits, char* ws, hipStream_t stream) {
+    hcc_trace_opts to{};
+    to.persistent = 1;
+    to.stack = HCC_STACK_SHORT;
+    to.refill = 32;
+    to.chunk = 64;
+    to.flags = HCC_TRACE_WIDE;
+    const uint32_t* perm = nullptr;
+    if (mode != HCC_KEY_NONE) {
+        const size_t ks = key_bits <= 32 ? 4 : 8;
+        void* keys = ws;
+        uint32_t* pm = (uint32_t*)(ws + al((size_t)d.n * ks));
+        void* sws = ws + al((size_t)d.n * ks) + al((size_t)d.n * 4);
+        const size_t swb = al(sort_workspace_bytes(d.n, key_bits));
+        hcc_status st = mode == HCC_KEY_HCC ? encode_hcc(d.cut, key_bits, d.d_rays, d.n, keys, stream)
+                                            : encode_twopoint(d.bvh, key_bits, d.d_rays, d.n, keys, stream);
+        if (st != HCC_OK) return st;
+        if ((st = radix_sort(keys, key_bits, d.n, pm, nullptr, nullptr, sws, swb, stream)) != HCC_OK) return st;
+        perm = pm;
+    }
+    return trace(d.bvh, d.d_rays, perm, d.n, d.mode == HCC_TRACE_CLOSEST, d.d_hits, d.d_occluded, to, stream);
+}
+
 // Launch a batch list.  With 'pinned' (page-locked host memory of at least
 // batch_table_bytes, kept alive by the caller until the stream has passed this launch) the
 // descriptor copy is asynchronous; without it a private buffer is used and the copy waited for.
+static hcc_status engine_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
+                                const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, hipStream_t stream, void* pinned,
+                                size_t pinned_bytes);
+
 hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
                         const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, hipStream_t stream, void* pinned,
                         size_t pinned_bytes) {
+    if (o.direct_min == 0) return engine_launch(d, nb, mode, key_bits, o, d_ws, ws_bytes, stream, pinned, pinned_bytes);
+    // batches of at least direct_min rays run through the full-device kernels after the engine
+    // launch of the others; their buffers follow the engine layout of the whole list
+    std::vector<hcc_batch_desc> rest;
+    for (uint32_t b = 0; b < nb; ++b)
+        if (d[b].n < o.direct_min) rest.push_back(d[b]);
+    size_t off = al(plan_batches(d, nb, nb, mode, key_bits, 0).total);
+    if (!rest.empty()) {
+        const hcc_status st = engine_launch(rest.data(), (uint32_t)rest.size(), mode, key_bits, o, d_ws, off, stream,
+                                            pinned, pinned_bytes);
+        if (st != HCC_OK) return st;
+    }
+    for (uint32_t b = 0; b < nb; ++b) {
+        if (d[b].n < o.direct_min) continue;
+        const size_t need = direct_bytes(d[b].n, mode, key_bits);
+        if (off + need > ws_bytes) return fail(HCC_ERR_INVALID, "hcc_batch_run: workspace too small (see hcc_batch_workspace)");
+        const hcc_status st = run_direct(d[b], mode, key_bits, (char*)d_ws + off, stream);
+        if (st != HCC_OK) return st;
+        off += need;
+    }
+    return HCC_OK;
+}
+
+static hcc_status engine_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
+                                const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, hipStream_t stream, void* pinned,
+                                size_t pinned_bytes) {
     Tables T;
     hcc_status st = fill_tables(d, nb, mode, key_bits, o, d_ws, ws_bytes, T);
     if (st != HCC_OK) return st;

@@ -28,6 +28,7 @@
 namespace hcc {
 size_t batch_table_bytes(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits);
 hcc_status batch_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, size_t* bytes);
+hcc_status engine_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, size_t* bytes);
 hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
                         const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, hipStream_t stream, void* pinned,
                         size_t pinned_bytes);
@@ -226,11 +227,12 @@ bool enqueue_direct(hcc_server_s* s, const hcc_batch_desc& d, hipStream_t st, vo
                                           : hcc::encode_twopoint(d.bvh, kb, d.d_rays, d.n, bufs[0], st)) == HCC_OK;
         if (ok) ok = hcc::radix_sort(bufs[0], kb, d.n, (uint32_t*)bufs[1], nullptr, nullptr, bufs[2], wsb, st) == HCC_OK;
     }
-    hcc_trace_opts to{};
+    hcc_trace_opts to{};   // the full-device trace: persistent 4-wide traversal, LDS short stack
     to.persistent = 1;
+    to.stack = HCC_STACK_SHORT;
     to.refill = 32;
     to.chunk = 64;
-    to.flags = (s->opts.batch.flags & HCC_TRACE_WIDE) ? HCC_TRACE_WIDE : HCC_TRACE_SPECULATE;
+    to.flags = HCC_TRACE_WIDE;
     if (ok && d.n > 0)
         ok = hcc::trace(d.bvh, d.d_rays, (const uint32_t*)bufs[1], d.n, d.mode == HCC_TRACE_CLOSEST, d.d_hits,
                         d.d_occluded, to, st) == HCC_OK;
@@ -326,7 +328,7 @@ void worker_loop(hcc_server_s* s) {
             Group g;
             g.ids = small;
             g.stream = s->streams[s->next_stream++ % s->streams.size()];
-            bool ok = hcc::batch_workspace(ds.data(), (uint32_t)ds.size(), s->opts.key_mode, s->opts.key_bits,
+            bool ok = hcc::engine_workspace(ds.data(), (uint32_t)ds.size(), s->opts.key_mode, s->opts.key_bits,
                                            &g.bytes) == HCC_OK;
             const size_t tb = hcc::batch_table_bytes(ds.data(), (uint32_t)ds.size(), s->opts.key_mode,
                                                      s->opts.key_bits);
@@ -383,6 +385,7 @@ __attribute__((visibility("default"))) hcc_status hcc_server_create(const hcc_se
     if (o.key_bits == 0) o.key_bits = 32;
     if (o.key_bits > 64 || o.streams > 32 || o.key_mode > HCC_KEY_TWOPOINT || (o.batch.flags & ~HCC_TRACE_WIDE))
         return fail(HCC_ERR_INVALID, "hcc_server_create: bad options");
+    o.batch.direct_min = 0;   // large requests are routed by the server itself (direct_min above)
     hcc_server_s* s = new hcc_server_s();
     s->opts = o;
     s->alloc = hcc::current_allocator();

@@ -80,6 +80,32 @@ def test_engine_matches_oracle_and_plain_path(H, scenes, mode, key_bits, cut, op
             assert_any(got, O.trace(s["ob"], rays, closest=False))
 
 
+@pytest.mark.parametrize("mode", ["hcc", "twopoint", "none"])
+def test_engine_direct_launches_for_large_batches(H, scenes, mode):
+    """With direct_min set, batches of that many rays go through the full-device kernels after
+    the engine launch of the rest; results are those of the lone path either way."""
+    key_mode = {"hcc": H.KEY_HCC, "twopoint": H.KEY_TWOPOINT, "none": 0}[mode]
+    rng = np.random.default_rng(11)
+    items = []
+    for n in (70000, 100, 65536, 65535, 3000, 140000):
+        s = scenes[int(rng.integers(0, len(scenes)))]
+        closest = bool(rng.random() < 0.7)
+        pool = s["diffuse"] if closest else s["shadow"]
+        rays = np.ascontiguousarray(np.resize(pool, (n, 8)), np.float32)
+        items.append((s, H.Batch(s["bvh"], torch.from_numpy(rays).cuda(), closest,
+                                 cut=s["cut32"] if mode == "hcc" else None), rays))
+    H.batch_run([b for _, b, _ in items], key_mode, 32, opts=H.BatchOpts(0, 0, 0, 0, 65536))
+    torch.cuda.synchronize()
+    for s, b, rays in items:
+        perm = None
+        if mode != "none":
+            perm = H.sort(H.encode(s["bvh"], b.cut, key_mode, 32, b.rays), 32)
+        ref = H.trace(s["bvh"], b.rays, perm, closest=b.closest).cpu().numpy()
+        assert np.array_equal(b.out.cpu().numpy().view(np.uint8), ref.view(np.uint8))
+    with pytest.raises(H.HCCError):
+        H.batch_run([b for _, b, _ in items], key_mode, 32, opts=H.BatchOpts(0, 0, 0, 0, 1000))
+
+
 def test_engine_reuses_workspace_and_is_deterministic(H, scenes):
     items = _batches(H, scenes, seed=5, key_cut="cut32")
     batches = [b for _, b, _ in items]
