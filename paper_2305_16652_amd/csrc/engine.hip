@@ -65,6 +65,7 @@ namespace {
 
 constexpr uint32_t kTile = 1024;      // keys per encode / sort tile (64 lanes x 16)
 constexpr uint32_t kDirectFloor = 65536;   // smallest batch that may take a direct launch
+constexpr int kEngShort = 8;               // 4-wide trace: stack entries per lane kept in LDS
 constexpr uint32_t kPerLane = 16;
 constexpr uint32_t kRadix = 256;
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagIncl = 2u << 30, kCountMask = (1u << 30) - 1u;
@@ -405,11 +406,18 @@ __device__ __forceinline__ void cswap4(float& ka, uint32_t& ia, float& kb, uint3
 
 // ---- T over the 4-wide nodes (the persistent 4-wide trace kernel's step, for rays
 // [begin, end) of the batch's order)
-__device__ void trace_range_wide(const EngScene& sc, const EngBatch& bt, const uint32_t* perm, uint32_t begin,
-                                 uint32_t end, uint32_t refill) {
-    const bool closest = bt.closest != 0;
+template <bool closest>
+__device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const uint32_t* perm, uint32_t begin,
+                                   uint32_t end, uint32_t refill, uint32_t* s_stk) {
     const uint64_t below = below_mask();
-    uint32_t stk[kWideStack];
+    // first kEngShort entries per lane in LDS (lane-interleaved), deeper ones in scratch
+    uint32_t deep[kWideStack - kEngShort];
+    uint32_t* lds = s_stk + __lane_id();
+    auto push = [&](uint32_t i, uint32_t x) {
+        if (i < (uint32_t)kEngShort) lds[i * 64] = x;
+        else deep[i - kEngShort] = x;
+    };
+    auto pop = [&](uint32_t i) { return i < (uint32_t)kEngShort ? lds[i * 64] : deep[i - kEngShort]; };
     uint32_t next = begin;
     bool has = false;
     uint32_t rid = 0, node = kNone, sp = 0, best_prim = kMissPrim, pnode = 0, pmask = 0;
@@ -489,12 +497,12 @@ __device__ void trace_range_wide(const EngScene& sc, const EngBatch& bt, const u
             cswap4(k0, i0, k2, i2);
             cswap4(k1, i1, k3, i3);
             cswap4(k1, i1, k2, i2);
-            if (i3 < n_int && sp < kWideStack) stk[sp++] = i3;
-            if (i2 < n_int && sp < kWideStack) stk[sp++] = i2;
-            if (i1 < n_int && sp < kWideStack) stk[sp++] = i1;
+            if (i3 < n_int && sp < kWideStack) push(sp++, i3);
+            if (i2 < n_int && sp < kWideStack) push(sp++, i2);
+            if (i1 < n_int && sp < kWideStack) push(sp++, i1);
             if (i0 < n_int) node = i0;
             else if (sp == 0) node = kNone;
-            else node = stk[--sp];
+            else node = pop(--sp);
         }
         const bool can_step = has && node != kNone && pmask == 0;
         const uint64_t busy = __ballot(has);
@@ -522,6 +530,12 @@ __device__ void trace_range_wide(const EngScene& sc, const EngBatch& bt, const u
     }
 }
 
+__device__ __forceinline__ void trace_range_wide(const EngScene& sc, const EngBatch& bt, const uint32_t* perm,
+                                                 uint32_t begin, uint32_t end, uint32_t refill, uint32_t* s_stk) {
+    if (bt.closest) trace_range_wide_t<true>(sc, bt, perm, begin, end, refill, s_stk);
+    else trace_range_wide_t<false>(sc, bt, perm, begin, end, refill, s_stk);
+}
+
 template <typename K, bool kWide>
 __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
                                             uint32_t nb, uint32_t total_items, uint32_t* queue, uint32_t mode,
@@ -529,7 +543,10 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
     __shared__ CutBox s_cut[64];
     __shared__ uint32_t s_whist[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
-    __shared__ uint16_t s_rank[kTile];
+    // the scatter's ranks and the 4-wide trace's short stacks are never live at the same time
+    __shared__ uint32_t s_share[kTile / 2 > kEngShort * 64 ? kTile / 2 : kEngShort * 64];
+    uint16_t* s_rank = reinterpret_cast<uint16_t*>(s_share);
+    uint32_t* s_stk = s_share;
     __shared__ uint32_t s_item;
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
@@ -548,7 +565,7 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
         const uint32_t j = item - bt.item0;
         if (mode == HCC_KEY_NONE) {
             if (kWide)
-                trace_range_wide(sc, bt, nullptr, j * bt.chunk, min(bt.n, (j + 1) * bt.chunk), refill);
+                trace_range_wide(sc, bt, nullptr, j * bt.chunk, min(bt.n, (j + 1) * bt.chunk), refill, s_stk);
             else
                 trace_range(sc, bt, nullptr, j * bt.chunk, min(bt.n, (j + 1) * bt.chunk), refill);
             continue;
@@ -567,7 +584,7 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
             wait_count(bt.done + passes, tiles, queue + 1);
             const uint32_t* perm = ((passes - 1) & 1) ? bt.vals_a : bt.vals_b;
             if (kWide)
-                trace_range_wide(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill);
+                trace_range_wide(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill, s_stk);
             else
                 trace_range(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill);
         }
