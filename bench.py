@@ -390,7 +390,8 @@ def run_serving(H, args):
         row = {}
         for name, server in (("plain", plain), ("continuous", None)):
             if server is None:
-                server = H.Server(key_mode=H.KEY_HCC, key_bits=32, max_group=16, streams=4)
+                server = H.Server(key_mode=H.KEY_HCC, key_bits=32, max_group=16, streams=4,
+                                  batch=H.BatchOpts(0, 0, 0, H.TRACE_WIDE, 0))
             lat, wall = serve(server, rate)
             row[name] = dict(p50_ms=round(float(np.percentile(lat, 50)) / 1e3, 3),
                              p99_ms=round(float(np.percentile(lat, 99)) / 1e3, 3),
