@@ -18,7 +18,7 @@ from . import (KEY_HCC, KEY_TWOPOINT, TraceOpts, encode, select_cut, sort, sort_
 PLAIN = [TraceOpts(b, s, 0, 0, 0, 0, 0, 0) for b in (64, 128) for s in (0, 2)]
 PERSISTENT = [TraceOpts(64, s, 0, 1, r, c, 8192, f)
               for s in (0,) for r in (24, 32) for c in (64, 128, 256) for f in (0, 1)]
-WIDE = [TraceOpts(64, s, 0, 1, r, c, 8192, 2) for s in (0, 2) for r in (24, 32) for c in (64, 128, 256)]
+WIDE = [TraceOpts(64, s, 0, 1, r, c, w, 2) for s in (1, 2) for r in (24, 32) for c in (64, 128) for w in (8192, 16384)]
 DEFAULT_CANDIDATES = PLAIN + PERSISTENT + WIDE
 
 

@@ -379,34 +379,31 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
 // farthest first.  kStats: counts, per lockstep iteration, the distinct 4-wide nodes fetched
 // by the stepping lanes and the distinct triangles fetched by a leaf batch (summed over the
 // wavefront into counts[0] and counts[1]).
-// Per-lane stack of the 4-wide traversal: the first kWideShort entries in LDS (lane-interleaved,
-// conflict free), deeper ones in scratch; or all of it in scratch.
-constexpr int kWideShort = 12;
-
-template <bool kLds>
-struct WideStack;
+// Per-lane stack of the 4-wide traversal: the first entries in LDS (lane-interleaved, conflict
+// free), deeper ones in scratch; or all of it in scratch.
+// kLds = 0: all in scratch; otherwise the number of entries kept in LDS (12 for
+// HCC_STACK_SHORT, 24 for HCC_STACK_LDS).
+template <int kLds>
+struct WideStack {
+    uint32_t* lds;
+    uint32_t deep[kWideStack - kLds];
+    __device__ void init(uint32_t* l) { lds = l + __lane_id(); }
+    __device__ void push(uint32_t sp, uint32_t x) {
+        if (sp < (uint32_t)kLds) lds[sp * 64] = x;
+        else deep[sp - kLds] = x;
+    }
+    __device__ uint32_t pop(uint32_t sp) { return sp < (uint32_t)kLds ? lds[sp * 64] : deep[sp - kLds]; }
+};
 
 template <>
-struct WideStack<false> {
+struct WideStack<0> {
     uint32_t s[kWideStack];
     __device__ void init(uint32_t*) {}
     __device__ void push(uint32_t sp, uint32_t x) { s[sp] = x; }
     __device__ uint32_t pop(uint32_t sp) { return s[sp]; }
 };
 
-template <>
-struct WideStack<true> {
-    uint32_t* lds;
-    uint32_t deep[kWideStack - kWideShort];
-    __device__ void init(uint32_t* l) { lds = l + __lane_id(); }
-    __device__ void push(uint32_t sp, uint32_t x) {
-        if (sp < (uint32_t)kWideShort) lds[sp * 64] = x;
-        else deep[sp - kWideShort] = x;
-    }
-    __device__ uint32_t pop(uint32_t sp) { return sp < (uint32_t)kWideShort ? lds[sp * 64] : deep[sp - kWideShort]; }
-};
-
-template <bool kClosest, bool kStats, bool kLds>
+template <bool kClosest, bool kStats, int kLds>
 __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn, const Tri* __restrict__ tris,
                                                    uint32_t n_int, const float4* __restrict__ rays,
                                                    const uint32_t* __restrict__ perm, uint32_t n,
@@ -420,7 +417,7 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
     uint32_t next = cidx * chunk;
     uint32_t end = min(next + chunk, n);
     const uint64_t below = lanes_below();
-    __shared__ uint32_t s_stack[kLds ? kWideShort * 64 : 1];
+    __shared__ uint32_t s_stack[kLds ? kLds * 64 : 1];
     WideStack<kLds> stack;
     stack.init(s_stack);
     bool has = false;
@@ -611,15 +608,16 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
     const float4* r = (const float4*)rays;
     float4* h = (float4*)hits;
     if (o.flags & HCC_TRACE_WIDE) {
-        // stack: scratch (HCC_STACK_SCRATCH) or the first entries in LDS (HCC_STACK_SHORT / _LDS)
-        const bool lds = o.stack != HCC_STACK_SCRATCH && !kStats;
+        // stack: scratch (HCC_STACK_SCRATCH, and always when counting), the first 12 entries in
+        // LDS (HCC_STACK_SHORT) or the first 24 (HCC_STACK_LDS)
+        const int lds = kStats ? 0 : (o.stack == HCC_STACK_SHORT ? 12 : (o.stack == HCC_STACK_LDS ? 24 : 0));
 #define HCC_WIDE(CL, LD)                                                                                       \
     k_trace_wide<CL, kStats, LD><<<waves, 64, 0, s>>>(b->wnodes, b->tris, b->n_int, r, perm, n, h, occ, refill, \
                                                       chunk, counts)
         if (closest) {
-            if (lds) HCC_WIDE(true, true); else HCC_WIDE(true, false);
+            if (lds == 12) HCC_WIDE(true, 12); else if (lds == 24) HCC_WIDE(true, 24); else HCC_WIDE(true, 0);
         } else {
-            if (lds) HCC_WIDE(false, true); else HCC_WIDE(false, false);
+            if (lds == 12) HCC_WIDE(false, 12); else if (lds == 24) HCC_WIDE(false, 24); else HCC_WIDE(false, 0);
         }
 #undef HCC_WIDE
         HCC_HIP(hipGetLastError());
