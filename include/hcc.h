@@ -291,6 +291,11 @@ hcc_status hcc_batch_workspace(const hcc_batch_desc* batches, uint32_t nb, hcc_k
 hcc_status hcc_batch_run(const hcc_batch_desc* batches, uint32_t nb, hcc_key_mode mode, uint32_t key_bits,
                          const hcc_batch_opts* opts, void* d_ws, size_t ws_bytes, hcc_stream stream);
 
+/* Wait for the stream, then report in *h_ok whether the last hcc_batch_run on this workspace
+ * resolved every dependency inside its launch (1), or whether a bounded wait gave up (0: the
+ * results of that run are not valid; this indicates a library fault, never a user error). */
+hcc_status hcc_batch_check(const void* d_ws, hcc_stream stream, uint32_t* h_ok);
+
 /* ---------------------------------------------------------------------------------------
  * Request server with continuous batching (not in the paper: serving around its path).
  * A worker thread admits queued requests in arrival order while the device ray-state budget

@@ -458,6 +458,18 @@ def batch_run(batches, mode: int, key_bits: int = 32, opts: BatchOpts | None = N
     return ws
 
 
+lib.hcc_batch_check.argtypes = [_P, _P, C.POINTER(C.c_uint32)]
+lib.hcc_batch_check.restype = C.c_int
+
+
+def batch_check(ws, stream=None) -> bool:
+    """Wait for the stream; True when the last batch_run on this workspace resolved every
+    dependency inside its launch."""
+    ok = C.c_uint32()
+    _check(lib.hcc_batch_check(C.c_void_p(ws.data_ptr()), _stream(stream), C.byref(ok)))
+    return bool(ok.value)
+
+
 # ------------------------------------------------------------------------------ request server
 
 class ServerOpts(C.Structure):

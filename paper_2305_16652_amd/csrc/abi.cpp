@@ -38,6 +38,7 @@ hcc_status fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hcc_status batch_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, size_t* bytes);
 hcc_status batch_run(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, const hcc_batch_opts& o,
                      void* d_ws, size_t ws_bytes, hipStream_t stream);
+hcc_status batch_check(const void* d_ws, hipStream_t stream, uint32_t* ok);
 
 namespace {
 thread_local std::string g_error;
@@ -486,6 +487,12 @@ __attribute__((visibility("default"))) hcc_status hcc_batch_run(const hcc_batch_
     if (o.direct_min != 0 && o.direct_min < 65536)
         return fail(HCC_ERR_INVALID, "hcc_batch_run: opts.direct_min must be 0 or at least 65536");
     return batch_run(batches, nb, mode, key_bits, o, d_ws, ws_bytes, S(stream));
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_batch_check(const void* d_ws, hcc_stream stream,
+                                                                  uint32_t* h_ok) {
+    if (!d_ws || !h_ok) return fail(HCC_ERR_INVALID, "hcc_batch_check: null argument");
+    return batch_check(d_ws, S(stream), h_ok);
 }
 
 __attribute__((visibility("default"))) hcc_status hcc_select_mlhcc_cut(hcc_bvh bvh, uint32_t top, uint32_t low,

@@ -635,12 +635,10 @@ static Plan plan_batches(const hcc_batch_desc* d, uint32_t nb, uint32_t n_scenes
     const size_t ks = key_bits <= 32 ? 4 : 8;
     const uint32_t passes = mode == HCC_KEY_NONE ? 0 : (key_bits + 7) / 8;
     size_t off = 0;
-    P.scenes_off = off; off += al(sizeof(EngScene) * n_scenes);
-    P.batches_off = off; off += al(sizeof(EngBatch) * nb);
-    P.tables = off;
-    // zeroed region: queue counter, histograms, look-back, completion counters
+    // zeroed region first: queue counter and error flag (bytes 0 and 4 of every workspace),
+    // histograms, look-back state, completion counters
     P.zero_off = off;
-    off += 256;   // queue counter
+    off += 256;
     P.hist.resize(nb); P.lookback.resize(nb); P.done.resize(nb);
     for (uint32_t b = 0; b < nb; ++b) {
         const size_t tiles = (d[b].n + kTile - 1) / kTile;
@@ -649,6 +647,10 @@ static Plan plan_batches(const hcc_batch_desc* d, uint32_t nb, uint32_t n_scenes
         P.done[b] = off; off += al((passes + 1) * 4);
     }
     P.zero_bytes = off - P.zero_off;
+    // descriptor tables (copied from the host at launch)
+    P.scenes_off = off; off += al(sizeof(EngScene) * n_scenes);
+    P.batches_off = off; off += al(sizeof(EngBatch) * nb);
+    P.tables = off - P.scenes_off;
     P.keys_a.resize(nb); P.keys_b.resize(nb); P.vals_a.resize(nb); P.vals_b.resize(nb);
     for (uint32_t b = 0; b < nb; ++b) {
         const size_t n = d[b].n;
@@ -825,6 +827,9 @@ hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uin
         const hcc_status st = engine_launch(rest.data(), (uint32_t)rest.size(), mode, key_bits, o, d_ws, off, stream,
                                             pinned, pinned_bytes);
         if (st != HCC_OK) return st;
+    } else {   // no engine launch: still clear the error flag that hcc_batch_check reads
+        k_zero<<<1, 64, 0, stream>>>((uint32_t*)d_ws, 64);
+        HCC_HIP(hipGetLastError());
     }
     for (uint32_t b = 0; b < nb; ++b) {
         if (d[b].n < o.direct_min) continue;
@@ -856,9 +861,9 @@ static hcc_status engine_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t m
         staging.assign(P.tables, 0);
         host = staging.data();
     }
-    std::memcpy(host + P.scenes_off, T.hs.data(), sizeof(EngScene) * T.hs.size());
-    std::memcpy(host + P.batches_off, T.hb.data(), sizeof(EngBatch) * T.hb.size());
-    HCC_HIP(hipMemcpyAsync(ws, host, P.tables, hipMemcpyHostToDevice, stream));
+    std::memcpy(host, T.hs.data(), sizeof(EngScene) * T.hs.size());
+    std::memcpy(host + (P.batches_off - P.scenes_off), T.hb.data(), sizeof(EngBatch) * T.hb.size());
+    HCC_HIP(hipMemcpyAsync(ws + P.scenes_off, host, P.tables, hipMemcpyHostToDevice, stream));
     if (!pinned) HCC_HIP(hipStreamSynchronize(stream));
     const size_t zw = h.zero_words;
     k_zero<<<(unsigned)std::min<size_t>(2048, (zw + 255) / 256), 256, 0, stream>>>(h.zero, zw);
@@ -939,6 +944,15 @@ hcc_status graph_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uin
     std::memcpy(host + soff, T.hs.data(), sizeof(EngScene) * T.hs.size());
     std::memcpy(host + boff, T.hb.data(), sizeof(EngBatch) * T.hb.size());
     HCC_HIP(hipGraphLaunch(exec, stream));
+    return HCC_OK;
+}
+
+// The engine's error flag (word 1 of every workspace): nonzero when a bounded wait gave up.
+hcc_status batch_check(const void* d_ws, hipStream_t stream, uint32_t* ok) {
+    uint32_t flag = 0;
+    HCC_HIP(hipMemcpyAsync(&flag, (const char*)d_ws + 4, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    HCC_HIP(hipStreamSynchronize(stream));
+    *ok = flag == 0 ? 1u : 0u;
     return HCC_OK;
 }
 

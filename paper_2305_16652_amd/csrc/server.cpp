@@ -29,6 +29,7 @@ namespace hcc {
 size_t batch_table_bytes(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits);
 hcc_status batch_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, size_t* bytes);
 hcc_status engine_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, size_t* bytes);
+hcc_status batch_check(const void* d_ws, hipStream_t stream, uint32_t* ok);
 hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
                         const hcc_batch_opts& o, void* d_ws, size_t ws_bytes, hipStream_t stream, void* pinned,
                         size_t pinned_bytes);
@@ -257,7 +258,12 @@ void worker_loop(hcc_server_s* s) {
         for (auto& g : s->inflight) {
             if (!g.done) continue;
             const hipError_t q = hipEventQuery(g.done);
-            if (q == hipSuccess) finish_group(s, g, true);
+            if (q == hipSuccess) {
+                uint32_t ok = 1;
+                if (g.ws && hcc::batch_check(g.ws, g.stream, &ok) == HCC_OK && !ok)
+                    s->error = "an engine launch gave up waiting on a dependency";
+                finish_group(s, g, ok != 0);
+            }
             else if (q != hipErrorNotReady) finish_group(s, g, false);
         }
         s->inflight.erase(std::remove_if(s->inflight.begin(), s->inflight.end(),

@@ -59,7 +59,8 @@ def test_engine_matches_oracle_and_plain_path(H, scenes, mode, key_bits, cut, op
     key_mode = {"hcc": H.KEY_HCC, "twopoint": H.KEY_TWOPOINT, "none": 0}[mode]
     items = _batches(H, scenes, seed=key_bits + (opts[0] if opts else 0), key_cut=cut if mode == "hcc" else None)
     o = H.BatchOpts(*opts) if opts else None
-    H.batch_run([b for _, b, _ in items], key_mode, key_bits, opts=o)
+    ws = H.batch_run([b for _, b, _ in items], key_mode, key_bits, opts=o)
+    assert H.batch_check(ws)
     torch.cuda.synchronize()
     for s, b, rays in items:
         n = rays.shape[0]
@@ -94,7 +95,10 @@ def test_engine_direct_launches_for_large_batches(H, scenes, mode):
         rays = np.ascontiguousarray(np.resize(pool, (n, 8)), np.float32)
         items.append((s, H.Batch(s["bvh"], torch.from_numpy(rays).cuda(), closest,
                                  cut=s["cut32"] if mode == "hcc" else None), rays))
-    H.batch_run([b for _, b, _ in items], key_mode, 32, opts=H.BatchOpts(0, 0, 0, 0, 65536))
+    ws = H.batch_run([b for _, b, _ in items], key_mode, 32, opts=H.BatchOpts(0, 0, 0, 0, 65536))
+    assert H.batch_check(ws)
+    big = [b for _, b, _ in items if b.rays.shape[0] >= 65536]
+    assert H.batch_check(H.batch_run(big, key_mode, 32, opts=H.BatchOpts(0, 0, 0, 0, 65536)))   # no engine part
     torch.cuda.synchronize()
     for s, b, rays in items:
         perm = None
