@@ -301,8 +301,8 @@ hcc_status hcc_batch_check(const void* d_ws, hcc_stream stream, uint32_t* h_ok);
  * A worker thread admits queued requests in arrival order while the device ray-state budget
  * and the slot limit allow, launches each set of newly admitted requests on the next of its
  * streams (so later requests overlap with earlier ones still running) -- the small ones together
- * as one engine batch, each large one (direct_min) through the full-device kernels -- and
- * retires them when their completion events fire.  A request's budget charge is its rays and
+ * as one engine batch, each large one (direct_min), or a small one admitted alone, through the
+ * full-device kernels -- and retires them when their completion events fire.  A request's budget charge is its rays and
  * results plus the engine workspace for its size.  Results are exactly those of a lone
  * hcc_encode + hcc_sort + hcc_trace of the request.  plain = 1 runs one request at a time
  * through those three calls instead (the baseline).  Buffers named in a request stay owned by
@@ -322,7 +322,8 @@ typedef struct hcc_server_opts {
                                  counter clear, engine) kept per launch slot; 0 = three calls */
     uint32_t direct_min;      /* continuous mode: a request of at least this many rays runs through
                                  the full-device encode / sort / trace kernels on its own stream
-                                 instead of the engine (0 = 65536; 0xFFFFFFFF = never) */
+                                 instead of the engine (0 = 65536; 0xFFFFFFFF = never, and then
+                                 also a small request admitted alone shares the engine path) */
     hcc_batch_opts batch;     /* engine options */
 } hcc_server_opts;
 

@@ -307,9 +307,12 @@ void worker_loop(hcc_server_s* s) {
             }
             // large requests run through the full-device kernels, each on the next stream; the
             // rest go together into one engine launch
+            // (a request admitted alone has nothing to share a launch with: it goes direct too)
             std::vector<uint64_t> small;
+            size_t n_small = 0;
+            for (uint64_t id : admit) n_small += s->reqs[id].desc.n < s->opts.direct_min ? 1 : 0;
             for (uint64_t id : admit) {
-                if (s->reqs[id].desc.n < s->opts.direct_min) {
+                if (s->reqs[id].desc.n < s->opts.direct_min && (n_small > 1 || s->opts.direct_min == 0xFFFFFFFFu)) {
                     small.push_back(id);
                     continue;
                 }

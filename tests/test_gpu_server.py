@@ -102,7 +102,7 @@ def test_server_results_equal_lone_requests(H, scenes, variant, key_mode):
 def test_server_graph_replays_match_eager(H, scenes):
     """The captured launch graphs are replayed group after group; between rounds the test runs
     its own eager work (the lone path) and synchronises, and checks every round's results."""
-    srv = _server(H, 1, "graph", max_group=4, streams=2)
+    srv = _server(H, 1, "engine-only", max_group=4, streams=2)
     for rnd in range(4):
         reqs = _requests(H, scenes, 12, seed=100 + rnd)
         ids = [srv.submit(b) for _, b, _ in reqs]
