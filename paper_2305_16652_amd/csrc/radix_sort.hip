@@ -75,16 +75,16 @@ __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uin
     const uint32_t t = threadIdx.x;
     for (uint32_t i = t; i < passes * kRadix; i += kBlock) s_h[i] = 0;
     __syncthreads();
-    const uint64_t lt = lanemask_lt();
+    // one LDS atomic per key and pass: with 256 bins per pass, lanes of a wavefront rarely
+    // collide, and this is far fewer instructions than ballot-matching equal digits
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         const uint32_t idx = base + t;
-        const bool valid = idx < n;
-        const K k = valid ? keys[idx] : K(0);
+        if (idx >= n) continue;
+        const K k = keys[idx];
         for (uint32_t p = 0; p < passes; ++p) {
             const uint32_t nb = min(8u, key_bits - skip - 8u * p);
             const uint32_t d = (uint32_t)(k >> (skip + 8u * p)) & ((1u << nb) - 1u);
-            const uint64_t m = match_digit(d, nb, valid);
-            if (valid && (m & lt) == 0) atomicAdd(&s_h[p * kRadix + d], (uint32_t)__popcll(m));
+            atomicAdd(&s_h[p * kRadix + d], 1u);
         }
     }
     __syncthreads();
