@@ -91,7 +91,7 @@ typedef struct hcc_hit { float t; uint32_t prim; float u, v; } hcc_hit;   /* mis
 typedef struct hcc_trace_opts {
     uint32_t block;           /* one-ray-per-lane launch: threads per block, 64, 128 or 256 (0 = 64) */
     uint32_t stack;           /* hcc_stack_mode */
-    uint32_t xcd_remap;       /* 1 = give each XCD a contiguous range of rays (0 = hardware order) */
+    uint32_t xcd_remap;       /* 1 = give each XCD a contiguous range of rays / chunks (0 = hardware order) */
     uint32_t persistent;      /* 1 = persistent wavefronts that refill idle lanes with new rays */
     uint32_t refill;          /* persistent: refill when at least this many lanes are idle, 1..64 (0 = 16) */
     uint32_t chunk;           /* persistent: consecutive rays a wavefront owns at a time, >= 64 (0 = 256) */
@@ -101,9 +101,9 @@ typedef struct hcc_trace_opts {
 
 /* hcc_trace_opts.flags */
 #define HCC_TRACE_SPECULATE 1u  /* persistent BVH2: keep descending while one leaf is postponed */
-#define HCC_TRACE_WIDE 2u       /* traverse the 4-wide nodes (the BVH2 collapsed two levels at a time,
-                                   built by hcc_build_bvh) with persistent wavefronts; refill, chunk
-                                   and waves apply, block, stack and xcd_remap do not */
+#define HCC_TRACE_WIDE 2u       /* traverse the 4-wide nodes (the BVH2 collapsed top down, built by
+                                   hcc_build_bvh) with persistent wavefronts; refill, chunk, waves,
+                                   stack and xcd_remap apply, block does not */
 
 /* ---------------------------------------------------------------------------------------
  * hcc_build_bvh -- linear BVH over n_tris triangles (Section 3.1: the acceleration structure

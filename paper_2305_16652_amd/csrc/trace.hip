@@ -220,12 +220,14 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
                                                          uint32_t n_int, const float4* __restrict__ rays,
                                                          const uint32_t* __restrict__ perm, uint32_t n,
                                                          float4* __restrict__ hits, uint8_t* __restrict__ occ,
-                                                         uint32_t refill, uint32_t chunk,
+                                                         uint32_t refill, uint32_t chunk, uint32_t remap,
                                                          unsigned long long* __restrict__ counts) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     __shared__ uint32_t s_stack[lds_entries<kStack>() * 64];
     const uint32_t nchunks = (n + chunk - 1) / chunk;
-    uint32_t cidx = blockIdx.x;
+    // remap: the wavefronts the hardware deals to one XCD take consecutive chunks, so each
+    // XCD's L2 sees one stretch of the (sorted) order at a time
+    uint32_t cidx = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     if (cidx >= nchunks) return;
     uint32_t next = cidx * chunk;
     uint32_t end = min(next + chunk, n);
@@ -408,11 +410,13 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
                                                    uint32_t n_int, const float4* __restrict__ rays,
                                                    const uint32_t* __restrict__ perm, uint32_t n,
                                                    float4* __restrict__ hits, uint8_t* __restrict__ occ,
-                                                   uint32_t refill, uint32_t chunk,
+                                                   uint32_t refill, uint32_t chunk, uint32_t remap,
                                                    unsigned long long* __restrict__ counts) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     const uint32_t nchunks = (n + chunk - 1) / chunk;
-    uint32_t cidx = blockIdx.x;
+    // remap: the wavefronts the hardware deals to one XCD take consecutive chunks, so each
+    // XCD's L2 sees one stretch of the (sorted) order at a time
+    uint32_t cidx = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     if (cidx >= nchunks) return;
     uint32_t next = cidx * chunk;
     uint32_t end = min(next + chunk, n);
@@ -613,7 +617,7 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
         const int lds = kStats ? 0 : (o.stack == HCC_STACK_SHORT ? 12 : (o.stack == HCC_STACK_LDS ? 24 : 0));
 #define HCC_WIDE(CL, LD)                                                                                       \
     k_trace_wide<CL, kStats, LD><<<waves, 64, 0, s>>>(b->wnodes, b->tris, b->n_int, r, perm, n, h, occ, refill, \
-                                                      chunk, counts)
+                                                      chunk, o.xcd_remap, counts)
         if (closest) {
             if (lds == 12) HCC_WIDE(true, 12); else if (lds == 24) HCC_WIDE(true, 24); else HCC_WIDE(true, 0);
         } else {
@@ -627,11 +631,12 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
     do {                                                                                                      \
         if (o.flags & HCC_TRACE_SPECULATE)                                                                    \
             k_trace_persistent<CL, STK, true, kStats><<<waves, 64, 0, s>>>(b->nodes, b->tris, b->n_int, r, perm, \
-                                                                           n, h, occ, refill, chunk, counts);  \
+                                                                           n, h, occ, refill, chunk,           \
+                                                                           o.xcd_remap, counts);               \
         else                                                                                                  \
             k_trace_persistent<CL, STK, false, kStats><<<waves, 64, 0, s>>>(b->nodes, b->tris, b->n_int, r,      \
                                                                             perm, n, h, occ, refill, chunk,     \
-                                                                            counts);                            \
+                                                                            o.xcd_remap, counts);               \
     } while (0)
     if (kStats && o.stack != HCC_STACK_SCRATCH)
         return fail(HCC_ERR_UNSUPPORTED, "hcc_trace_count: counting runs with the scratch stack only");

@@ -174,7 +174,9 @@ OPTS = [(128, 1, 0, 0, 0, 0, 0), (64, 1, 1, 0, 0, 0, 0), (256, 1, 0, 0, 0, 0, 0)
         (0, 0, 0, 1, 32, 64, 0, 1), (0, 2, 0, 1, 5, 128, 11, 1),
         # 4-wide nodes (flags bit 1), with and without the persistent field, odd chunk / refill / waves
         (0, 0, 0, 1, 16, 256, 0, 2), (64, 1, 1, 0, 32, 64, 0, 2), (0, 0, 0, 1, 1, 64, 3, 2),
-        (0, 2, 0, 1, 64, 1000, 7, 3), (0, 1, 0, 1, 16, 64, 0, 2), (0, 2, 0, 1, 1, 64, 5, 2)]
+        (0, 2, 0, 1, 64, 1000, 7, 3), (0, 1, 0, 1, 16, 64, 0, 2), (0, 2, 0, 1, 1, 64, 5, 2),
+        # XCD-contiguous chunk order for the persistent and 4-wide kernels
+        (0, 2, 1, 1, 32, 64, 0, 2), (0, 0, 1, 1, 16, 256, 13, 1)]
 WIDE = (0, 0, 0, 1, 32, 64, 0, 2)
 
 
