@@ -23,7 +23,7 @@ THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
 # bench.py's default launch configuration (block, stack, remap, persistent, refill, chunk, waves, flags);
 # the autotuner picks among these and the one-ray-per-lane launch, which test_gpu_parity covers
 BENCH_OPTS = (64, 0, 0, 1, 32, 64, 8192, 1)
-WIDE_OPTS = (64, 0, 0, 1, 24, 128, 8192, 2)       # the 4-wide traversal
+WIDE_OPTS = (64, 2, 0, 1, 32, 64, 8192, 2)        # the 4-wide traversal, LDS short stack (bench's pick)
 
 
 def _say(msg):
