@@ -289,7 +289,11 @@ __global__ __launch_bounds__(256) void k_wide_level(const uint32_t* __restrict__
             ref[j] = u >= n_int ? (kWideLeaf | (u - n_int)) : u;
             if (u < n_int) next[atomicAdd(next_count, 1u)] = u;
         } else {
-            for (int a = 0; a < 3; ++a) lo[a][j] = hi[a][j] = 0.0f;
+            // inverted box: rejected by the sign-selected child test without a check of ref
+            for (int a = 0; a < 3; ++a) {
+                lo[a][j] = INFINITY;
+                hi[a][j] = -INFINITY;
+            }
             ref[j] = kWideEmpty;
         }
     }

@@ -16,6 +16,7 @@
 // and observed with an agent-scope load + acquire fence.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "hcc_internal.h"
@@ -423,8 +424,10 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
     uint32_t rid = 0, node = kNone, sp = 0, best_prim = kMissPrim, pnode = 0, pmask = 0;
     float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0, tmin = 0, tmax = 0;
     float best_t = 0, best_u = 0, best_v = 0;
+    WideRay wr{0, 0, 0, false};
     bool found = false;
     const uint32_t n_int = sc.n_int;
+    const bool fast_nodes = n_int <= kWideFastNodes;
     auto test_tri = [&](uint32_t slot) {
         const Tri tr = sc.tris[slot];
         const uint32_t prim = __float_as_uint(tr.r.y);
@@ -451,6 +454,7 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
                         ox = ra.x; oy = ra.y; oz = ra.z; tmin = ra.w;
                         dx = rb.x; dy = rb.y; dz = rb.z; tmax = rb.w;
                         ix = 1.0f / dx; iy = 1.0f / dy; iz = 1.0f / dz;
+                        wr = wide_ray(ox, oy, oz, ix, iy, iz);
                         best_t = tmax; best_u = 0.0f; best_v = 0.0f; best_prim = kMissPrim;
                         found = false;
                         sp = 0;
@@ -468,19 +472,16 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
                 break;
             }
         }
-        if (has && node != kNone && pmask == 0) {
-            const Node4 nd = sc.wnodes[node];
-            const float lim = closest ? best_t : tmax;
-            const uint4 r = nd.ref;
-            float t0, t1, t2, t3;
-            const bool h0 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.x, nd.loy.x, nd.loz.x, nd.hix.x, nd.hiy.x,
-                                 nd.hiz.x, t0) && r.x != kWideEmpty;
-            const bool h1 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.y, nd.loy.y, nd.loz.y, nd.hix.y, nd.hiy.y,
-                                 nd.hiz.y, t1) && r.y != kWideEmpty;
-            const bool h2 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.z, nd.loy.z, nd.loz.z, nd.hix.z, nd.hiy.z,
-                                 nd.hiz.z, t2) && r.z != kWideEmpty;
-            const bool h3 = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.w, nd.loy.w, nd.loz.w, nd.hix.w, nd.hiy.w,
-                                 nd.hiz.w, t3) && r.w != kWideEmpty;
+        const bool step = has && node != kNone && pmask == 0;
+        // the node step is specialised on the (wavefront-uniform) form of the child test
+        auto node_step = [&](auto kind) {
+            uint4 r;
+            bool hh[4];
+            float tt[4];
+            wide_test<decltype(kind)::value>(sc.wnodes, node, wr, ox, oy, oz, ix, iy, iz, tmin,
+                                             closest ? best_t : tmax, r, hh, tt);
+            const bool h0 = hh[0], h1 = hh[1], h2 = hh[2], h3 = hh[3];
+            const float t0 = tt[0], t1 = tt[1], t2 = tt[2], t3 = tt[3];
             const bool l0 = h0 && (r.x & kWideLeaf), l1 = h1 && (r.y & kWideLeaf);
             const bool l2 = h2 && (r.z & kWideLeaf), l3 = h3 && (r.w & kWideLeaf);
             const uint32_t lm = (l0 ? 1u : 0u) | (l1 ? 2u : 0u) | (l2 ? 4u : 0u) | (l3 ? 8u : 0u);
@@ -503,6 +504,11 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
             if (i0 < n_int) node = i0;
             else if (sp == 0) node = kNone;
             else node = pop(--sp);
+        };
+        if (fast_nodes && __ballot(step && !wr.fast) == 0) {
+            if (step) node_step(std::true_type{});
+        } else {
+            if (step) node_step(std::false_type{});
         }
         const bool can_step = has && node != kNone && pmask == 0;
         const uint64_t busy = __ballot(has);

@@ -73,6 +73,77 @@ __device__ __forceinline__ bool slab(float ox, float oy, float oz, float ix, flo
     return tnear <= tfar;
 }
 
+// Child-box test of a 4-wide node.  For a ray with a finite origin and an inverse direction that
+// is finite and nonzero on every axis ("fast" ray), the entry plane of axis a is lo_a when 1/d_a
+// has its sign bit clear and hi_a otherwise, so (entry - o_a) * inv_a is exactly min(t0, t1) of
+// the slab test above, and the exit plane gives max(t0, t1): the slab's per-axis min/max pairs
+// are replaced by choosing which plane to fetch.  Entry planes sit at byte offsets x: 0 or 48,
+// y: 16 or 64, z: 32 or 80 inside the node; the exit plane of an axis is at the entry offset XOR
+// 48 / 80 / 112.  Empty slots hold the inverted box (+inf, -inf): for a fast ray (+-inf - o) * inv
+// is an infinity, never NaN, so such a slot gets entry +inf and exit -inf and is rejected without
+// looking at ref.  Any other ray needs the slab test itself (where 0 * inf can make an axis NaN)
+// and the check of ref.
+struct WideRay {
+    uint32_t ex, ey, ez;   // entry-plane byte offsets within a node
+    bool fast;
+};
+
+__device__ __forceinline__ bool finite_nonzero(float x) { return fabsf(x) < INFINITY && x != 0.0f; }
+
+__device__ __forceinline__ WideRay wide_ray(float ox, float oy, float oz, float ix, float iy, float iz) {
+    WideRay w;
+    w.fast = fabsf(ox) < INFINITY && fabsf(oy) < INFINITY && fabsf(oz) < INFINITY && finite_nonzero(ix) &&
+             finite_nonzero(iy) && finite_nonzero(iz);
+    w.ex = signbit(ix) ? 48u : 0u;
+    w.ey = signbit(iy) ? 64u : 16u;
+    w.ez = signbit(iz) ? 80u : 32u;
+    return w;
+}
+
+// Byte offsets into the node array are 32-bit on the selected-plane path.
+constexpr uint32_t kWideFastNodes = 0xFFFFFFFFu / (uint32_t)sizeof(Node4);
+
+// The four child tests of node `node` for the calling lane: kFast, the selected-plane form (only
+// for fast rays, and node arrays whose byte offsets fit 32 bits); else the slab test.
+template <bool kFast>
+__device__ __forceinline__ void wide_test(const Node4* __restrict__ wn, uint32_t node, const WideRay& w, float ox,
+                                          float oy, float oz, float ix, float iy, float iz, float tmin, float lim,
+                                          uint4& ref, bool (&h)[4], float (&t)[4]) {
+    if constexpr (kFast) {
+        const char* base = reinterpret_cast<const char*>(wn);
+        const uint32_t at = node * (uint32_t)sizeof(Node4);
+        const float4 nx = *reinterpret_cast<const float4*>(base + (at + w.ex));
+        const float4 fx = *reinterpret_cast<const float4*>(base + (at + (w.ex ^ 48u)));
+        const float4 ny = *reinterpret_cast<const float4*>(base + (at + w.ey));
+        const float4 fy = *reinterpret_cast<const float4*>(base + (at + (w.ey ^ 80u)));
+        const float4 nz = *reinterpret_cast<const float4*>(base + (at + w.ez));
+        const float4 fz = *reinterpret_cast<const float4*>(base + (at + (w.ez ^ 112u)));
+        ref = *reinterpret_cast<const uint4*>(base + (at + 96u));
+        const float enx[4] = {nx.x, nx.y, nx.z, nx.w}, eny[4] = {ny.x, ny.y, ny.z, ny.w};
+        const float enz[4] = {nz.x, nz.y, nz.z, nz.w}, exx[4] = {fx.x, fx.y, fx.z, fx.w};
+        const float exy[4] = {fy.x, fy.y, fy.z, fy.w}, exz[4] = {fz.x, fz.y, fz.z, fz.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float tn = fmaxf(fmaxf(fmaxf((enx[j] - ox) * ix, (eny[j] - oy) * iy), (enz[j] - oz) * iz), tmin);
+            const float tf = fminf(fminf(fminf((exx[j] - ox) * ix, (exy[j] - oy) * iy), (exz[j] - oz) * iz) *
+                                       0x1.000006p+0f, lim);
+            t[j] = tn;
+            h[j] = tn <= tf;
+        }
+    } else {
+        const Node4 nd = wn[node];
+        ref = nd.ref;
+        h[0] = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.x, nd.loy.x, nd.loz.x, nd.hix.x, nd.hiy.x, nd.hiz.x,
+                    t[0]) && ref.x != kWideEmpty;
+        h[1] = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.y, nd.loy.y, nd.loz.y, nd.hix.y, nd.hiy.y, nd.hiz.y,
+                    t[1]) && ref.y != kWideEmpty;
+        h[2] = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.z, nd.loy.z, nd.loz.z, nd.hix.z, nd.hiy.z, nd.hiz.z,
+                    t[2]) && ref.z != kWideEmpty;
+        h[3] = slab(ox, oy, oz, ix, iy, iz, tmin, lim, nd.lox.w, nd.loy.w, nd.loz.w, nd.hix.w, nd.hiy.w, nd.hiz.w,
+                    t[3]) && ref.w != kWideEmpty;
+    }
+}
+
 // Moller-Trumbore, double sided, float32, fixed operation order, no FMA contraction.
 __device__ __forceinline__ bool tri_test(const Tri& tr, float ox, float oy, float oz, float dx, float dy, float dz,
                                          float tmin, float tmax, float& t, float& u, float& v) {

@@ -296,6 +296,21 @@ def test_degenerate_rays(H, gpu_bvh, tiny):
                               O.encode_twopoint(rays, O.scene_box(tris), kb))
 
 
+def test_nonfinite_origins(H, gpu_bvh, tiny):
+    """Rays with an infinite or NaN origin component, in the same wavefronts as ordinary rays:
+    the 4-wide kernels must give them the slab test (whose NaN handling the oracle shares), while
+    the ordinary rays around them keep the selected-plane child test."""
+    rays = tiny["secondary"][:2048].copy()
+    rays[7::64, 0] = np.nan
+    rays[21::64, 1] = np.inf
+    rays[40::64, 2] = -np.inf
+    tris = tiny["spec"].tris
+    for o in (None, H.TraceOpts(*WIDE), H.TraceOpts(64, 2, 0, 1, 32, 64, 0, H.TRACE_WIDE)):
+        assert_closest(H.trace(gpu_bvh, _dev(rays), opts=o).cpu().numpy(), O.trace(tiny["ob"], rays), rays, tris)
+        assert_any(H.trace(gpu_bvh, _dev(rays), closest=False, opts=o).cpu().numpy(),
+                   O.trace(tiny["ob"], rays, closest=False))
+
+
 def test_empty_inputs(H, gpu_bvh):
     empty = torch.empty((0, 8), dtype=torch.float32, device="cuda")
     cut = H.select_cut(gpu_bvh, 8)
