@@ -68,6 +68,11 @@ __global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
     for (; i < n; i += stride) p[i] = v;
 }
 
+// Digit histograms of every pass in one read of the keys.  Thread g takes the four consecutive
+// keys 4g .. 4g+3 and, per pass, adds each run of equal digits among them with one LDS atomic;
+// when all 256 keys of a full wavefront share the digit, one lane adds 256.  Keys are skewed
+// and locally coherent (many rays share a code, neighbours often do), so this keeps most
+// lanes of a wavefront from hitting one bin in the same atomic.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint32_t n, uint32_t key_bits,
                                                  uint32_t skip, uint32_t passes, uint32_t* __restrict__ hist) {
@@ -75,16 +80,49 @@ __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uin
     const uint32_t t = threadIdx.x;
     for (uint32_t i = t; i < passes * kRadix; i += kBlock) s_h[i] = 0;
     __syncthreads();
-    // one LDS atomic per key and pass: with 256 bins per pass, lanes of a wavefront rarely
-    // collide, and this is far fewer instructions than ballot-matching equal digits
-    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
-        const uint32_t idx = base + t;
-        if (idx >= n) continue;
-        const K k = keys[idx];
+    const uint32_t groups = (n + 3u) / 4u, full = n / 4u;
+    const bool aligned = ((uintptr_t)keys & 15u) == 0;
+    for (uint32_t base = blockIdx.x * kBlock; base < groups; base += gridDim.x * kBlock) {
+        const uint32_t g = base + t;
+        // keys of this thread: a prefix of the four is valid
+        const uint32_t nv = g < full ? 4u : (g < groups ? n - 4u * g : 0u);
+        K kk[4];
+        if (nv == 4u && aligned && sizeof(K) == 4) {
+            const uint4 q = *reinterpret_cast<const uint4*>(keys + 4 * (size_t)g);
+            kk[0] = (K)q.x; kk[1] = (K)q.y; kk[2] = (K)q.z; kk[3] = (K)q.w;
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) kk[j] = j < nv ? keys[4 * (size_t)g + j] : K(0);
+        }
+        // this thread's wavefront covers 64 full groups
+        const bool wave_full = (base + (t & ~63u) + 64u) <= full;
         for (uint32_t p = 0; p < passes; ++p) {
-            const uint32_t nb = min(8u, key_bits - skip - 8u * p);
-            const uint32_t d = (uint32_t)(k >> (skip + 8u * p)) & ((1u << nb) - 1u);
-            atomicAdd(&s_h[p * kRadix + d], 1u);
+            const uint32_t sh = skip + 8u * p;
+            const uint32_t msk = (1u << min(8u, key_bits - sh)) - 1u;
+            uint32_t d[4];
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) d[j] = (uint32_t)(kk[j] >> sh) & msk;
+            uint32_t* h = s_h + p * kRadix;
+            const uint32_t v0 = __builtin_amdgcn_readfirstlane(d[0]);
+            const bool same = d[0] == v0 && d[1] == v0 && d[2] == v0 && d[3] == v0;
+            if (wave_full && __ballot(same) == ~0ull) {
+                if ((t & 63u) == 0) atomicAdd(&h[v0], 256u);
+                continue;
+            }
+            uint32_t cur = d[0], run = nv ? 1u : 0u;
+#pragma unroll
+            for (uint32_t j = 1; j < 4; ++j) {
+                if (j < nv) {
+                    if (d[j] == cur) {
+                        ++run;
+                    } else {
+                        atomicAdd(&h[cur], run);
+                        cur = d[j];
+                        run = 1u;
+                    }
+                }
+            }
+            if (run) atomicAdd(&h[cur], run);
         }
     }
     __syncthreads();
@@ -158,18 +196,33 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ kin, c
         __hip_atomic_store(mine, kFlagIncl | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
         __hip_atomic_store(mine, kFlagAgg | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // walk back over the earlier tiles four at a time (four loads in flight per round trip);
+        // tile 0 always holds an inclusive prefix, so the walk ends at or above it
+        constexpr int kLookWindow = 4;
         int64_t j = (int64_t)tile - 1;
         while (true) {
-            const uint32_t x = __hip_atomic_load(lookback + (size_t)j * kRadix + d, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t f = x & ~kCountMask;
-            if (f == 0) {
-                __builtin_amdgcn_s_sleep(1);
-                continue;
+            uint32_t x[kLookWindow];
+#pragma unroll
+            for (int q = 0; q < kLookWindow; ++q)
+                x[q] = j - q >= 0 ? __hip_atomic_load(lookback + (size_t)(j - q) * kRadix + d, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)
+                                  : kFlagIncl;
+            int used = kLookWindow;
+            bool done = false;
+#pragma unroll
+            for (int q = 0; q < kLookWindow; ++q) {
+                if (done || used < kLookWindow) continue;
+                const uint32_t f = x[q] & ~kCountMask;
+                if (f == 0) {
+                    used = q;          // not yet published: take what came before, poll again
+                } else {
+                    excl += x[q] & kCountMask;
+                    done = f == kFlagIncl;
+                }
             }
-            excl += x & kCountMask;
-            if (f == kFlagIncl) break;
-            --j;
+            if (done) break;
+            j -= used;
+            if (used < kLookWindow) __builtin_amdgcn_s_sleep(1);
         }
         __hip_atomic_store(mine, kFlagIncl | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -312,7 +365,7 @@ hcc_status run_sort(const K* keys, uint32_t key_bits, uint32_t skip, uint32_t n,
     const size_t zero_words = (L.total - L.hist) / 4;
     k_fill_u32<<<dim3((unsigned)std::min<size_t>(1024, (zero_words + 255) / 256)), dim3(256), 0, stream>>>(
         hist, zero_words, 0u);
-    const uint32_t hist_blocks = std::min<uint32_t>(2048u, (n + kBlock - 1) / kBlock);
+    const uint32_t hist_blocks = std::min<uint32_t>(2048u, ((n + 3) / 4 + kBlock - 1) / kBlock);
     k_hist<K><<<dim3(hist_blocks), dim3(kBlock), 0, stream>>>(keys, n, key_bits, skip, passes, hist);
 
     K* final_keys = sorted_keys ? sorted_keys : (K*)(ws + L.keys_a);

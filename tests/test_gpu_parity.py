@@ -150,6 +150,18 @@ def test_sort_bit_exact(H, n, key_bits, kind):
     assert np.array_equal(_keys_np(sk, key_bits), keys[p.astype(np.int64)])
 
 
+@pytest.mark.parametrize("kind", ["few", "uniform"])
+def test_sort_unaligned_keys(H, kind):
+    """Keys starting 4 bytes past a 16-byte boundary (the histogram reads them one at a time)."""
+    n = 70_001
+    keys = _rand_keys(n, 32, kind, seed=11)
+    buf = torch.from_numpy(np.concatenate([np.zeros(1, np.uint32), keys]).view(np.int32)).cuda()
+    dt = buf[1:]
+    assert dt.data_ptr() % 16 == 4
+    perm = H.sort(dt, 32)
+    assert np.array_equal(perm.cpu().numpy().view(np.uint32), O.sort(keys))
+
+
 def test_sort_hcc_keys_match_oracle(H, gpu_bvh, tiny):
     cut = H.select_cut(gpu_bvh, 64)
     rays = _dev(tiny["secondary"])
