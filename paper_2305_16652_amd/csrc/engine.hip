@@ -42,7 +42,7 @@ struct EngScene {
 };
 
 struct EngHeader {
-    uint32_t nb, total_items, mode, key_bits, passes, refill, pad0, pad1;
+    uint32_t nb, total_items, mode, key_bits, passes, refill, total_tiles, pad1;
     uint32_t* zero;        // region cleared before the engine runs (starts with the queue counter)
     uint32_t* queue;
     uint64_t zero_words;
@@ -59,7 +59,8 @@ struct EngBatch {
     uint32_t* hist;        // passes x 256
     uint32_t* lookback;    // passes x tiles x 256
     uint32_t* done;        // passes + 1 completion counters
-    uint32_t scene, n, closest, tiles, trace_items, item0, items, chunk;   // chunk: rays per trace item
+    // tile0 / trace0: tiles / trace items of the batches before this one; chunk: rays per trace item
+    uint32_t scene, n, closest, tiles, trace_items, tile0, trace0, chunk;
 };
 
 namespace {
@@ -544,8 +545,8 @@ __device__ __forceinline__ void trace_range_wide(const EngScene& sc, const EngBa
 
 template <typename K, bool kWide>
 __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
-                                            uint32_t nb, uint32_t total_items, uint32_t* queue, uint32_t mode,
-                                            uint32_t key_bits, uint32_t passes, uint32_t refill) {
+                                            uint32_t nb, uint32_t total_items, uint32_t total_tiles, uint32_t* queue,
+                                            uint32_t mode, uint32_t key_bits, uint32_t passes, uint32_t refill) {
     __shared__ CutBox s_cut[64];
     __shared__ uint32_t s_whist[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
@@ -554,54 +555,60 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
     uint16_t* s_rank = reinterpret_cast<uint16_t*>(s_share);
     uint32_t* s_stk = s_share;
     __shared__ uint32_t s_item;
+    // Items are phase-major: the encode tiles of every batch, then the tiles of sort pass 0 of
+    // every batch, ..., then the trace items of every batch.  An item depends only on its own
+    // batch's previous phase, which was handed out before the whole current phase, so waits are
+    // rare (only the last batches of a phase can still be running) and never circular.
+    const uint32_t sort_items = mode == HCC_KEY_NONE ? 0u : (passes + 1) * total_tiles;
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
         __syncthreads();
         const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);   // wave-uniform: scalar from here
         __syncthreads();
         if (item >= total_items) break;
-        // batch owning this item (item0 ascending)
+        const bool sorting = item < sort_items;
+        const uint32_t phase = sorting ? item / max(total_tiles, 1u) : 0u;
+        const uint32_t r = sorting ? item - phase * total_tiles : item - sort_items;
+        // batch owning position r of this phase: the last one starting at or before it
         uint32_t lo = 0, hi = nb - 1;
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) >> 1;
-            if (batches[mid].item0 <= item) lo = mid; else hi = mid - 1;
+            if ((sorting ? batches[mid].tile0 : batches[mid].trace0) <= r) lo = mid; else hi = mid - 1;
         }
         const EngBatch& bt = batches[lo];
         const EngScene& sc = scenes[bt.scene];
-        const uint32_t j = item - bt.item0;
-        if (mode == HCC_KEY_NONE) {
-            if (kWide)
-                trace_range_wide(sc, bt, nullptr, j * bt.chunk, min(bt.n, (j + 1) * bt.chunk), refill, s_stk);
-            else
-                trace_range(sc, bt, nullptr, j * bt.chunk, min(bt.n, (j + 1) * bt.chunk), refill);
-            continue;
-        }
-        const uint32_t tiles = bt.tiles;
-        if (j < tiles) {
-            encode_tile<K>(sc, bt, j, mode, key_bits, passes, s_cut);
-            signal(bt.done);
-        } else if (j < tiles * (1 + passes)) {
-            const uint32_t p = (j - tiles) / tiles, tile = (j - tiles) % tiles;
-            wait_count(bt.done + p, tiles, queue + 1);
-            scatter_tile<K>(bt, tile, p, key_bits, s_whist, s_gbase, s_rank, queue + 1);
-            signal(bt.done + p + 1);
-        } else {
-            const uint32_t c = j - tiles * (1 + passes);
-            wait_count(bt.done + passes, tiles, queue + 1);
-            const uint32_t* perm = ((passes - 1) & 1) ? bt.vals_a : bt.vals_b;
+        if (!sorting) {
+            const uint32_t c = r - bt.trace0;
+            const uint32_t* perm = nullptr;
+            if (mode != HCC_KEY_NONE) {
+                wait_count(bt.done + passes, bt.tiles, queue + 1);
+                perm = ((passes - 1) & 1) ? bt.vals_a : bt.vals_b;
+            }
             if (kWide)
                 trace_range_wide(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill, s_stk);
             else
                 trace_range(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill);
+            continue;
+        }
+        const uint32_t tile = r - bt.tile0;
+        if (phase == 0) {
+            encode_tile<K>(sc, bt, tile, mode, key_bits, passes, s_cut);
+            signal(bt.done);
+        } else {
+            const uint32_t p = phase - 1;
+            wait_count(bt.done + p, bt.tiles, queue + 1);
+            scatter_tile<K>(bt, tile, p, key_bits, s_whist, s_gbase, s_rank, queue + 1);
+            signal(bt.done + p + 1);
         }
     }
 }
 
 template <typename K, bool kWide>
 __global__ __launch_bounds__(64) void k_engine(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
-                                               uint32_t nb, uint32_t total_items, uint32_t* queue, uint32_t mode,
+                                               uint32_t nb, uint32_t total_items, uint32_t total_tiles,
+                                               uint32_t* queue, uint32_t mode,
                                                uint32_t key_bits, uint32_t passes, uint32_t refill) {
-    engine_loop<K, kWide>(scenes, batches, nb, total_items, queue, mode, key_bits, passes, refill);
+    engine_loop<K, kWide>(scenes, batches, nb, total_items, total_tiles, queue, mode, key_bits, passes, refill);
 }
 
 __global__ void k_zero(uint32_t* p, size_t n) {
@@ -614,7 +621,8 @@ __global__ void k_zero(uint32_t* p, size_t n) {
 template <typename K, bool kWide>
 __global__ __launch_bounds__(64) void k_engine_hdr(const EngHeader* __restrict__ h, const EngScene* __restrict__ scenes,
                                                    const EngBatch* __restrict__ batches) {
-    engine_loop<K, kWide>(scenes, batches, h->nb, h->total_items, h->queue, h->mode, h->key_bits, h->passes,
+    engine_loop<K, kWide>(scenes, batches, h->nb, h->total_items, h->total_tiles, h->queue, h->mode, h->key_bits,
+                          h->passes,
                           h->refill);
 }
 
@@ -744,7 +752,7 @@ static hcc_status fill_tables(const hcc_batch_desc* d, uint32_t nb, uint32_t mod
         }
     }
     T.hb.assign(nb, EngBatch{});
-    uint32_t item = 0;
+    uint32_t tiles_before = 0, trace_before = 0;
     for (uint32_t b = 0; b < nb; ++b) {
         EngBatch& e = T.hb[b];
         e.rays = (const float4*)d[b].d_rays;
@@ -770,13 +778,15 @@ static hcc_status fill_tables(const hcc_batch_desc* d, uint32_t nb, uint32_t mod
             e.keys_a = e.keys_b = nullptr;
             e.vals_a = e.vals_b = nullptr;
         }
-        e.item0 = item;
-        e.items = mode == HCC_KEY_NONE ? e.trace_items : e.tiles * (1 + passes) + e.trace_items;
-        item += e.items;
+        e.tile0 = tiles_before;
+        e.trace0 = trace_before;
+        tiles_before += e.tiles;
+        trace_before += e.trace_items;
     }
     EngHeader& h = T.hdr;
     h.nb = nb;
-    h.total_items = item;
+    h.total_tiles = tiles_before;
+    h.total_items = (mode == HCC_KEY_NONE ? 0u : tiles_before * (1 + passes)) + trace_before;
     h.mode = mode;
     h.key_bits = key_bits;
     h.passes = passes;
@@ -879,8 +889,8 @@ static hcc_status engine_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t m
     const unsigned grid = std::max(1u, std::min(waves, h.total_items));
     const bool wide = (o.flags & HCC_TRACE_WIDE) != 0;
 #define HCC_ENGINE(KT, WD)                                                                                        \
-    k_engine<KT, WD><<<grid, 64, 0, stream>>>(dsc, dbt, nb, h.total_items, h.queue, mode, key_bits, h.passes,   \
-                                              h.refill)
+    k_engine<KT, WD><<<grid, 64, 0, stream>>>(dsc, dbt, nb, h.total_items, h.total_tiles, h.queue, mode,       \
+                                              key_bits, h.passes, h.refill)
     if (key_bits <= 32) {
         if (wide) HCC_ENGINE(uint32_t, true); else HCC_ENGINE(uint32_t, false);
     } else {
