@@ -471,7 +471,7 @@ def run_batched(H, args):
         ws = H.batch_run(batches, H.KEY_HCC, K)
         for chunk in (128, 256, 512):
             for refill in (24, 32):
-                for flags in (0, H.TRACE_WIDE):
+                for flags in (0, H.TRACE_WIDE, H.TRACE_WIDE | H.TRACE_SLAB):
                     o = H.BatchOpts(chunk, refill, 8192, flags)
                     ms = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws), reps=2)
                     table.append((ms, K, chunk, refill, flags))
@@ -636,6 +636,7 @@ def run_drift(H, args):
     bvh = H.build_bvh(torch.from_numpy(spec.tris).to(dev))
     opts = H.TraceOpts(64, 2, 0, 1, 32, 64, 8192, H.TRACE_WIDE)
     rays = W.pinhole_rays(spec, args.width, args.height, args.drift_spp, seed=91)
+    from paper_2305_16652_amd import autotune as AT
     log(f"drift scene: {spec.tris.shape[0]} triangles, {rays.shape[0]} primary rays ({time.time() - t0:.1f}s)")
     out = dict(triangles=int(spec.tris.shape[0]), camera=f"{args.width}x{args.height}x{args.drift_spp}",
                bounces={})
@@ -647,11 +648,13 @@ def run_drift(H, args):
         t, prim = h[:, 0].copy(), h[:, 1].copy().view(np.uint32)
         rays, _ = W.spawn_diffuse(rays, t, prim, spec.tris, seed=92, bounce=bounce - 1)
         rd = torch.from_numpy(rays).to(dev)
+        # one set of 4-wide trace options per bounce, tuned on the unsorted rays
+        opts = AT.tune_trace(bvh, rd, None, candidates=AT.WIDE)[0]
         rows = [measure_variant(H, bvh, rd, dict(mode="nosort"), opts, args.drift_reps)]
         for k in ks:
             for v in (dict(mode="twopoint", K=k), dict(mode="hcc", C=k, K=k), dict(mode="grid", K=k)):
                 rows.append(measure_variant(H, bvh, rd, v, opts, args.drift_reps))
-        out["bounces"][str(bounce)] = dict(rays=int(rd.shape[0]), rows=rows)
+        out["bounces"][str(bounce)] = dict(rays=int(rd.shape[0]), rows=rows, trace_opts=AT.opts_dict(opts))
         log(f"drift bounce {bounce} ({rd.shape[0]} rays): " +
             "; ".join(f"{r['method']} {r['mrays_s']:.0f} Mrays/s {r['node_fetches_per_ray']:.1f} nf/ray "
                       f"anc32 {r.get('anc32', 0):.2f}" for r in rows))

@@ -1,10 +1,12 @@
 """Autotuner for the trace launch options and the HCC cut size / key length.
 
 Times candidate configurations on the device with HIP events (through the C ABI) and keeps
-the fastest.  The search space covers what the trace kernel exposes: one-ray-per-lane blocks
+the fastest.  The search space covers what the trace kernels expose: one-ray-per-lane blocks
 (64/128/256 lanes) vs persistent wavefronts, the stack placement (scratch, LDS, split), the
-persistent refill threshold, chunk size and speculative descent; for HCC additionally the cut
-size C and key length K (the paper's configuration is C = K).
+persistent refill threshold, chunk size and speculative descent, and for the 4-wide traversal
+the wavefront count and the child-box test (selected planes or slab, whichever suits the
+scene's size against the caches); for HCC additionally the cut size C and key length K (the
+paper's configuration is C = K).
 """
 from __future__ import annotations
 
@@ -18,7 +20,8 @@ from . import (KEY_HCC, KEY_TWOPOINT, TraceOpts, encode, select_cut, sort, sort_
 PLAIN = [TraceOpts(b, s, 0, 0, 0, 0, 0, 0) for b in (64, 128) for s in (0, 2)]
 PERSISTENT = [TraceOpts(64, s, 0, 1, r, c, 8192, f)
               for s in (0,) for r in (24, 32) for c in (64, 128, 256) for f in (0, 1)]
-WIDE = [TraceOpts(64, s, 0, 1, r, c, w, 2) for s in (1, 2) for r in (24, 32) for c in (64, 128) for w in (8192, 16384)]
+# 4-wide: LDS short stack, both child-box tests (selected planes / slab, flags 2 / 6)
+WIDE = [TraceOpts(64, 2, 0, 1, r, c, w, f) for f in (2, 6) for r in (24, 32) for c in (64, 128) for w in (8192, 16384)]
 DEFAULT_CANDIDATES = PLAIN + PERSISTENT + WIDE
 
 

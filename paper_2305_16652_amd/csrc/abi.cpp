@@ -399,6 +399,8 @@ __attribute__((visibility("default"))) hcc_status hcc_trace_ex(hcc_bvh bvh, cons
     if (st != HCC_OK || n == 0) return st;
     hcc_trace_opts o{};
     if (opts) o = *opts;
+    if (o.flags & ~(HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB))
+        return fail(HCC_ERR_INVALID, "hcc_trace: unknown opts.flags bits");
     return trace(bvh, d_rays, d_perm, n, mode == HCC_TRACE_CLOSEST, d_hits, d_occluded, o, S(stream));
 }
 
@@ -412,6 +414,8 @@ __attribute__((visibility("default"))) hcc_status hcc_trace_count(hcc_bvh bvh, c
     if (!d_counts) return fail(HCC_ERR_INVALID, "hcc_trace_count: null d_counts");
     hcc_trace_opts o{};
     if (opts) o = *opts;
+    if (o.flags & ~(HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB))
+        return fail(HCC_ERR_INVALID, "hcc_trace_count: unknown opts.flags bits");
     return trace_count(bvh, d_rays, d_perm, n, mode == HCC_TRACE_CLOSEST, d_hits, d_occluded, o,
                        (unsigned long long*)d_counts, S(stream));
 }
@@ -483,7 +487,8 @@ __attribute__((visibility("default"))) hcc_status hcc_batch_run(const hcc_batch_
     if (!d_ws || ((uintptr_t)d_ws & 255u)) return fail(HCC_ERR_INVALID, "hcc_batch_run: workspace must be 256-byte aligned");
     hcc_batch_opts o{};
     if (opts) o = *opts;
-    if ((o.flags & ~HCC_TRACE_WIDE) != 0) return fail(HCC_ERR_INVALID, "hcc_batch_run: unknown opts.flags bits");
+    if ((o.flags & ~(HCC_TRACE_WIDE | HCC_TRACE_SLAB)) != 0)
+        return fail(HCC_ERR_INVALID, "hcc_batch_run: unknown opts.flags bits");
     if (o.direct_min != 0 && o.direct_min < 65536)
         return fail(HCC_ERR_INVALID, "hcc_batch_run: opts.direct_min must be 0 or at least 65536");
     return batch_run(batches, nb, mode, key_bits, o, d_ws, ws_bytes, S(stream));

@@ -42,7 +42,7 @@ struct EngScene {
 };
 
 struct EngHeader {
-    uint32_t nb, total_items, mode, key_bits, passes, refill, total_tiles, pad1;
+    uint32_t nb, total_items, mode, key_bits, passes, refill, total_tiles, slab;   // slab: HCC_TRACE_SLAB given
     uint32_t* zero;        // region cleared before the engine runs (starts with the queue counter)
     uint32_t* queue;
     uint64_t zero_words;
@@ -410,7 +410,7 @@ __device__ __forceinline__ void cswap4(float& ka, uint32_t& ia, float& kb, uint3
 // [begin, end) of the batch's order)
 template <bool closest>
 __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const uint32_t* perm, uint32_t begin,
-                                   uint32_t end, uint32_t refill, uint32_t* s_stk) {
+                                   uint32_t end, uint32_t refill, uint32_t slab, uint32_t* s_stk) {
     const uint64_t below = below_mask();
     // first kEngShort entries per lane in LDS (lane-interleaved), deeper ones in scratch
     uint32_t deep[kWideStack - kEngShort];
@@ -428,7 +428,7 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
     WideRay wr{0, 0, 0, false};
     bool found = false;
     const uint32_t n_int = sc.n_int;
-    const bool fast_nodes = n_int <= kWideFastNodes;
+    const bool fast_nodes = !slab && n_int <= kWideFastNodes;
     auto test_tri = [&](uint32_t slot) {
         const Tri tr = sc.tris[slot];
         const uint32_t prim = __float_as_uint(tr.r.y);
@@ -538,15 +538,17 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
 }
 
 __device__ __forceinline__ void trace_range_wide(const EngScene& sc, const EngBatch& bt, const uint32_t* perm,
-                                                 uint32_t begin, uint32_t end, uint32_t refill, uint32_t* s_stk) {
-    if (bt.closest) trace_range_wide_t<true>(sc, bt, perm, begin, end, refill, s_stk);
-    else trace_range_wide_t<false>(sc, bt, perm, begin, end, refill, s_stk);
+                                                 uint32_t begin, uint32_t end, uint32_t refill, uint32_t slab,
+                                                 uint32_t* s_stk) {
+    if (bt.closest) trace_range_wide_t<true>(sc, bt, perm, begin, end, refill, slab, s_stk);
+    else trace_range_wide_t<false>(sc, bt, perm, begin, end, refill, slab, s_stk);
 }
 
 template <typename K, bool kWide>
 __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
                                             uint32_t nb, uint32_t total_items, uint32_t total_tiles, uint32_t* queue,
-                                            uint32_t mode, uint32_t key_bits, uint32_t passes, uint32_t refill) {
+                                            uint32_t mode, uint32_t key_bits, uint32_t passes, uint32_t refill,
+                                            uint32_t slab) {
     __shared__ CutBox s_cut[64];
     __shared__ uint32_t s_whist[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
@@ -585,7 +587,7 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
                 perm = ((passes - 1) & 1) ? bt.vals_a : bt.vals_b;
             }
             if (kWide)
-                trace_range_wide(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill, s_stk);
+                trace_range_wide(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill, slab, s_stk);
             else
                 trace_range(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill);
             continue;
@@ -607,8 +609,9 @@ template <typename K, bool kWide>
 __global__ __launch_bounds__(64) void k_engine(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
                                                uint32_t nb, uint32_t total_items, uint32_t total_tiles,
                                                uint32_t* queue, uint32_t mode,
-                                               uint32_t key_bits, uint32_t passes, uint32_t refill) {
-    engine_loop<K, kWide>(scenes, batches, nb, total_items, total_tiles, queue, mode, key_bits, passes, refill);
+                                               uint32_t key_bits, uint32_t passes, uint32_t refill, uint32_t slab) {
+    engine_loop<K, kWide>(scenes, batches, nb, total_items, total_tiles, queue, mode, key_bits, passes, refill,
+                          slab);
 }
 
 __global__ void k_zero(uint32_t* p, size_t n) {
@@ -623,7 +626,7 @@ __global__ __launch_bounds__(64) void k_engine_hdr(const EngHeader* __restrict__
                                                    const EngBatch* __restrict__ batches) {
     engine_loop<K, kWide>(scenes, batches, h->nb, h->total_items, h->total_tiles, h->queue, h->mode, h->key_bits,
                           h->passes,
-                          h->refill);
+                          h->refill, h->slab);
 }
 
 __global__ void k_zero_hdr(const EngHeader* __restrict__ h) {
@@ -791,6 +794,7 @@ static hcc_status fill_tables(const hcc_batch_desc* d, uint32_t nb, uint32_t mod
     h.key_bits = key_bits;
     h.passes = passes;
     h.refill = refill;
+    h.slab = (o.flags & HCC_TRACE_SLAB) ? 1u : 0u;
     h.zero = (uint32_t*)(ws + P.zero_off);
     h.queue = (uint32_t*)(ws + P.zero_off);
     h.zero_words = P.zero_bytes / 4;
@@ -890,7 +894,7 @@ static hcc_status engine_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t m
     const bool wide = (o.flags & HCC_TRACE_WIDE) != 0;
 #define HCC_ENGINE(KT, WD)                                                                                        \
     k_engine<KT, WD><<<grid, 64, 0, stream>>>(dsc, dbt, nb, h.total_items, h.total_tiles, h.queue, mode,       \
-                                              key_bits, h.passes, h.refill)
+                                              key_bits, h.passes, h.refill, h.slab)
     if (key_bits <= 32) {
         if (wide) HCC_ENGINE(uint32_t, true); else HCC_ENGINE(uint32_t, false);
     } else {

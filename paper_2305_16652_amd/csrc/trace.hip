@@ -412,7 +412,7 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
                                                    uint32_t n_int, const float4* __restrict__ rays,
                                                    const uint32_t* __restrict__ perm, uint32_t n,
                                                    float4* __restrict__ hits, uint8_t* __restrict__ occ,
-                                                   uint32_t refill, uint32_t chunk, uint32_t remap,
+                                                   uint32_t refill, uint32_t chunk, uint32_t remap, uint32_t slab,
                                                    unsigned long long* __restrict__ counts) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     const uint32_t nchunks = (n + chunk - 1) / chunk;
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
     float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0, tmin = 0, tmax = 0;
     float best_t = 0, best_u = 0, best_v = 0;
     WideRay wr{0, 0, 0, false};
-    const bool fast_nodes = n_int <= kWideFastNodes;
+    const bool fast_nodes = !slab && n_int <= kWideFastNodes;
     bool found = false;
     uint32_t c_nodes = 0, c_tris = 0;
 
@@ -623,7 +623,7 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
         const int lds = kStats ? 0 : (o.stack == HCC_STACK_SHORT ? 12 : (o.stack == HCC_STACK_LDS ? 24 : 0));
 #define HCC_WIDE(CL, LD)                                                                                       \
     k_trace_wide<CL, kStats, LD><<<waves, 64, 0, s>>>(b->wnodes, b->tris, b->n_int, r, perm, n, h, occ, refill, \
-                                                      chunk, o.xcd_remap, counts)
+                                                      chunk, o.xcd_remap, (o.flags & HCC_TRACE_SLAB) ? 1u : 0u, counts)
         if (closest) {
             if (lds == 12) HCC_WIDE(true, 12); else if (lds == 24) HCC_WIDE(true, 24); else HCC_WIDE(true, 0);
         } else {

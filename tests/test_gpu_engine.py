@@ -54,7 +54,8 @@ def _batches(H, scenes, seed, key_cut):
 
 @pytest.mark.parametrize("mode,key_bits,cut", [("hcc", 32, "cut32"), ("hcc", 64, "cut64"), ("hcc", 16, "cut32"),
                                                ("twopoint", 32, None), ("twopoint", 64, None), ("none", 32, None)])
-@pytest.mark.parametrize("opts", [None, (64, 1, 7, 0), (1000, 64, 3, 0), (256, 32, 0, 2), (64, 5, 11, 2)])
+@pytest.mark.parametrize("opts", [None, (64, 1, 7, 0), (1000, 64, 3, 0), (256, 32, 0, 2), (64, 5, 11, 2),
+                                  (128, 24, 0, 6)])
 def test_engine_matches_oracle_and_plain_path(H, scenes, mode, key_bits, cut, opts):
     key_mode = {"hcc": H.KEY_HCC, "twopoint": H.KEY_TWOPOINT, "none": 0}[mode]
     items = _batches(H, scenes, seed=key_bits + (opts[0] if opts else 0), key_cut=cut if mode == "hcc" else None)
@@ -138,3 +139,5 @@ def test_engine_invalid_arguments(H, scenes):
         H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 0)
     with pytest.raises(H.HCCError):
         H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 1))
+    with pytest.raises(H.HCCError):
+        H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 8))

@@ -90,9 +90,10 @@ def test_fullsize_hcc_keys_sort_trace(frame, cut_size, key_bits):
     sample = np.arange(0, sec.shape[0], 997)
     oh = O.trace(ob, sec, subset=sample, threads=THREADS)
     assert_closest(hits, oh, sec, frame["spec"].tris, idx=sample)
-    # the 4-wide traversal returns the same closest hits on every ray
-    wide = H.trace(bvh, rays, perm, opts=H.TraceOpts(*WIDE_OPTS)).cpu().numpy()
-    assert np.array_equal(wide.view(np.uint32), hits.view(np.uint32))
+    # the 4-wide traversal returns the same closest hits on every ray, with either child test
+    for flags in (H.TRACE_WIDE, H.TRACE_WIDE | H.TRACE_SLAB):
+        wide = H.trace(bvh, rays, perm, opts=H.TraceOpts(*WIDE_OPTS[:7], flags)).cpu().numpy()
+        assert np.array_equal(wide.view(np.uint32), hits.view(np.uint32))
 
 
 def test_fullsize_twopoint_keys(frame):
@@ -111,5 +112,6 @@ def test_fullsize_shadow_any_hit(frame):
     sample = np.arange(0, shd.shape[0], 1999)
     ref = O.trace(ob, shd, subset=sample, closest=False, threads=THREADS)
     assert_any(occ, ref, idx=sample)
-    wide = H.trace(bvh, rays, perm, closest=False, opts=H.TraceOpts(*WIDE_OPTS)).cpu().numpy()
-    assert np.array_equal(wide, occ)
+    for flags in (H.TRACE_WIDE, H.TRACE_WIDE | H.TRACE_SLAB):
+        wide = H.trace(bvh, rays, perm, closest=False, opts=H.TraceOpts(*WIDE_OPTS[:7], flags)).cpu().numpy()
+        assert np.array_equal(wide, occ)

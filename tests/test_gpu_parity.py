@@ -188,7 +188,9 @@ OPTS = [(128, 1, 0, 0, 0, 0, 0), (64, 1, 1, 0, 0, 0, 0), (256, 1, 0, 0, 0, 0, 0)
         (0, 0, 0, 1, 16, 256, 0, 2), (64, 1, 1, 0, 32, 64, 0, 2), (0, 0, 0, 1, 1, 64, 3, 2),
         (0, 2, 0, 1, 64, 1000, 7, 3), (0, 1, 0, 1, 16, 64, 0, 2), (0, 2, 0, 1, 1, 64, 5, 2),
         # XCD-contiguous chunk order for the persistent and 4-wide kernels
-        (0, 2, 1, 1, 32, 64, 0, 2), (0, 0, 1, 1, 16, 256, 13, 1)]
+        (0, 2, 1, 1, 32, 64, 0, 2), (0, 0, 1, 1, 16, 256, 13, 1),
+        # 4-wide with every child box through the slab test (flags bit 2)
+        (0, 2, 0, 1, 32, 64, 0, 6), (0, 0, 1, 1, 16, 256, 9, 6), (0, 1, 0, 1, 1, 64, 3, 6)]
 WIDE = (0, 0, 0, 1, 32, 64, 0, 2)
 
 
@@ -295,7 +297,8 @@ def test_degenerate_rays(H, gpu_bvh, tiny):
     rays[4::7, 7] = 0.0          # zero-length segments
     rays[5::11, 4:7] = 0.0       # zero direction
     tris = tiny["spec"].tris
-    for o in (None, H.TraceOpts(*WIDE), H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 1)):
+    for o in (None, H.TraceOpts(*WIDE), H.TraceOpts(*WIDE[:7], H.TRACE_WIDE | H.TRACE_SLAB),
+              H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 1)):
         assert_closest(H.trace(gpu_bvh, _dev(rays), opts=o).cpu().numpy(), O.trace(tiny["ob"], rays), rays, tris)
         assert_any(H.trace(gpu_bvh, _dev(rays), closest=False, opts=o).cpu().numpy(),
                    O.trace(tiny["ob"], rays, closest=False))
@@ -345,6 +348,8 @@ def test_invalid_arguments(H, gpu_bvh):
         H.trace(gpu_bvh, rays, opts=H.TraceOpts(96, 0, 0, 0, 0, 0, 0, 0))
     with pytest.raises(H.HCCError):
         H.trace(gpu_bvh, rays, opts=H.TraceOpts(64, 7, 0, 0, 0, 0, 0, 0))
+    with pytest.raises(H.HCCError):
+        H.trace(gpu_bvh, rays, opts=H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 8))      # unknown flag bit
     other = H.build_bvh(torch.tensor([[0, 0, 0, 1, 0, 0, 0, 1, 0]], dtype=torch.float32, device="cuda"))
     with pytest.raises(H.HCCError):
         H.encode(gpu_bvh, H.select_cut(other, 1), H.KEY_HCC, 32, rays)   # cut from another BVH
