@@ -243,15 +243,18 @@ __global__ __launch_bounds__(256) void k_refit(uint32_t n, const uint32_t* __res
 // 4-wide nodes, one level of the wide tree per launch: a frontier node starts from its two
 // children and, while it has fewer than four and one of them is internal, replaces the
 // internal child of largest surface area by that child's two children (greedy SAH-style
-// collapse).  Internal members become the next level's frontier.  Each BVH2 node is a member
-// of exactly one wide node, so the output (indexed by BVH2 id) does not depend on the order
-// in which the frontier is appended.
+// collapse).  Internal members become the next level's frontier.  Wide nodes are stored
+// compactly in level order: frontier entry i of this level is wide node level_base + i, and
+// the next level starts right after this one, each node's internal members taking consecutive
+// places there (one reservation per node), so siblings sit next to each other in memory.
 __global__ __launch_bounds__(256) void k_wide_level(const uint32_t* __restrict__ frontier, uint32_t count,
-                                                    uint32_t n_int, const uint32_t* __restrict__ child,
+                                                    uint32_t level_base, uint32_t n_int,
+                                                    const uint32_t* __restrict__ child,
                                                     const float* __restrict__ boxes, Node4* __restrict__ wide,
                                                     uint32_t* __restrict__ next, uint32_t* __restrict__ next_count) {
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
     if (i >= count) return;
+    const uint32_t next_base = level_base + count;
     const uint32_t x = frontier[i];
     uint32_t list[4] = {child[2 * (size_t)x], child[2 * (size_t)x + 1], kNone, kNone};
     uint32_t m = 2;
@@ -276,6 +279,9 @@ __global__ __launch_bounds__(256) void k_wide_level(const uint32_t* __restrict__
         list[best + 1] = child[2 * (size_t)u + 1];
         ++m;
     }
+    uint32_t n_in = 0;
+    for (uint32_t j = 0; j < m; ++j) n_in += list[j] < n_int ? 1u : 0u;
+    uint32_t at = n_in ? atomicAdd(next_count, n_in) : 0u;
     float lo[3][4], hi[3][4];
     uint32_t ref[4];
     for (uint32_t j = 0; j < 4; ++j) {
@@ -286,8 +292,12 @@ __global__ __launch_bounds__(256) void k_wide_level(const uint32_t* __restrict__
                 lo[a][j] = bx[a];
                 hi[a][j] = bx[3 + a];
             }
-            ref[j] = u >= n_int ? (kWideLeaf | (u - n_int)) : u;
-            if (u < n_int) next[atomicAdd(next_count, 1u)] = u;
+            if (u >= n_int) {
+                ref[j] = kWideLeaf | (u - n_int);
+            } else {
+                ref[j] = next_base + at;
+                next[at++] = u;
+            }
         } else {
             // inverted box: rejected by the sign-selected child test without a check of ref
             for (int a = 0; a < 3; ++a) {
@@ -306,7 +316,7 @@ __global__ __launch_bounds__(256) void k_wide_level(const uint32_t* __restrict__
     w.hiz = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
     w.ref = make_uint4(ref[0], ref[1], ref[2], ref[3]);
     w.pad = make_uint4(0, 0, 0, 0);
-    wide[x] = w;
+    wide[level_base + i] = w;
 }
 
 __global__ void k_fill(uint32_t* p, size_t n, uint32_t v) {
@@ -435,12 +445,13 @@ hcc_status build_bvh(const float* d_tris, uint32_t n, hipStream_t stream, hcc_bv
     if (e == hipSuccess && b->n_int > 0) {
         uint32_t* cur = codes;
         uint32_t* nxt = codes_sorted;
-        uint32_t count = 1;
+        uint32_t count = 1, level_base = 0;
         k_fill<<<1, 256, 0, stream>>>(cur, 1, 0u);
         for (int level = 0; count > 0 && level < 256 && e == hipSuccess; ++level) {
             k_fill<<<1, 256, 0, stream>>>(flags, 1, 0u);
-            k_wide_level<<<blocks_for(count), 256, 0, stream>>>(cur, count, b->n_int, b->child, b->boxes, b->wnodes,
-                                                                nxt, flags);
+            k_wide_level<<<blocks_for(count), 256, 0, stream>>>(cur, count, level_base, b->n_int, b->child, b->boxes,
+                                                                b->wnodes, nxt, flags);
+            level_base += count;
             e = hipGetLastError();
             if (e == hipSuccess) e = hipMemcpyAsync(&count, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
             if (e == hipSuccess) e = hipStreamSynchronize(stream);

@@ -27,8 +27,9 @@ struct alignas(64) Node {
 // 4-wide node for traversal, 128 bytes (two cache lines): the BVH2 collapsed top down.  The
 // wide node of BVH2 node X holds up to four BVH2 descendants of X that together cover its
 // subtree (X's children, internal ones replaced by their children, largest surface area first).
-// Slot j: box (lox[j], loy[j], loz[j]) - (hix[j], hiy[j], hiz[j]); ref[j] = BVH2 id of an internal
-// member (whose wide node is stored at that same index), kWideLeaf | triangle slot, or kWideEmpty.
+// Slot j: box (lox[j], loy[j], loz[j]) - (hix[j], hiy[j], hiz[j]); ref[j] = index of the wide
+// node of an internal member (wide nodes are stored in level order, the root at 0),
+// kWideLeaf | triangle slot, or kWideEmpty.
 struct alignas(64) Node4 {
     float4 lox, loy, loz, hix, hiy, hiz;
     uint4 ref;
@@ -222,7 +223,7 @@ struct hcc_bvh_s {
     uint32_t n = 0;                 // triangles
     uint32_t n_int = 0;             // internal nodes = n - 1
     hcc::Node* nodes = nullptr;     // n_int
-    hcc::Node4* wnodes = nullptr;   // n_int slots, filled at even-depth internal ids
+    hcc::Node4* wnodes = nullptr;   // 4-wide nodes in level order from the root (at most n_int)
     hcc::Tri* tris = nullptr;       // n (Morton order)
     float* boxes = nullptr;         // (2n-1) x 6
     double* had = nullptr;          // 2n-1
