@@ -12,6 +12,11 @@ over the whole batch.  The same batch is also timed for NoSort (trace in generat
 and TwoPoint (6-D Morton key).  Each method runs in its own fastest configuration, chosen
 before the timed region by the autotuner (trace launch options; key length; for HCC the cut
 size, C = K as in the paper).  Prints one JSON line on stdout; progress goes to stderr.
+
+Beside the headline the line carries: the roofline of the trace kernel, the CPU oracle's rate,
+a grid of reordering methods on the same batch, bounces 2 and 3 of the frame, the 10M-triangle
+boundary-drift workload, the uneven-batch engine workload and the request-server workload
+(each can be skipped with its --no-... flag).
 """
 from __future__ import annotations
 
@@ -69,6 +74,7 @@ def parse():
     ap.add_argument("--no-grid", action="store_true", help="skip the frame workload's method grid")
     ap.add_argument("--grid-reps", type=int, default=5)
     ap.add_argument("--no-drift", action="store_true", help="skip the 10M-triangle boundary-drift workload")
+    ap.add_argument("--no-bounces", action="store_true", help="skip the frame workload's bounces 2 and 3")
     ap.add_argument("--drift-tris", type=int, default=10_000_000)
     ap.add_argument("--drift-spp", type=int, default=4)
     ap.add_argument("--drift-keys", default="16,24,32,48,64")
@@ -263,6 +269,7 @@ def main():
     if not args.no_grid and "hcc" in conf:
         grid = run_method_grid(H, bvh, rays, conf["hcc"]["opts"], args.grid_reps)
     del bufs
+    bounces = None if args.no_bounces else run_bounces(H, args, bvh, tris_h, sec, rays)
     drift = None if args.no_drift else run_drift(H, args)
     batched = None if args.no_batched else run_batched(H, args)
     serve = None if args.no_serve else run_serving(H, args)
@@ -300,6 +307,7 @@ def main():
         "build_ms": round(build_ms, 2),
         "select_cut_ms": round(cut_ms, 2),
         "method_grid": grid,
+        "frame_bounces": bounces,
         "drift": drift,
         "batched": batched,
         "serve": serve,
@@ -622,6 +630,36 @@ def run_method_grid(H, bvh, rays, opts, reps):
                                     for r in rows))
     log(f"method grid best: {best['method']} {best['mrays_s']} Mrays/s")
     return rows
+
+
+def run_bounces(H, args, bvh, tris_h, sec, rays):
+    """Bounces 2 and 3 of the frame workload: diffuse rays spawned at the previous bounce's
+    closest hits (origins now scattered over the scene, directions random), each bounce's
+    NoSort, TwoPoint (K = 32) and HCC (C = K = 32) with trace options tuned on its NoSort
+    order."""
+    import torch
+    import workloads as W
+    from paper_2305_16652_amd import autotune as AT
+    out = {}
+    prev, prev_d = sec, rays
+    for bounce in (2, 3):
+        t0 = time.time()
+        h = H.trace(bvh, prev_d, opts=H.TraceOpts(64, 2, 0, 1, 32, 64, 16384, H.TRACE_WIDE)).cpu().numpy()
+        nxt, _ = W.spawn_diffuse(prev, h[:, 0].copy(), h[:, 1].copy().view(np.uint32), tris_h, seed=7,
+                                 bounce=bounce - 1)
+        rd = torch.from_numpy(nxt).to(rays.device)
+        opts = AT.tune_trace(bvh, rd, None, candidates=AT.WIDE)[0]
+        rows = [measure_variant(H, bvh, rd, v, opts, args.grid_reps)
+                for v in (dict(mode="nosort"), dict(mode="twopoint", K=32), dict(mode="hcc", C=32, K=32))]
+        out[str(bounce)] = dict(rays=int(rd.shape[0]), trace_opts=AT.opts_dict(opts), rows=rows)
+        log(f"frame bounce {bounce} ({rd.shape[0]} rays, {time.time() - t0:.1f}s): " +
+            "; ".join(f"{r['method']} {r['mrays_s']:.0f} Mrays/s (trace {r['trace_ms']:.2f} ms, "
+                      f"{r['node_fetches_per_ray']:.1f} nf/ray)" for r in rows))
+        if prev_d is not rays:
+            del prev_d
+        prev, prev_d = nxt, rd
+    del prev_d
+    return out
 
 
 def run_drift(H, args):
