@@ -11,7 +11,8 @@ A step = HCC encode + stable radix sort + closest-hit trace through the sorted p
 over the whole batch.  The same batch is also timed for NoSort (trace in generation order)
 and TwoPoint (6-D Morton key).  Each method runs in its own fastest configuration, chosen
 before the timed region by the autotuner (trace launch options; key length; for HCC the cut
-size, C = K as in the paper).  Prints one JSON line on stdout; progress goes to stderr.
+size C from 32 to 4,096 with C >= K -- the frame configuration's cut sizes -- or only the paper's
+C = K pairs with --paper-exact).  Prints one JSON line on stdout; progress goes to stderr.
 
 Beside the headline the line carries: the roofline of the trace kernel, the CPU oracle's rate,
 a grid of reordering methods on the same batch, bounces 2 and 3 of the frame, the 10M-triangle
@@ -53,6 +54,9 @@ def parse():
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--tune", type=int, default=1, help="autotune each method (0: use the flags below)")
     ap.add_argument("--cut", type=int, default=32)
+    ap.add_argument("--hcc-cuts", default="32,64,256,512,1024,2048,4096",
+                    help="cut sizes the HCC tuning tries (with K in {32, 64}, C >= K)")
+    ap.add_argument("--paper-exact", action="store_true", help="HCC tuning only over C = K (the paper's pairs)")
     ap.add_argument("--key-bits", type=int, default=32)
     ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--stack", type=int, default=0, help="0 scratch, 1 LDS, 2 LDS+scratch")
@@ -153,7 +157,11 @@ def main():
         if m not in methods:
             continue
         if args.tune:
-            ch, _ = AT.tune_reorder(bvh, rays, m)
+            if m == "hcc":
+                cs = tuple(int(c) for c in args.hcc_cuts.split(","))
+                ch, _ = AT.tune_reorder(bvh, rays, m, cuts=cs, paper_exact=args.paper_exact)
+            else:
+                ch, _ = AT.tune_reorder(bvh, rays, m)
             conf[m] = dict(cut=ch.cut, key_bits=ch.key_bits, opts=ch.opts)
         else:
             conf[m] = dict(cut=args.cut if m == "hcc" else 0, key_bits=args.key_bits, opts=flag_opts)

@@ -80,12 +80,13 @@ class Choice:
 def tune_reorder(bvh, rays, mode: str, cuts=(32, 64), key_bits=(32, 64), closest: bool = True,
                  candidates=None, reps: int = 2, paper_exact: bool = True) -> tuple[Choice, list]:
     """Best (cut, key length, trace options) for a reordering method, by total encode + sort +
-    trace time.  mode: 'hcc' or 'twopoint' (cut ignored).  With paper_exact only C = K pairs."""
+    trace time.  mode: 'hcc' or 'twopoint' (cut ignored).  With paper_exact only C = K pairs,
+    otherwise every pair with C >= K (the key then holds the K cut nodes of highest HAD)."""
     n = rays.shape[0]
     dev = rays.device
     results = []
     if mode == "hcc":
-        pairs = [(c, k) for c, k in itertools.product(cuts, key_bits) if (c == k or not paper_exact)]
+        pairs = [(c, k) for c, k in itertools.product(cuts, key_bits) if (c == k or (not paper_exact and c >= k))]
     else:
         pairs = [(0, k) for k in key_bits]
     for c, k in pairs:
