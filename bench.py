@@ -277,7 +277,8 @@ def main():
     if not args.no_grid and "hcc" in conf:
         grid = run_method_grid(H, bvh, rays, conf["hcc"]["opts"], args.grid_reps)
     del bufs
-    bounces = None if args.no_bounces else run_bounces(H, args, bvh, tris_h, sec, rays)
+    hcc_ck = (conf["hcc"]["cut"], conf["hcc"]["key_bits"]) if "hcc" in conf else (32, 32)
+    bounces = None if args.no_bounces else run_bounces(H, args, bvh, tris_h, sec, rays, hcc_ck)
     drift = None if args.no_drift else run_drift(H, args)
     batched = None if args.no_batched else run_batched(H, args)
     serve = None if args.no_serve else run_serving(H, args)
@@ -640,11 +641,11 @@ def run_method_grid(H, bvh, rays, opts, reps):
     return rows
 
 
-def run_bounces(H, args, bvh, tris_h, sec, rays):
+def run_bounces(H, args, bvh, tris_h, sec, rays, hcc_ck):
     """Bounces 2 and 3 of the frame workload: diffuse rays spawned at the previous bounce's
     closest hits (origins now scattered over the scene, directions random), each bounce's
-    NoSort, TwoPoint (K = 32) and HCC (C = K = 32) with trace options tuned on its NoSort
-    order."""
+    NoSort, TwoPoint (K = 32) and HCC (the cut size and key length picked for bounce 1) with
+    trace options tuned on its NoSort order."""
     import torch
     import workloads as W
     from paper_2305_16652_amd import autotune as AT
@@ -658,7 +659,8 @@ def run_bounces(H, args, bvh, tris_h, sec, rays):
         rd = torch.from_numpy(nxt).to(rays.device)
         opts = AT.tune_trace(bvh, rd, None, candidates=AT.WIDE)[0]
         rows = [measure_variant(H, bvh, rd, v, opts, args.grid_reps)
-                for v in (dict(mode="nosort"), dict(mode="twopoint", K=32), dict(mode="hcc", C=32, K=32))]
+                for v in (dict(mode="nosort"), dict(mode="twopoint", K=32),
+                          dict(mode="hcc", C=hcc_ck[0], K=hcc_ck[1]))]
         out[str(bounce)] = dict(rays=int(rd.shape[0]), trace_opts=AT.opts_dict(opts), rows=rows)
         log(f"frame bounce {bounce} ({rd.shape[0]} rays, {time.time() - t0:.1f}s): " +
             "; ".join(f"{r['method']} {r['mrays_s']:.0f} Mrays/s (trace {r['trace_ms']:.2f} ms, "
