@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--hcc-cuts", default="32,64,256,512,1024,2048,4096",
                     help="cut sizes the HCC tuning tries (with K in {32, 64}, C >= K)")
     ap.add_argument("--paper-exact", action="store_true", help="HCC tuning only over C = K (the paper's pairs)")
+    ap.add_argument("--skips", default="0,8,16",
+                    help="low key bits the tuned sort may leave out (the paper's shortened sort; 0 = full key)")
+    ap.add_argument("--skip", type=int, default=0, help="skipped low key bits without tuning")
     ap.add_argument("--key-bits", type=int, default=32)
     ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--stack", type=int, default=0, help="0 scratch, 1 LDS, 2 LDS+scratch")
@@ -152,22 +155,24 @@ def main():
     conf = {}
     if "nosort" in methods:
         o = AT.tune_trace(bvh, rays, None)[0] if args.tune else flag_opts
-        conf["nosort"] = dict(cut=0, key_bits=0, opts=o)
+        conf["nosort"] = dict(cut=0, key_bits=0, skip=0, opts=o)
     for m in ("twopoint", "hcc"):
         if m not in methods:
             continue
         if args.tune:
+            sk = tuple(int(x) for x in args.skips.split(","))
             if m == "hcc":
                 cs = tuple(int(c) for c in args.hcc_cuts.split(","))
-                ch, _ = AT.tune_reorder(bvh, rays, m, cuts=cs, paper_exact=args.paper_exact)
+                ch, _ = AT.tune_reorder(bvh, rays, m, cuts=cs, paper_exact=args.paper_exact, skips=sk)
             else:
-                ch, _ = AT.tune_reorder(bvh, rays, m)
-            conf[m] = dict(cut=ch.cut, key_bits=ch.key_bits, opts=ch.opts)
+                ch, _ = AT.tune_reorder(bvh, rays, m, skips=sk)
+            conf[m] = dict(cut=ch.cut, key_bits=ch.key_bits, skip=ch.skip, opts=ch.opts)
         else:
-            conf[m] = dict(cut=args.cut if m == "hcc" else 0, key_bits=args.key_bits, opts=flag_opts)
+            conf[m] = dict(cut=args.cut if m == "hcc" else 0, key_bits=args.key_bits, skip=args.skip, opts=flag_opts)
     if args.tune:
         log(f"autotuned in {time.time() - t0:.1f}s: " +
-            "; ".join(f"{m} C={c['cut']} K={c['key_bits']} {AT.opts_dict(c['opts'])}" for m, c in conf.items()))
+            "; ".join(f"{m} C={c['cut']} K={c['key_bits']} skip={c.get('skip', 0)} {AT.opts_dict(c['opts'])}"
+                      for m, c in conf.items()))
     e0.record()
     cuts = {m: H.select_cut(bvh, c["cut"]) for m, c in conf.items() if m == "hcc"}
     e1.record()
@@ -200,7 +205,7 @@ def main():
                 H.encode(bvh, None, H.KEY_TWOPOINT, k, rr, out=b["keys"])
             if evs:
                 evs[1].record()
-            H.sort(b["keys"], k, perm=b["perm"], ws=b["ws"])
+            H.sort_ex(b["keys"], k, c["skip"], 0, perm=b["perm"], ws=b["ws"])
             perm = b["perm"]
         elif evs:
             evs[1].record()
@@ -271,13 +276,15 @@ def main():
                                conf["hcc"]["opts"])
     cpu = None
     if not args.no_cpu and "hcc" in conf:
-        cpu = cpu_baseline(tris_h, sec, args, hcc_hits.cpu().numpy(), conf["hcc"]["cut"], conf["hcc"]["key_bits"])
+        cpu = cpu_baseline(tris_h, sec, args, hcc_hits.cpu().numpy(), conf["hcc"]["cut"], conf["hcc"]["key_bits"],
+                           conf["hcc"]["skip"])
 
     grid = None
     if not args.no_grid and "hcc" in conf:
         grid = run_method_grid(H, bvh, rays, conf["hcc"]["opts"], args.grid_reps)
     del bufs
-    hcc_ck = (conf["hcc"]["cut"], conf["hcc"]["key_bits"]) if "hcc" in conf else (32, 32)
+    hcc_ck = ((conf["hcc"]["cut"], conf["hcc"]["key_bits"], conf["hcc"]["skip"]) if "hcc" in conf else (32, 32, 0),
+              conf["twopoint"]["skip"] if "twopoint" in conf else 0)
     bounces = None if args.no_bounces else run_bounces(H, args, bvh, tris_h, sec, rays, hcc_ck)
     drift = None if args.no_drift else run_drift(H, args)
     batched = None if args.no_batched else run_batched(H, args)
@@ -303,12 +310,15 @@ def main():
         "config": {
             "workload": (f"frame: {tris_h.shape[0]:,}-triangle room with 100 icospheres + 100 tori, "
                          f"{args.width}x{args.height}x{args.spp} spp, bounce-1 diffuse secondary rays; "
-                         f"{head} cut {hc['cut']} nodes, {hc['key_bits']}-bit keys"),
+                         f"{head} cut {hc['cut']} nodes, {hc['key_bits']}-bit keys"
+                         + (f", sorted on the top {hc['key_bits'] - hc['skip']} bits" if hc.get("skip") else "")),
             "triangles": int(tris_h.shape[0]), "rays": int(R), "cut": hc["cut"], "key_bits": hc["key_bits"],
+            "skip_bits": hc.get("skip", 0),
             "trace_opts": AT.opts_dict(hc["opts"]),
         },
         "methods": {m: dict({k: round(v, 4) for k, v in r.items()}, cut=conf[m]["cut"],
-                            key_bits=conf[m]["key_bits"], trace_opts=AT.opts_dict(conf[m]["opts"]))
+                            key_bits=conf[m]["key_bits"], skip_bits=conf[m].get("skip", 0),
+                            trace_opts=AT.opts_dict(conf[m]["opts"]))
                     for m, r in results.items()},
         "speedup_vs_nosort": round(hcc["mrays_s"] / nos["mrays_s"], 3) if nos else None,
         "speedup_vs_twopoint": round(hcc["mrays_s"] / tpt["mrays_s"], 3) if tpt else None,
@@ -644,8 +654,8 @@ def run_method_grid(H, bvh, rays, opts, reps):
 def run_bounces(H, args, bvh, tris_h, sec, rays, hcc_ck):
     """Bounces 2 and 3 of the frame workload: diffuse rays spawned at the previous bounce's
     closest hits (origins now scattered over the scene, directions random), each bounce's
-    NoSort, TwoPoint (K = 32) and HCC (the cut size and key length picked for bounce 1) with
-    trace options tuned on its NoSort order."""
+    NoSort, TwoPoint (K = 32) and HCC (the cut size, key length and skipped bits picked for
+    bounce 1) with trace options tuned on its NoSort order."""
     import torch
     import workloads as W
     from paper_2305_16652_amd import autotune as AT
@@ -659,8 +669,8 @@ def run_bounces(H, args, bvh, tris_h, sec, rays, hcc_ck):
         rd = torch.from_numpy(nxt).to(rays.device)
         opts = AT.tune_trace(bvh, rd, None, candidates=AT.WIDE)[0]
         rows = [measure_variant(H, bvh, rd, v, opts, args.grid_reps)
-                for v in (dict(mode="nosort"), dict(mode="twopoint", K=32),
-                          dict(mode="hcc", C=hcc_ck[0], K=hcc_ck[1]))]
+                for v in (dict(mode="nosort"), dict(mode="twopoint", K=32, skip=hcc_ck[1]),
+                          dict(mode="hcc", C=hcc_ck[0][0], K=hcc_ck[0][1], skip=hcc_ck[0][2]))]
         out[str(bounce)] = dict(rays=int(rd.shape[0]), trace_opts=AT.opts_dict(opts), rows=rows)
         log(f"frame bounce {bounce} ({rd.shape[0]} rays, {time.time() - t0:.1f}s): " +
             "; ".join(f"{r['method']} {r['mrays_s']:.0f} Mrays/s (trace {r['trace_ms']:.2f} ms, "
@@ -758,7 +768,7 @@ def roofline_of(H, bvh, rays, perm, R, trace_ms_mean, opts):
     return roofline
 
 
-def cpu_baseline(tris_h, sec, args, gpu_hits, cut_size, key_bits):
+def cpu_baseline(tris_h, sec, args, gpu_hits, cut_size, key_bits, skip=0):
     """The oracle's encode + sort + trace on a strided sample of the same secondary rays."""
     import oracle as O
     cores = len(os.sched_getaffinity(0))
@@ -769,7 +779,7 @@ def cpu_baseline(tris_h, sec, args, gpu_hits, cut_size, key_bits):
     cb = O.cut_boxes(ob, O.select_cut(ob, O.had(ob), cut_size))
     t0 = time.time()
     keys = O.encode_hcc(sample, cb, key_bits, threads=cores)
-    perm = O.sort(keys)
+    perm = O.sort_prefix(keys, key_bits, skip)
     h = O.trace(ob, sample, perm=perm, threads=cores)
     dt = time.time() - t0
     g = gpu_hits[:: args.cpu_stride]
@@ -778,13 +788,14 @@ def cpu_baseline(tris_h, sec, args, gpu_hits, cut_size, key_bits):
     # the same oracle on one thread, over a sparser sample of the same rays
     one = np.ascontiguousarray(sec[:: args.cpu_stride * 8])
     t0 = time.time()
-    h1 = O.trace(ob, one, perm=O.sort(O.encode_hcc(one, cb, key_bits)), threads=1)
+    h1 = O.trace(ob, one, perm=O.sort_prefix(O.encode_hcc(one, cb, key_bits), key_bits, skip), threads=1)
     dt1 = time.time() - t0
     log(f"CPU oracle, 1 thread: {one.shape[0]} rays in {dt1:.1f}s, {one.shape[0] / dt1 / 1e6:.4f} Mrays/s")
     del h1
     return dict(value=round(n / dt / 1e6, 4), unit="Mrays/s", cores=cores, kind="oracle",
                 sample=f"every {args.cpu_stride}th bounce-1 secondary ray ({n} rays): HCC encode (C={cut_size}, "
-                       f"K={key_bits}) + stable sort + closest-hit trace, {dt:.1f} s wall",
+                       f"K={key_bits}) + stable sort (on the top {key_bits - skip} bits) + closest-hit trace, "
+                       f"{dt:.1f} s wall",
                 prim_agreement_with_gpu=agree,
                 single_thread=dict(value=round(one.shape[0] / dt1 / 1e6, 4), unit="Mrays/s", cores=1,
                                    sample=f"every {args.cpu_stride * 8}th ray ({one.shape[0]} rays), {dt1:.1f} s"))

@@ -15,7 +15,8 @@ from dataclasses import dataclass
 
 import torch
 
-from . import (KEY_HCC, KEY_TWOPOINT, TraceOpts, encode, select_cut, sort, sort_workspace_bytes, trace)
+from . import (KEY_HCC, KEY_TWOPOINT, TraceOpts, encode, select_cut, sort_ex, sort_workspace_bytes,
+               trace)
 
 PLAIN = [TraceOpts(b, s, 0, 0, 0, 0, 0, 0) for b in (64, 128) for s in (0, 2)]
 PERSISTENT = [TraceOpts(64, s, 0, 1, r, c, 8192, f)
@@ -66,22 +67,25 @@ class Choice:
     encode_ms: float
     sort_ms: float
     trace_ms: float
+    skip: int = 0          # low key bits the sort leaves out (a stable sort by key >> skip)
 
     @property
     def total_ms(self) -> float:
         return self.encode_ms + self.sort_ms + self.trace_ms
 
     def as_dict(self) -> dict:
-        return dict(mode=self.mode, cut=self.cut, key_bits=self.key_bits, opts=opts_dict(self.opts),
+        return dict(mode=self.mode, cut=self.cut, key_bits=self.key_bits, skip=self.skip, opts=opts_dict(self.opts),
                     encode_ms=round(self.encode_ms, 4), sort_ms=round(self.sort_ms, 4),
                     trace_ms=round(self.trace_ms, 4), total_ms=round(self.total_ms, 4))
 
 
 def tune_reorder(bvh, rays, mode: str, cuts=(32, 64), key_bits=(32, 64), closest: bool = True,
-                 candidates=None, reps: int = 2, paper_exact: bool = True) -> tuple[Choice, list]:
-    """Best (cut, key length, trace options) for a reordering method, by total encode + sort +
-    trace time.  mode: 'hcc' or 'twopoint' (cut ignored).  With paper_exact only C = K pairs,
-    otherwise every pair with C >= K (the key then holds the K cut nodes of highest HAD)."""
+                 candidates=None, reps: int = 2, paper_exact: bool = True, skips=(0,)) -> tuple[Choice, list]:
+    """Best (cut, key length, skipped low bits, trace options) for a reordering method, by total
+    encode + sort + trace time.  mode: 'hcc' or 'twopoint' (cut ignored).  With paper_exact only
+    C = K pairs, otherwise every pair with C >= K (the key then holds the K cut nodes of highest
+    HAD).  skips: numbers of low key bits the sort may leave out (the paper's shortened sort);
+    the trace options are tuned on the first of them and reused for the others."""
     n = rays.shape[0]
     dev = rays.device
     results = []
@@ -89,6 +93,8 @@ def tune_reorder(bvh, rays, mode: str, cuts=(32, 64), key_bits=(32, 64), closest
         pairs = [(c, k) for c, k in itertools.product(cuts, key_bits) if (c == k or (not paper_exact and c >= k))]
     else:
         pairs = [(0, k) for k in key_bits]
+    out = (torch.empty((n, 4), dtype=torch.float32, device=dev) if closest
+           else torch.empty(n, dtype=torch.uint8, device=dev))
     for c, k in pairs:
         cut = select_cut(bvh, c) if mode == "hcc" else None
         keys = torch.empty(n, dtype=torch.int32 if k <= 32 else torch.int64, device=dev)
@@ -96,8 +102,15 @@ def tune_reorder(bvh, rays, mode: str, cuts=(32, 64), key_bits=(32, 64), closest
         ws = torch.empty(sort_workspace_bytes(n, k), dtype=torch.uint8, device=dev)
         m = KEY_HCC if mode == "hcc" else KEY_TWOPOINT
         enc_ms = _time(lambda: encode(bvh, cut, m, k, rays, out=keys), reps)
-        sort_ms = _time(lambda: sort(keys, k, perm=perm, ws=ws), reps)
-        o, tr_ms, _ = tune_trace(bvh, rays, perm, closest, candidates, reps)
-        results.append(Choice(mode, c, k, o, enc_ms, sort_ms, tr_ms))
+        o = None
+        for s in skips:
+            if s >= k:
+                continue
+            sort_ms = _time(lambda: sort_ex(keys, k, s, 0, perm=perm, ws=ws), reps)
+            if o is None:
+                o, tr_ms, _ = tune_trace(bvh, rays, perm, closest, candidates, reps)
+            else:
+                tr_ms = _time(lambda: trace(bvh, rays, perm, closest=closest, out=out, opts=o), reps)
+            results.append(Choice(mode, c, k, o, enc_ms, sort_ms, tr_ms, s))
     results.sort(key=lambda ch: ch.total_ms)
     return results[0], results
