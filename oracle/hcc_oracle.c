@@ -549,7 +549,7 @@ void oracle_encode_twopoint(const float* rays, uint32_t n, const float* scene_lo
 }
 
 /* ------------------------------------------------------------------ O6: sort
- * Keys sorted "as natural numbers" (Section 4.2.3), ascending; the output is the
+ * Keys sorted as unsigned integers (Section 4.2.3), ascending; the output is the
  * permutation of ray indices (the paper sorts ray indices, Section 5).  Stable:
  * equal keys keep their input order (the comparison on the index makes qsort
  * stable). */

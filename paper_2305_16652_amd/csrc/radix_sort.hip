@@ -1,6 +1,6 @@
 // Stable LSD radix sort of (key, index) pairs for gfx950, 8-bit digits.
 //
-// Sorting the ray keys "as natural numbers" and handing the trace kernel the sorted
+// Sorting the ray keys as unsigned integers and handing the trace kernel the sorted
 // ray indices is the reorder step of the method (Sections 4.2.3 and 5).  Design:
 //   1. one read of the keys builds the digit histograms of every pass at once;
 //   2. per pass, one kernel ranks a tile of 4096 keys (4 wavefronts x 16 keys per lane)
