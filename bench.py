@@ -12,7 +12,7 @@ over the whole batch.  The same batch is also timed for NoSort (trace in generat
 and TwoPoint (6-D Morton key).  Each method runs in its own fastest configuration, chosen
 before the timed region by the autotuner (trace launch options; key length; for HCC the cut
 size C from 32 to 4,096 with C >= K -- the frame configuration's cut sizes -- or only the paper's
-C = K pairs with --paper-exact).  Prints one JSON line on stdout; progress goes to stderr.
+C = K pairs with --paper-exact; key lengths 16 / 32 / 64; low key bits left out of the sort).  Prints one JSON line on stdout; progress goes to stderr.
 
 Beside the headline the line carries: the roofline of the trace kernel, the CPU oracle's rate,
 a grid of reordering methods on the same batch, bounces 2 and 3 of the frame, the 10M-triangle
@@ -54,12 +54,13 @@ def parse():
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--tune", type=int, default=1, help="autotune each method (0: use the flags below)")
     ap.add_argument("--cut", type=int, default=32)
-    ap.add_argument("--hcc-cuts", default="32,64,256,512,1024,2048,4096",
-                    help="cut sizes the HCC tuning tries (with K in {32, 64}, C >= K)")
+    ap.add_argument("--hcc-cuts", default="16,32,64,256,512,1024,2048,4096",
+                    help="cut sizes the HCC tuning tries (with each tuned key length K, C >= K)")
     ap.add_argument("--paper-exact", action="store_true", help="HCC tuning only over C = K (the paper's pairs)")
     ap.add_argument("--skips", default="0,8,16",
                     help="low key bits the tuned sort may leave out (the paper's shortened sort; 0 = full key)")
     ap.add_argument("--skip", type=int, default=0, help="skipped low key bits without tuning")
+    ap.add_argument("--tune-key-bits", default="16,32,64", help="key lengths the reordering tuning tries")
     ap.add_argument("--key-bits", type=int, default=32)
     ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--stack", type=int, default=0, help="0 scratch, 1 LDS, 2 LDS+scratch")
@@ -161,11 +162,12 @@ def main():
             continue
         if args.tune:
             sk = tuple(int(x) for x in args.skips.split(","))
+            kb = tuple(int(x) for x in args.tune_key_bits.split(","))
             if m == "hcc":
                 cs = tuple(int(c) for c in args.hcc_cuts.split(","))
-                ch, _ = AT.tune_reorder(bvh, rays, m, cuts=cs, paper_exact=args.paper_exact, skips=sk)
+                ch, _ = AT.tune_reorder(bvh, rays, m, cuts=cs, key_bits=kb, paper_exact=args.paper_exact, skips=sk)
             else:
-                ch, _ = AT.tune_reorder(bvh, rays, m, skips=sk)
+                ch, _ = AT.tune_reorder(bvh, rays, m, key_bits=kb, skips=sk)
             conf[m] = dict(cut=ch.cut, key_bits=ch.key_bits, skip=ch.skip, opts=ch.opts)
         else:
             conf[m] = dict(cut=args.cut if m == "hcc" else 0, key_bits=args.key_bits, skip=args.skip, opts=flag_opts)
