@@ -489,26 +489,28 @@ def run_batched(H, args):
 
     res = {}
     cuts = {}
-    for K in (16, 24, 32):
-        cuts[K] = [H.select_cut(s["bvh"], K) for s in scenes]
-    # engine options: autotuned over chunk, refill and key length (cut = key length)
+    # engine options: autotuned over key length K, cut size C (C = K, or a 256-node cut whose K
+    # cut nodes of highest HAD form the key), chunk, refill and the trace flags
+    pairs = [(K, C) for K in (8, 16, 24, 32) for C in sorted({K, 256})]
+    for K, C in pairs:
+        cuts[C] = cuts.get(C) or [H.select_cut(s["bvh"], C) for s in scenes]
     best = None
     table = []
-    for K in (16, 24, 32):
+    for K, C in pairs:
         for b, p in zip(batches, plan):
-            b.cut = cuts[K][p["scene"]]
+            b.cut = cuts[C][p["scene"]]
         ws = H.batch_run(batches, H.KEY_HCC, K)
         for chunk in (128, 256, 512):
             for refill in (24, 32):
                 for flags in (0, H.TRACE_WIDE, H.TRACE_WIDE | H.TRACE_SLAB):
                     o = H.BatchOpts(chunk, refill, 8192, flags)
                     ms = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws), reps=2)
-                    table.append((ms, K, chunk, refill, flags))
+                    table.append((ms, K, C, chunk, refill, flags))
                     if best is None or ms < best[0]:
-                        best = (ms, K, chunk, refill, flags)
-    _, K, chunk, refill, flags = best
+                        best = (ms, K, C, chunk, refill, flags)
+    _, K, C, chunk, refill, flags = best
     for b, p in zip(batches, plan):
-        b.cut = cuts[K][p["scene"]]
+        b.cut = cuts[C][p["scene"]]
     o = H.BatchOpts(chunk, refill, 8192, flags, 0)
     ws = H.batch_run(batches, H.KEY_HCC, K, opts=o)
     res["engine_hcc_ms"] = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws))
@@ -526,12 +528,12 @@ def run_batched(H, args):
     res["plain_nosort_ms"] = timeit(lambda: plain(0, K))
     out = {k.replace("_ms", "_mrays_s"): round(total / (v * 1e-3) / 1e6, 1) for k, v in res.items()}
     out.update({k: round(v, 3) for k, v in res.items()})
-    out.update(dict(batches=len(plan), rays=total, key_bits=K, cut=K,
+    out.update(dict(batches=len(plan), rays=total, key_bits=K, cut=C,
                     engine_opts=dict(chunk=chunk, refill=refill, flags=flags), hybrid_direct_min=direct_min,
                     plain_trace_opts=AT.opts_dict(topts),
                     speedup_engine_vs_plain_hcc=round(res["plain_hcc_ms"] / res["engine_hcc_ms"], 3),
                     scenes="cluster 10K/100K/1M/2M triangles",
-                    tuning=[dict(ms=round(t[0], 3), key_bits=t[1], chunk=t[2], refill=t[3], flags=t[4])
+                    tuning=[dict(ms=round(t[0], 3), key_bits=t[1], cut=t[2], chunk=t[3], refill=t[4], flags=t[5])
                             for t in sorted(table)[:5]]))
     log(f"batched: engine HCC {out['engine_hcc_mrays_s']} Mrays/s (with direct launches >= {direct_min} rays: "
         f"{out['hybrid_hcc_mrays_s']}) vs plain {out['plain_hcc_mrays_s']}; NoSort engine "
