@@ -516,12 +516,21 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
         const uint64_t waiting = __ballot(has && pmask != 0);
         const uint64_t stepping = __ballot(can_step);
         if (waiting != 0 && (2 * __popcll(waiting) >= __popcll(busy) || stepping == 0)) {
-            if (has && pmask != 0) {
-                const uint4 r = sc.wnodes[pnode].ref;
-                if (pmask & 1u) test_tri(r.x & ~kWideLeaf);
-                if ((pmask & 2u) && (closest || !found)) test_tri(r.y & ~kWideLeaf);
-                if ((pmask & 4u) && (closest || !found)) test_tri(r.z & ~kWideLeaf);
-                if ((pmask & 8u) && (closest || !found)) test_tri(r.w & ~kWideLeaf);
+            const bool mine = has && pmask != 0;
+            uint4 r = make_uint4(kNone, kNone, kNone, kNone);
+            if (mine) r = sc.wnodes[pnode].ref;
+            // pending triangles lowest slot first, one per lane and round
+            uint32_t left = mine ? pmask : 0u;
+            while (__ballot(left != 0) != 0) {
+                if (left != 0) {
+                    const uint32_t j = __builtin_ctz(left);
+                    left &= left - 1u;
+                    const uint32_t ref = j == 0 ? r.x : (j == 1 ? r.y : (j == 2 ? r.z : r.w));
+                    test_tri(ref & ~kWideLeaf);
+                    if (!closest && found) left = 0;
+                }
+            }
+            if (mine) {
                 pmask = 0;
                 if (!closest && found) node = kNone;
             }

@@ -549,11 +549,19 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
                 c_tris += wave_distinct_on(r.z, mine && (pmask & 4u));
                 c_tris += wave_distinct_on(r.w, mine && (pmask & 8u));
             }
+            // each lane tests its pending triangles lowest slot first, one per round: the
+            // wavefront runs as many rounds as its fullest lane has triangles, not one per slot
+            uint32_t left = mine ? pmask : 0u;
+            while (__ballot(left != 0) != 0) {
+                if (left != 0) {
+                    const uint32_t j = __builtin_ctz(left);
+                    left &= left - 1u;
+                    const uint32_t ref = j == 0 ? r.x : (j == 1 ? r.y : (j == 2 ? r.z : r.w));
+                    test_tri(ref & ~kWideLeaf);
+                    if (!kClosest && found) left = 0;
+                }
+            }
             if (mine) {
-                if (pmask & 1u) test_tri(r.x & ~kWideLeaf);
-                if ((pmask & 2u) && (kClosest || !found)) test_tri(r.y & ~kWideLeaf);
-                if ((pmask & 4u) && (kClosest || !found)) test_tri(r.z & ~kWideLeaf);
-                if ((pmask & 8u) && (kClosest || !found)) test_tri(r.w & ~kWideLeaf);
                 pmask = 0;
                 if (!kClosest && found) node = kNone;
             }
