@@ -424,11 +424,12 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
     uint32_t end = min(next + chunk, n);
     const uint64_t below = lanes_below();
     __shared__ uint32_t s_stack[kLds ? kLds * 64 : 1];
+    __shared__ uint4 s_leaf[64];   // refs of the node whose hit leaves a lane has pending
     WideStack<kLds> stack;
     stack.init(s_stack);
     bool has = false;
     uint32_t rid = 0, node = kNone, sp = 0, best_prim = kMissPrim;
-    uint32_t pnode = 0, pmask = 0;
+    uint32_t pmask = 0;
     float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, ix = 0, iy = 0, iz = 0, tmin = 0, tmax = 0;
     float best_t = 0, best_u = 0, best_v = 0;
     WideRay wr{0, 0, 0, false};
@@ -498,15 +499,13 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
             float tt[4];
             wide_test<decltype(kind)::value>(wn, node, wr, ox, oy, oz, ix, iy, iz, tmin, kClosest ? best_t : tmax, r,
                                              hh, tt);
+            s_leaf[__lane_id()] = r;   // read back only if this step leaves hit leaves pending
             const bool h0 = hh[0], h1 = hh[1], h2 = hh[2], h3 = hh[3];
             const float t0 = tt[0], t1 = tt[1], t2 = tt[2], t3 = tt[3];
             const bool l0 = h0 && (r.x & kWideLeaf), l1 = h1 && (r.y & kWideLeaf);
             const bool l2 = h2 && (r.z & kWideLeaf), l3 = h3 && (r.w & kWideLeaf);
             const uint32_t lm = (l0 ? 1u : 0u) | (l1 ? 2u : 0u) | (l2 ? 4u : 0u) | (l3 ? 8u : 0u);
-            if (lm) {
-                pnode = node;
-                pmask = lm;
-            }
+            if (lm) pmask = lm;
             // hit internal children, nearest first (a missed or leaf slot sorts last as kNone)
             float k0 = (h0 && !l0) ? t0 : INFINITY, k1 = (h1 && !l1) ? t1 : INFINITY;
             float k2 = (h2 && !l2) ? t2 : INFINITY, k3 = (h3 && !l3) ? t3 : INFINITY;
@@ -542,7 +541,7 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
         if (waiting != 0 && (2 * __popcll(waiting) >= __popcll(busy) || stepping == 0)) {
             const bool mine = has && pmask != 0;
             uint4 r = make_uint4(kNone, kNone, kNone, kNone);
-            if (mine) r = wn[pnode].ref;
+            if (mine) r = s_leaf[__lane_id()];
             if (kStats) {
                 c_tris += wave_distinct_on(r.x, mine && (pmask & 1u));
                 c_tris += wave_distinct_on(r.y, mine && (pmask & 2u));
