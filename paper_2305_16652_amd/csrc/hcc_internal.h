@@ -153,9 +153,10 @@ __device__ __forceinline__ bool tri_test(const Tri& tr, float ox, float oy, floa
     const float e2x = tr.q.z, e2y = tr.q.w, e2z = tr.r.x;
     const float px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
     const float det = (e1x * px + e1y * py) + e1z * pz;
+    // s before the first exit, so that all of the triangle is fetched in one round trip
+    const float sx = ox - v0x, sy = oy - v0y, sz = oz - v0z;
     if (det == 0.0f) return false;
     const float inv = 1.0f / det;
-    const float sx = ox - v0x, sy = oy - v0y, sz = oz - v0z;
     u = ((sx * px + sy * py) + sz * pz) * inv;
     if (!(u >= 0.0f && u <= 1.0f)) return false;
     const float qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
