@@ -397,6 +397,9 @@ struct WideStack {
         else deep[sp - kLds] = x;
     }
     __device__ uint32_t pop(uint32_t sp) { return sp < (uint32_t)kLds ? lds[sp * 64] : deep[sp - kLds]; }
+    // entries known to sit in the LDS part (sp < kLds)
+    __device__ void push_lds(uint32_t sp, uint32_t x) { lds[sp * 64] = x; }
+    __device__ uint32_t pop_lds(uint32_t sp) { return lds[sp * 64]; }
 };
 
 template <>
@@ -405,6 +408,8 @@ struct WideStack<0> {
     __device__ void init(uint32_t*) {}
     __device__ void push(uint32_t sp, uint32_t x) { s[sp] = x; }
     __device__ uint32_t pop(uint32_t sp) { return s[sp]; }
+    __device__ void push_lds(uint32_t sp, uint32_t x) { s[sp] = x; }
+    __device__ uint32_t pop_lds(uint32_t sp) { return s[sp]; }
 };
 
 template <bool kClosest, bool kStats, int kLds>
@@ -516,15 +521,26 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
             cswap(k0, i0, k2, i2);
             cswap(k1, i1, k3, i3);
             cswap(k1, i1, k2, i2);
-            if (i3 < n_int && sp < kWideStack) stack.push(sp++, i3);
-            if (i2 < n_int && sp < kWideStack) stack.push(sp++, i2);
-            if (i1 < n_int && sp < kWideStack) stack.push(sp++, i1);
-            if (i0 < n_int) {
-                node = i0;
-            } else if (sp == 0) {
-                node = kNone;
+            if (kLds > 0 && __ballot(sp + 3 > (uint32_t)kLds) == 0) {
+                // every stepping lane has room for three more entries in the LDS part of its
+                // stack: no per-entry choice between LDS and scratch
+                if (i3 < n_int) stack.push_lds(sp++, i3);
+                if (i2 < n_int) stack.push_lds(sp++, i2);
+                if (i1 < n_int) stack.push_lds(sp++, i1);
+                if (i0 < n_int) node = i0;
+                else if (sp == 0) node = kNone;
+                else node = stack.pop_lds(--sp);
             } else {
-                node = stack.pop(--sp);
+                if (i3 < n_int && sp < kWideStack) stack.push(sp++, i3);
+                if (i2 < n_int && sp < kWideStack) stack.push(sp++, i2);
+                if (i1 < n_int && sp < kWideStack) stack.push(sp++, i1);
+                if (i0 < n_int) {
+                    node = i0;
+                } else if (sp == 0) {
+                    node = kNone;
+                } else {
+                    node = stack.pop(--sp);
+                }
             }
         };
         if (fast_nodes && __ballot(step && !wr.fast) == 0) {
