@@ -189,15 +189,16 @@ __device__ __forceinline__ uint32_t wave_distinct_on(uint32_t x, bool on) {
     return count;
 }
 
+// Compare-exchange by selects (no branch: a branch per exchange costs more than the four
+// selects in a wavefront whose lanes disagree).
 __device__ __forceinline__ void cswap(float& ka, uint32_t& ia, float& kb, uint32_t& ib) {
-    if (kb < ka) {
-        const float k = ka;
-        ka = kb;
-        kb = k;
-        const uint32_t i = ia;
-        ia = ib;
-        ib = i;
-    }
+    const bool sw = kb < ka;
+    const float k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+    const uint32_t i0 = sw ? ib : ia, i1 = sw ? ia : ib;
+    ka = k0;
+    kb = k1;
+    ia = i0;
+    ib = i1;
 }
 
 __device__ __forceinline__ uint64_t lanes_below() {
@@ -524,12 +525,18 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
             if (kLds > 0 && __ballot(sp + 3 > (uint32_t)kLds) == 0) {
                 // every stepping lane has room for three more entries in the LDS part of its
                 // stack: no per-entry choice between LDS and scratch
-                if (i3 < n_int) stack.push_lds(sp++, i3);
-                if (i2 < n_int) stack.push_lds(sp++, i2);
-                if (i1 < n_int) stack.push_lds(sp++, i1);
-                if (i0 < n_int) node = i0;
-                else if (sp == 0) node = kNone;
-                else node = stack.pop_lds(--sp);
+                // without branches: each candidate is written at the top and kept if valid (the
+                // three slots above sp exist), and the top is read back for the pop
+                stack.push_lds(sp, i3);
+                sp += i3 < n_int ? 1u : 0u;
+                stack.push_lds(sp, i2);
+                sp += i2 < n_int ? 1u : 0u;
+                stack.push_lds(sp, i1);
+                sp += i1 < n_int ? 1u : 0u;
+                const uint32_t top = stack.pop_lds(sp > 0 ? sp - 1 : 0);
+                const bool descend = i0 < n_int;
+                node = descend ? i0 : (sp == 0 ? kNone : top);
+                sp -= (!descend && sp > 0) ? 1u : 0u;
             } else {
                 if (i3 < n_int && sp < kWideStack) stack.push(sp++, i3);
                 if (i2 < n_int && sp < kWideStack) stack.push(sp++, i2);
