@@ -447,13 +447,17 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
         const Tri tr = tris[slot];
         const uint32_t prim = __float_as_uint(tr.r.y);
         float t, u, v;
-        if (tri_test(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v)) {
-            if (!kClosest) {
-                found = true;
-            } else if (t < best_t || (t == best_t && prim < best_prim)) {
-                best_t = t; best_u = u; best_v = v; best_prim = prim;
-                found = true;
-            }
+        const bool hit = tri_test(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v);
+        if (!kClosest) {
+            found = found || hit;
+        } else {
+            // nearer hit, or an equally near one of a smaller triangle id: taken by selects
+            const bool take = hit && (t < best_t || (t == best_t && prim < best_prim));
+            best_t = take ? t : best_t;
+            best_u = take ? u : best_u;
+            best_v = take ? v : best_v;
+            best_prim = take ? prim : best_prim;
+            found = found || take;
         }
     };
 
@@ -511,7 +515,7 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
             const bool l0 = h0 && (r.x & kWideLeaf), l1 = h1 && (r.y & kWideLeaf);
             const bool l2 = h2 && (r.z & kWideLeaf), l3 = h3 && (r.w & kWideLeaf);
             const uint32_t lm = (l0 ? 1u : 0u) | (l1 ? 2u : 0u) | (l2 ? 4u : 0u) | (l3 ? 8u : 0u);
-            if (lm) pmask = lm;
+            pmask = lm;   // a stepping lane has none pending
             // hit internal children, nearest first (a missed or leaf slot sorts last as kNone)
             float k0 = (h0 && !l0) ? t0 : INFINITY, k1 = (h1 && !l1) ? t1 : INFINITY;
             float k2 = (h2 && !l2) ? t2 : INFINITY, k3 = (h3 && !l3) ? t3 : INFINITY;
