@@ -67,7 +67,7 @@ namespace {
 
 constexpr uint32_t kTile = 1024;      // keys per encode / sort tile (64 lanes x 16)
 constexpr uint32_t kDirectFloor = 65536;   // smallest batch that may take a direct launch
-constexpr int kEngShort = 8;               // 4-wide trace: stack entries per lane kept in LDS
+constexpr int kEngShort = 12;              // 4-wide trace: stack entries per lane kept in LDS
 constexpr uint32_t kPerLane = 16;
 constexpr uint32_t kRadix = 256;
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagIncl = 2u << 30, kCountMask = (1u << 30) - 1u;
@@ -395,15 +395,15 @@ __device__ void trace_range(const EngScene& sc, const EngBatch& bt, const uint32
     }
 }
 
+// compare-exchange by selects (no branch)
 __device__ __forceinline__ void cswap4(float& ka, uint32_t& ia, float& kb, uint32_t& ib) {
-    if (kb < ka) {
-        const float k = ka;
-        ka = kb;
-        kb = k;
-        const uint32_t i = ia;
-        ia = ib;
-        ib = i;
-    }
+    const bool sw = kb < ka;
+    const float k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+    const uint32_t i0 = sw ? ib : ia, i1 = sw ? ia : ib;
+    ka = k0;
+    kb = k1;
+    ia = i0;
+    ib = i1;
 }
 
 // ---- T over the 4-wide nodes (the persistent 4-wide trace kernel's step, for rays
@@ -433,13 +433,16 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
         const Tri tr = sc.tris[slot];
         const uint32_t prim = __float_as_uint(tr.r.y);
         float t, u, v;
-        if (tri_test(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v)) {
-            if (!closest) {
-                found = true;
-            } else if (t < best_t || (t == best_t && prim < best_prim)) {
-                best_t = t; best_u = u; best_v = v; best_prim = prim;
-                found = true;
-            }
+        const bool hit = tri_test(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v);
+        if (!closest) {
+            found = found || hit;
+        } else {
+            const bool take = hit && (t < best_t || (t == best_t && prim < best_prim));
+            best_t = take ? t : best_t;
+            best_u = take ? u : best_u;
+            best_v = take ? v : best_v;
+            best_prim = take ? prim : best_prim;
+            found = found || take;
         }
     };
     while (true) {
@@ -499,12 +502,27 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
             cswap4(k0, i0, k2, i2);
             cswap4(k1, i1, k3, i3);
             cswap4(k1, i1, k2, i2);
-            if (i3 < n_int && sp < kWideStack) push(sp++, i3);
-            if (i2 < n_int && sp < kWideStack) push(sp++, i2);
-            if (i1 < n_int && sp < kWideStack) push(sp++, i1);
-            if (i0 < n_int) node = i0;
-            else if (sp == 0) node = kNone;
-            else node = pop(--sp);
+            if (__ballot(sp + 3 > (uint32_t)kEngShort) == 0) {
+                // every stepping lane has three free LDS slots above its stack top: candidates
+                // are written there and kept if valid, and the top is read back for the pop
+                lds[sp * 64] = i3;
+                sp += i3 < n_int ? 1u : 0u;
+                lds[sp * 64] = i2;
+                sp += i2 < n_int ? 1u : 0u;
+                lds[sp * 64] = i1;
+                sp += i1 < n_int ? 1u : 0u;
+                const uint32_t top = lds[(sp > 0 ? sp - 1 : 0) * 64];
+                const bool descend = i0 < n_int;
+                node = descend ? i0 : (sp == 0 ? kNone : top);
+                sp -= (!descend && sp > 0) ? 1u : 0u;
+            } else {
+                if (i3 < n_int && sp < kWideStack) push(sp++, i3);
+                if (i2 < n_int && sp < kWideStack) push(sp++, i2);
+                if (i1 < n_int && sp < kWideStack) push(sp++, i1);
+                if (i0 < n_int) node = i0;
+                else if (sp == 0) node = kNone;
+                else node = pop(--sp);
+            }
         };
         if (fast_nodes && __ballot(step && !wr.fast) == 0) {
             if (step) node_step(std::true_type{});
