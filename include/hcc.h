@@ -58,7 +58,7 @@ typedef enum { HCC_TRACE_CLOSEST = 0, HCC_TRACE_ANY = 1 } hcc_trace_mode;
 typedef enum {
     HCC_STACK_SCRATCH = 0,    /* per-lane traversal stack in private (scratch) memory (default) */
     HCC_STACK_LDS = 1,        /* BVH2 kernels: whole stack in LDS (64 entries); 4-wide: first 24 in LDS */
-    HCC_STACK_SHORT = 2       /* first entries in LDS (BVH2: 16, 4-wide: 12), deeper ones in scratch */
+    HCC_STACK_SHORT = 2       /* first entries in LDS (BVH2: 16, 4-wide: 16), deeper ones in scratch */
 } hcc_stack_mode;
 
 typedef struct hcc_bvh_s* hcc_bvh;

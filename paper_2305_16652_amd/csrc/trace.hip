@@ -386,8 +386,9 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
 // wavefront into counts[0] and counts[1]).
 // Per-lane stack of the 4-wide traversal: the first entries in LDS (lane-interleaved, conflict
 // free), deeper ones in scratch; or all of it in scratch.
-// kLds = 0: all in scratch; otherwise the number of entries kept in LDS (12 for
-// HCC_STACK_SHORT, 24 for HCC_STACK_LDS).
+// kLds = 0: all in scratch; otherwise the number of entries kept in LDS (16 for
+// HCC_STACK_SHORT: with the 1 KB of pending-leaf refs that is 5 KB per wavefront, so the LDS
+// of a CU holds exactly its 32 wavefronts; 24 for HCC_STACK_LDS).
 template <int kLds>
 struct WideStack {
     uint32_t* lds;
@@ -654,16 +655,16 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
     const float4* r = (const float4*)rays;
     float4* h = (float4*)hits;
     if (o.flags & HCC_TRACE_WIDE) {
-        // stack: scratch (HCC_STACK_SCRATCH, and always when counting), the first 12 entries in
+        // stack: scratch (HCC_STACK_SCRATCH, and always when counting), the first 16 entries in
         // LDS (HCC_STACK_SHORT) or the first 24 (HCC_STACK_LDS)
-        const int lds = kStats ? 0 : (o.stack == HCC_STACK_SHORT ? 12 : (o.stack == HCC_STACK_LDS ? 24 : 0));
+        const int lds = kStats ? 0 : (o.stack == HCC_STACK_SHORT ? 16 : (o.stack == HCC_STACK_LDS ? 24 : 0));
 #define HCC_WIDE(CL, LD)                                                                                       \
     k_trace_wide<CL, kStats, LD><<<waves, 64, 0, s>>>(b->wnodes, b->tris, b->n_int, r, perm, n, h, occ, refill, \
                                                       chunk, o.xcd_remap, (o.flags & HCC_TRACE_SLAB) ? 1u : 0u, counts)
         if (closest) {
-            if (lds == 12) HCC_WIDE(true, 12); else if (lds == 24) HCC_WIDE(true, 24); else HCC_WIDE(true, 0);
+            if (lds == 16) HCC_WIDE(true, 16); else if (lds == 24) HCC_WIDE(true, 24); else HCC_WIDE(true, 0);
         } else {
-            if (lds == 12) HCC_WIDE(false, 12); else if (lds == 24) HCC_WIDE(false, 24); else HCC_WIDE(false, 0);
+            if (lds == 16) HCC_WIDE(false, 16); else if (lds == 24) HCC_WIDE(false, 24); else HCC_WIDE(false, 0);
         }
 #undef HCC_WIDE
         HCC_HIP(hipGetLastError());
