@@ -667,7 +667,7 @@ def run_bounces(H, args, bvh, tris_h, sec, rays, hcc_ck):
     prev, prev_d = sec, rays
     for bounce in (2, 3):
         t0 = time.time()
-        h = H.trace(bvh, prev_d, opts=H.TraceOpts(64, 2, 0, 1, 32, 64, 16384, H.TRACE_WIDE)).cpu().numpy()
+        h = H.trace(bvh, prev_d, opts=H.TraceOpts(64, 2, 0, 1, 32, 128, 8192, H.TRACE_WIDE)).cpu().numpy()
         nxt, _ = W.spawn_diffuse(prev, h[:, 0].copy(), h[:, 1].copy().view(np.uint32), tris_h, seed=7,
                                  bounce=bounce - 1)
         rd = torch.from_numpy(nxt).to(rays.device)

@@ -91,10 +91,18 @@ typedef struct hcc_hit { float t; uint32_t prim; float u, v; } hcc_hit;   /* mis
 typedef struct hcc_trace_opts {
     uint32_t block;           /* one-ray-per-lane launch: threads per block, 64, 128 or 256 (0 = 64) */
     uint32_t stack;           /* hcc_stack_mode */
-    uint32_t xcd_remap;       /* 1 = give each XCD a contiguous range of rays / chunks (0 = hardware order) */
+    uint32_t xcd_remap;       /* 1 = give each XCD a contiguous range of rays / chunks (0 = hardware order);
+                                 persistent launches: the static chunk order only (see chunk) */
     uint32_t persistent;      /* 1 = persistent wavefronts that refill idle lanes with new rays */
     uint32_t refill;          /* persistent: refill when at least this many lanes are idle, 1..64 (0 = 16) */
-    uint32_t chunk;           /* persistent: consecutive rays a wavefront owns at a time, >= 64 (0 = 256) */
+    uint32_t chunk;           /* persistent: consecutive rays a wavefront owns at a time, >= 64 (0 = 256).
+                                 A wavefront whose chunk runs out takes the next one from a
+                                 per-stream device counter the library keeps (one of 256 slots per
+                                 device, taken on the stream's first persistent launch); while
+                                 the stream is being captured into a graph, once the slots are
+                                 taken, and in hcc_trace_count, wavefront w takes chunks w,
+                                 w + waves, w + 2 waves, ... instead.  Results are the same
+                                 either way. */
     uint32_t waves;           /* persistent: wavefronts launched (0 = 8192) */
     uint32_t flags;           /* HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB */
 } hcc_trace_opts;

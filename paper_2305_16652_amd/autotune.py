@@ -22,7 +22,7 @@ PLAIN = [TraceOpts(b, s, 0, 0, 0, 0, 0, 0) for b in (64, 128) for s in (0, 2)]
 PERSISTENT = [TraceOpts(64, s, 0, 1, r, c, 8192, f)
               for s in (0,) for r in (24, 32) for c in (64, 128, 256) for f in (0, 1)]
 # 4-wide: LDS short stack, both child-box tests (selected planes / slab, flags 2 / 6)
-WIDE = [TraceOpts(64, 2, 0, 1, r, c, w, f) for f in (2, 6) for r in (24, 32) for c in (64, 128) for w in (8192, 16384)]
+WIDE = [TraceOpts(64, 2, 0, 1, r, c, 8192, f) for f in (2, 6) for r in (24, 32) for c in (64, 128, 256)]
 DEFAULT_CANDIDATES = PLAIN + PERSISTENT + WIDE
 
 

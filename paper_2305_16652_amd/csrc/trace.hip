@@ -10,7 +10,10 @@
 //
 // Closest hit keeps the smallest (t, triangle index) pair, which makes the answer
 // independent of traversal order; any hit stops at the first triangle in the segment.
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "hcc_internal.h"
 
@@ -206,6 +209,54 @@ __device__ __forceinline__ uint64_t lanes_below() {
     return lane == 0 ? 0ull : (~0ull >> (64u - lane));
 }
 
+// Chunks of a persistent launch: it deals out the sorted positions in chunks of `chunk`
+// consecutive ones.  With a queue slot a wavefront takes the next chunk from a device counter
+// whenever its own runs out, so wavefronts that drew cheap rays take more chunks and all of them
+// finish together; without one (counting launches, launches captured into a graph, streams
+// beyond the slots) wavefront w takes chunks w, w + grid, w + 2 grid, ...  A slot is 128 bytes
+// per stream that launches persistent traces, claimed on the stream's first launch: word 0 is
+// the next chunk, word 1 the number of wavefronts done; the launch's last wavefront puts both
+// back to 0, so a slot reads zero whenever no launch of its stream runs (launches on one stream
+// never overlap).
+constexpr uint32_t kQueueSlots = 256, kQueueWords = 32, kNoQueue = 0xFFFFFFFFu;
+__device__ uint32_t g_chunk_queue[kQueueSlots * kQueueWords];
+
+struct Chunks {
+    uint32_t* q;
+    uint32_t n, chunk, nchunks, cidx, next, end;
+    // wavefront-uniform calls only (every lane of the wavefront active)
+    __device__ void init(uint32_t slot, uint32_t n_, uint32_t chunk_, uint32_t remap) {
+        q = slot == kNoQueue ? nullptr : g_chunk_queue + (size_t)slot * kQueueWords;
+        n = n_;
+        chunk = chunk_;
+        nchunks = (n + chunk - 1) / chunk;
+        // remap: the wavefronts the hardware deals to one XCD start on consecutive chunks
+        cidx = q ? take() : (remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x);
+        set();
+    }
+    __device__ uint32_t take() {
+        uint32_t c = 0;
+        if (__lane_id() == 0) c = atomicAdd(q, 1u);
+        return __shfl(c, 0);
+    }
+    __device__ void set() {
+        next = cidx < nchunks ? cidx * chunk : n;
+        end = cidx < nchunks ? min(next + chunk, n) : n;
+    }
+    // the wavefront's next chunk, once the current one is dealt out (chunks are never empty)
+    __device__ void advance() {
+        if (next < end || cidx >= nchunks) return;
+        cidx = q ? take() : cidx + gridDim.x;
+        set();
+    }
+    __device__ void finish() {
+        if (q && __lane_id() == 0 && atomicAdd(q + 1, 1u) == gridDim.x - 1) {
+            atomicExch(q, 0u);
+            atomicExch(q + 1, 0u);
+        }
+    }
+};
+
 // Persistent wavefronts (one wavefront per block).  Wavefront b owns chunks b, b + grid,
 // b + 2 grid, ... of the trace order; whenever at least 'refill' of its lanes are idle it
 // hands them the next rays of its current chunk.  Lanes whose ray finished early therefore
@@ -224,16 +275,11 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
                                                          const uint32_t* __restrict__ perm, uint32_t n,
                                                          float4* __restrict__ hits, uint8_t* __restrict__ occ,
                                                          uint32_t refill, uint32_t chunk, uint32_t remap,
-                                                         unsigned long long* __restrict__ counts) {
+                                                         uint32_t qslot, unsigned long long* __restrict__ counts) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     __shared__ uint32_t s_stack[lds_entries<kStack>() * 64];
-    const uint32_t nchunks = (n + chunk - 1) / chunk;
-    // remap: the wavefronts the hardware deals to one XCD take consecutive chunks, so each
-    // XCD's L2 sees one stretch of the (sorted) order at a time
-    uint32_t cidx = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-    if (cidx >= nchunks) return;
-    uint32_t next = cidx * chunk;
-    uint32_t end = min(next + chunk, n);
+    Chunks ch;
+    ch.init(qslot, n, chunk, remap);
     const uint64_t below = lanes_below();
     Stack<kStack, 64> st;
     st.init(s_stack);
@@ -264,16 +310,10 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
         const uint64_t idle = __ballot(!has);
         const uint32_t nidle = (uint32_t)__popcll(idle);
         if (nidle >= refill) {
-            while (next >= end && cidx < nchunks) {
-                cidx += gridDim.x;
-                if (cidx < nchunks) {
-                    next = cidx * chunk;
-                    end = min(next + chunk, n);
-                }
-            }
-            if (next < end) {
-                const uint32_t k = next + (uint32_t)__popcll(idle & below);
-                if (!has && k < end) {
+            ch.advance();
+            if (ch.next < ch.end) {
+                const uint32_t k = ch.next + (uint32_t)__popcll(idle & below);
+                if (!has && k < ch.end) {
                     rid = perm ? perm[k] : k;
                     if (rid < n) {
                         const float4 ra = rays[2 * (size_t)rid];
@@ -290,7 +330,7 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
                         has = true;
                     }
                 }
-                next = min(next + nidle, end);
+                ch.next = min(ch.next + nidle, ch.end);
             } else if (nidle == 64) {
                 break;
             }
@@ -375,6 +415,7 @@ __global__ __launch_bounds__(64) void k_trace_persistent(const Node* __restrict_
         atomicAdd(counts, (unsigned long long)c_nodes);
         atomicAdd(counts + 1, (unsigned long long)c_tris);
     }
+    ch.finish();
 }
 
 // Persistent wavefronts over the 4-wide nodes (same refill and batched-leaf scheme as
@@ -420,15 +461,10 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
                                                    const uint32_t* __restrict__ perm, uint32_t n,
                                                    float4* __restrict__ hits, uint8_t* __restrict__ occ,
                                                    uint32_t refill, uint32_t chunk, uint32_t remap, uint32_t slab,
-                                                   unsigned long long* __restrict__ counts) {
+                                                   uint32_t qslot, unsigned long long* __restrict__ counts) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;
-    const uint32_t nchunks = (n + chunk - 1) / chunk;
-    // remap: the wavefronts the hardware deals to one XCD take consecutive chunks, so each
-    // XCD's L2 sees one stretch of the (sorted) order at a time
-    uint32_t cidx = remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-    if (cidx >= nchunks) return;
-    uint32_t next = cidx * chunk;
-    uint32_t end = min(next + chunk, n);
+    Chunks ch;
+    ch.init(qslot, n, chunk, remap);
     const uint64_t below = lanes_below();
     __shared__ uint32_t s_stack[kLds ? kLds * 64 : 1];
     __shared__ uint4 s_leaf[64];   // refs of the node whose hit leaves a lane has pending
@@ -467,16 +503,10 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
         const uint64_t idle = __ballot(!has);
         const uint32_t nidle = (uint32_t)__popcll(idle);
         if (nidle >= refill) {
-            while (next >= end && cidx < nchunks) {
-                cidx += gridDim.x;
-                if (cidx < nchunks) {
-                    next = cidx * chunk;
-                    end = min(next + chunk, n);
-                }
-            }
-            if (next < end) {
-                const uint32_t k = next + (uint32_t)__popcll(idle & below);
-                if (!has && k < end) {
+            ch.advance();
+            if (ch.next < ch.end) {
+                const uint32_t k = ch.next + (uint32_t)__popcll(idle & below);
+                if (!has && k < ch.end) {
                     rid = perm ? perm[k] : k;
                     if (rid < n) {
                         const float4 ra = rays[2 * (size_t)rid];
@@ -494,7 +524,7 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
                         has = true;
                     }
                 }
-                next = min(next + nidle, end);
+                ch.next = min(ch.next + nidle, ch.end);
             } else if (nidle == 64) {
                 break;
             }
@@ -610,6 +640,7 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
         atomicAdd(counts, (unsigned long long)c_nodes);
         atomicAdd(counts + 1, (unsigned long long)c_tris);
     }
+    ch.finish();
 }
 
 template <bool kClosest, int kStack, int kBlock, bool kStats>
@@ -643,6 +674,30 @@ hcc_status dispatch_stack(uint32_t stack, uint32_t block, const hcc_bvh_s* b, co
 }
 
 
+// The chunk-queue slot of stream s on the current device; kNoQueue while s is being captured
+// into a graph (a replay could overlap a launch on the stream the slot belongs to) and once
+// every slot of the device is taken.
+uint32_t queue_slot(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return kNoQueue;
+    }
+    int dev = 0;
+    if (cs != hipStreamCaptureStatusNone || hipGetDevice(&dev) != hipSuccess) return kNoQueue;
+    static std::mutex mu;
+    static std::map<std::pair<int, hipStream_t>, uint32_t> slots;
+    static std::map<int, uint32_t> taken;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(dev, s);
+    const auto it = slots.find(key);
+    if (it != slots.end()) return it->second;
+    uint32_t& used = taken[dev];
+    if (used >= kQueueSlots) return kNoQueue;
+    slots.emplace(key, used);
+    return used++;
+}
+
 // Persistent launches (BVH2 or 4-wide), optionally counting wavefront-distinct fetches.
 template <bool kStats>
 hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
@@ -652,6 +707,8 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
     const uint32_t chunk = std::max<uint32_t>(64u, o.chunk ? o.chunk : 256u);
     const uint32_t nchunks = (uint32_t)(((uint64_t)n + chunk - 1) / chunk);
     const uint32_t waves = std::min<uint32_t>(nchunks, o.waves ? o.waves : 8192u);
+    // counting launches keep the static assignment, so that their counts are reproducible
+    const uint32_t qslot = kStats ? kNoQueue : queue_slot(s);
     const float4* r = (const float4*)rays;
     float4* h = (float4*)hits;
     if (o.flags & HCC_TRACE_WIDE) {
@@ -660,7 +717,7 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
         const int lds = kStats ? 0 : (o.stack == HCC_STACK_SHORT ? 16 : (o.stack == HCC_STACK_LDS ? 24 : 0));
 #define HCC_WIDE(CL, LD)                                                                                       \
     k_trace_wide<CL, kStats, LD><<<waves, 64, 0, s>>>(b->wnodes, b->tris, b->n_int, r, perm, n, h, occ, refill, \
-                                                      chunk, o.xcd_remap, (o.flags & HCC_TRACE_SLAB) ? 1u : 0u, counts)
+                                                      chunk, o.xcd_remap, (o.flags & HCC_TRACE_SLAB) ? 1u : 0u, qslot, counts)
         if (closest) {
             if (lds == 16) HCC_WIDE(true, 16); else if (lds == 24) HCC_WIDE(true, 24); else HCC_WIDE(true, 0);
         } else {
@@ -675,11 +732,11 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
         if (o.flags & HCC_TRACE_SPECULATE)                                                                    \
             k_trace_persistent<CL, STK, true, kStats><<<waves, 64, 0, s>>>(b->nodes, b->tris, b->n_int, r, perm, \
                                                                            n, h, occ, refill, chunk,           \
-                                                                           o.xcd_remap, counts);               \
+                                                                           o.xcd_remap, qslot, counts);        \
         else                                                                                                  \
             k_trace_persistent<CL, STK, false, kStats><<<waves, 64, 0, s>>>(b->nodes, b->tris, b->n_int, r,      \
                                                                             perm, n, h, occ, refill, chunk,     \
-                                                                            o.xcd_remap, counts);               \
+                                                                            o.xcd_remap, qslot, counts);        \
     } while (0)
     if (kStats && o.stack != HCC_STACK_SCRATCH)
         return fail(HCC_ERR_UNSUPPORTED, "hcc_trace_count: counting runs with the scratch stack only");
