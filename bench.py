@@ -57,10 +57,10 @@ def parse():
     ap.add_argument("--hcc-cuts", default="16,32,64,256,512,1024,2048,4096",
                     help="cut sizes the HCC tuning tries (with each tuned key length K, C >= K)")
     ap.add_argument("--paper-exact", action="store_true", help="HCC tuning only over C = K (the paper's pairs)")
-    ap.add_argument("--skips", default="0,8,16",
+    ap.add_argument("--skips", default="0,4,8,12,14,16",
                     help="low key bits the tuned sort may leave out (the paper's shortened sort; 0 = full key)")
     ap.add_argument("--skip", type=int, default=0, help="skipped low key bits without tuning")
-    ap.add_argument("--tune-key-bits", default="16,32,64", help="key lengths the reordering tuning tries")
+    ap.add_argument("--tune-key-bits", default="8,16,32,64", help="key lengths the reordering tuning tries")
     ap.add_argument("--key-bits", type=int, default=32)
     ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--stack", type=int, default=0, help="0 scratch, 1 LDS, 2 LDS+scratch")
