@@ -57,10 +57,10 @@ def parse():
     ap.add_argument("--hcc-cuts", default="16,32,64,256,512,1024,2048,4096",
                     help="cut sizes the HCC tuning tries (with each tuned key length K, C >= K)")
     ap.add_argument("--paper-exact", action="store_true", help="HCC tuning only over C = K (the paper's pairs)")
-    ap.add_argument("--skips", default="0,4,8,12,14,16",
+    ap.add_argument("--skips", default="0,2,4,6,8,12,14,16",
                     help="low key bits the tuned sort may leave out (the paper's shortened sort; 0 = full key)")
     ap.add_argument("--skip", type=int, default=0, help="skipped low key bits without tuning")
-    ap.add_argument("--tune-key-bits", default="8,16,32,64", help="key lengths the reordering tuning tries")
+    ap.add_argument("--tune-key-bits", default="2,4,8,16,32,64", help="key lengths the reordering tuning tries")
     ap.add_argument("--key-bits", type=int, default=32)
     ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--stack", type=int, default=0, help="0 scratch, 1 LDS, 2 LDS+scratch")
@@ -491,7 +491,7 @@ def run_batched(H, args):
     cuts = {}
     # engine options: autotuned over key length K, cut size C (C = K, or a 256-node cut whose K
     # cut nodes of highest HAD form the key), chunk, refill and the trace flags
-    pairs = [(K, C) for K in (8, 16, 24, 32) for C in sorted({K, 256})]
+    pairs = [(K, C) for K in (2, 4, 8, 16, 24, 32) for C in sorted({K, 256})]
     for K, C in pairs:
         cuts[C] = cuts.get(C) or [H.select_cut(s["bvh"], C) for s in scenes]
     best = None
