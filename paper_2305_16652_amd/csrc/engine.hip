@@ -104,6 +104,21 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t& total) 
 // fault in 'err' and carries on, so a broken dependency yields wrong results, never a hang.
 constexpr uint32_t kSpinLimit = 1u << 24;
 
+// Data handed from one phase to the next inside the launch (keys, permutation values, pass
+// histograms) is stored and loaded with device-scope atomic accesses, which are coherent across
+// the XCDs' separate L2 caches.  A phase's completion count is raised only after the wavefront's
+// stores have completed, and the next phase reads that data only after seeing the count, so no
+// L2 write-back or invalidation (a device-scope fence) is needed: those flushed and emptied the
+// L2 under every tile, the trace phase's scene data included.
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dev(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void wait_count(const uint32_t* p, uint32_t target, uint32_t* err) {
     uint32_t spins = 0;
     while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -113,11 +128,15 @@ __device__ __forceinline__ void wait_count(const uint32_t* p, uint32_t target, u
             break;
         }
     }
-    __threadfence();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);   // the phase's loads stay after the wait
 }
 
 __device__ __forceinline__ void signal(uint32_t* p) {
-    __threadfence();
+    // every memory operation of this wavefront, its device-scope stores included, completes
+    // before the count is raised
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if (__lane_id() == 0) atomicAdd(p, 1u);
 }
 
@@ -164,15 +183,18 @@ __device__ K twopoint_key(const EngScene& sc, uint32_t key_bits, float4 a, float
     return key;
 }
 
-// ---- E: keys of one tile + histogram of every pass
+// ---- E: keys of one tile + histogram of every pass.  The first pass's digits are counted in
+// LDS and added to the batch's histogram once per tile (every tile of a batch adds to the same
+// few bins, so per-key global atomics would queue on them); later passes add per wavefront
+// group of equal digits.
 template <typename K>
 __device__ void encode_tile(const EngScene& sc, const EngBatch& bt, uint32_t tile, uint32_t mode, uint32_t key_bits,
-                            uint32_t passes, CutBox* s_cut) {
+                            uint32_t passes, CutBox* s_cut, uint32_t* s_h0) {
     const uint32_t lane = __lane_id();
-    if (mode == HCC_KEY_HCC) {
+    for (uint32_t j = 0; j < 4; ++j) s_h0[lane * 4 + j] = 0;
+    if (mode == HCC_KEY_HCC)
         for (uint32_t i = lane; i < sc.m; i += 64) s_cut[i] = sc.cut[i];
-        __syncthreads();
-    }
+    __syncthreads();
     const uint64_t lt = below_mask();
     K* keys = (K*)bt.keys_a;
     for (uint32_t i = 0; i < kPerLane; ++i) {
@@ -182,14 +204,22 @@ __device__ void encode_tile(const EngScene& sc, const EngBatch& bt, uint32_t til
         if (valid) {
             const float4 a = bt.rays[2 * (size_t)idx], b = bt.rays[2 * (size_t)idx + 1];
             key = mode == HCC_KEY_HCC ? hcc_key<K>(s_cut, sc.m, key_bits, a, b) : twopoint_key<K>(sc, key_bits, a, b);
-            keys[idx] = key;
+            st_dev(keys + idx, key);
         }
         for (uint32_t p = 0; p < passes; ++p) {
             const uint32_t nb = min(8u, key_bits - 8u * p);
             const uint32_t d = (uint32_t)(key >> (8u * p)) & ((1u << nb) - 1u);
             const uint64_t m = same_digit(d, nb, valid);
-            if (valid && (m & lt) == 0) atomicAdd(&bt.hist[p * kRadix + d], (uint32_t)__popcll(m));
+            if (valid && (m & lt) == 0) {
+                if (p == 0) atomicAdd(&s_h0[d], (uint32_t)__popcll(m));
+                else atomicAdd(&bt.hist[p * kRadix + d], (uint32_t)__popcll(m));
+            }
         }
+    }
+    __syncthreads();
+    for (uint32_t j = 0; j < 4; ++j) {
+        const uint32_t c = s_h0[lane * 4 + j];
+        if (c) atomicAdd(&bt.hist[lane * 4 + j], c);
     }
     __syncthreads();
 }
@@ -215,7 +245,7 @@ __device__ void scatter_tile(const EngBatch& bt, uint32_t tile, uint32_t p, uint
     for (uint32_t i = 0; i < kPerLane; ++i) {
         const uint32_t idx = base_idx + i * 64;
         const bool valid = idx < bt.n;
-        const K key = valid ? kin[idx] : K(0);
+        const K key = valid ? ld_dev(kin + idx) : K(0);
         const uint32_t d = (uint32_t)(key >> shift) & mask;
         const uint64_t m = same_digit(d, nbits, valid);
         const uint32_t below = (uint32_t)__popcll(m & lt);
@@ -260,7 +290,7 @@ __device__ void scatter_tile(const EngBatch& bt, uint32_t tile, uint32_t p, uint
     // global start of each digit: exclusive scan of the pass histogram + earlier tiles
     uint32_t h[4], hs = 0, total;
     for (uint32_t j = 0; j < 4; ++j) {
-        h[j] = bt.hist[p * kRadix + lane * 4 + j];
+        h[j] = ld_dev(bt.hist + p * kRadix + lane * 4 + j);
         hs += h[j];
     }
     uint32_t base = wave_excl_scan(hs, total);
@@ -273,13 +303,13 @@ __device__ void scatter_tile(const EngBatch& bt, uint32_t tile, uint32_t p, uint
     for (uint32_t i = 0; i < kPerLane; ++i) {
         const uint32_t idx = base_idx + i * 64;
         if (idx < bt.n) {
-            const K key = kin[idx];
-            const uint32_t val = p == 0 ? idx : vin[idx];
+            const K key = ld_dev(kin + idx);
+            const uint32_t val = p == 0 ? idx : ld_dev(vin + idx);
             const uint32_t d = (uint32_t)(key >> shift) & mask;
             const uint32_t pos = s_gbase[d] + s_rank[i * 64 + lane];
             if (pos < bt.n) {   // always true unless a dependency failed (then 'err' is set)
-                kout[pos] = key;
-                vout[pos] = val;
+                st_dev(kout + pos, key);
+                st_dev(vout + pos, val);
             }
         }
     }
@@ -319,7 +349,7 @@ __device__ void trace_range(const EngScene& sc, const EngBatch& bt, const uint32
             if (next < end) {
                 const uint32_t k = next + (uint32_t)__popcll(idle & below);
                 if (!has && k < end) {
-                    rid = perm ? perm[k] : k;
+                    rid = perm ? ld_dev(perm + k) : k;
                     if (rid < bt.n) {
                         const float4 ra = bt.rays[2 * (size_t)rid], rb = bt.rays[2 * (size_t)rid + 1];
                         ox = ra.x; oy = ra.y; oz = ra.z; tmin = ra.w;
@@ -452,7 +482,7 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
             if (next < end) {
                 const uint32_t k = next + (uint32_t)__popcll(idle & below);
                 if (!has && k < end) {
-                    rid = perm ? perm[k] : k;
+                    rid = perm ? ld_dev(perm + k) : k;
                     if (rid < bt.n) {
                         const float4 ra = bt.rays[2 * (size_t)rid], rb = bt.rays[2 * (size_t)rid + 1];
                         ox = ra.x; oy = ra.y; oz = ra.z; tmin = ra.w;
@@ -623,7 +653,7 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
         }
         const uint32_t tile = r - bt.tile0;
         if (phase == 0) {
-            encode_tile<K>(sc, bt, tile, mode, key_bits, passes, s_cut);
+            encode_tile<K>(sc, bt, tile, mode, key_bits, passes, s_cut, s_whist);
             signal(bt.done);
         } else {
             const uint32_t p = phase - 1;

@@ -141,3 +141,34 @@ def test_engine_invalid_arguments(H, scenes):
         H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 1))
     with pytest.raises(H.HCCError):
         H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 8))
+
+
+@pytest.mark.parametrize("mode,key_bits,cut", [("hcc", 8, "cut32"), ("hcc", 16, "cut32"), ("twopoint", 32, None)])
+def test_engine_large_batches_across_phases(H, scenes, mode, key_bits, cut):
+    """Batches of hundreds of tiles, so that a batch's encode tiles, each sort pass's tiles and
+    its trace chunks run on many wavefronts of every XCD and every phase reads what other
+    wavefronts wrote in the launch: results equal the plain path's on every ray (outputs are
+    filled with a pattern no result has before each run), on two runs in a row."""
+    key_mode = {"hcc": H.KEY_HCC, "twopoint": H.KEY_TWOPOINT}[mode]
+    rng = np.random.default_rng(key_bits)
+    items = []
+    for n in (400_000, 250_000, 1_000, 131_072, 300_001, 64):
+        s = scenes[int(rng.integers(0, len(scenes)))]
+        closest = bool(rng.random() < 0.7)
+        pool = s["diffuse"] if closest else s["shadow"]
+        rays = np.ascontiguousarray(np.resize(pool[int(rng.integers(0, 100)):], (n, 8)), np.float32)
+        items.append((s, H.Batch(s["bvh"], torch.from_numpy(rays).cuda(), closest,
+                                 cut=s[cut] if cut else None)))
+    refs = []
+    for s, b in items:
+        perm = H.sort(H.encode(s["bvh"], b.cut, key_mode, key_bits, b.rays), key_bits)
+        refs.append(H.trace(s["bvh"], b.rays, perm, closest=b.closest).cpu().numpy())
+    ws = None
+    for rep in range(2):
+        for _, b in items:
+            b.out.fill_(float("nan") if b.out.dtype == torch.float32 else 7)
+        ws = H.batch_run([b for _, b in items], key_mode, key_bits, opts=H.BatchOpts(256, 32, 0, H.TRACE_WIDE),
+                         ws=ws)
+        assert H.batch_check(ws)
+        for (_, b), ref in zip(items, refs):
+            assert np.array_equal(b.out.cpu().numpy().view(np.uint8), ref.view(np.uint8)), f"run {rep}"
