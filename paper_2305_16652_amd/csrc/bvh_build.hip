@@ -191,6 +191,12 @@ __device__ __forceinline__ double load_agent(const double* p) {
     return __longlong_as_double(
         (long long)__hip_atomic_load((const uint64_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
+__device__ __forceinline__ void store_agent(float* p, float v) {
+    __hip_atomic_store((uint32_t*)p, __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(double* p, double v) {
+    __hip_atomic_store((uint64_t*)p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Bottom-up pass.  kBoxes: union boxes and fill nodes; always: HAD with 'lambda'.
 template <bool kBoxes>
@@ -201,10 +207,16 @@ __global__ __launch_bounds__(256) void k_refit(uint32_t n, const uint32_t* __res
     if (j >= n) return;
     const uint32_t n_int = n - 1;
     uint32_t node = parent[n_int + j];
+    // Boxes and HAD values that other threads read are stored and loaded with device-scope
+    // atomic accesses (coherent across the XCDs' L2 caches); a thread counts its arrival at the
+    // parent only once its stores have completed.  Device-scope fences instead would write back
+    // and invalidate the L2 at every step.
     while (node != kNone) {
-        __threadfence();                                  // publish this child's results
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);                    // this child's results are stored
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (atomicAdd(&flags[node], 1u) == 0) return;     // sibling not done: it continues
-        __threadfence();                                  // see the sibling's results
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);          // the sibling's results are read after
         const uint32_t c0 = child[2 * node], c1 = child[2 * node + 1];
         const float* b0 = boxes + 6 * (size_t)c0;
         const float* b1 = boxes + 6 * (size_t)c1;
@@ -222,7 +234,7 @@ __global__ __launch_bounds__(256) void k_refit(uint32_t n, const uint32_t* __res
                 b[3 + a] = fmaxf(x0[3 + a], x1[3 + a]);
             }
 #pragma unroll
-            for (int a = 0; a < 6; ++a) boxes[6 * (size_t)node + a] = b[a];
+            for (int a = 0; a < 6; ++a) store_agent(boxes + 6 * (size_t)node + a, b[a]);
             Node nd;
             nd.a = make_float4(x0[0], x0[1], x0[2], x0[3]);
             nd.b = make_float4(x0[4], x0[5], x1[0], x1[1]);
@@ -235,7 +247,7 @@ __global__ __launch_bounds__(256) void k_refit(uint32_t n, const uint32_t* __res
         }
         const double h0 = load_agent(had + c0);
         const double h1 = load_agent(had + c1);
-        had[node] = (h0 + h1) + lambda * box_sa(b[0], b[1], b[2], b[3], b[4], b[5]);
+        store_agent(had + node, (h0 + h1) + lambda * box_sa(b[0], b[1], b[2], b[3], b[4], b[5]));
         node = parent[node];
     }
 }
