@@ -89,6 +89,9 @@ def parse():
     ap.add_argument("--drift-reps", type=int, default=5)
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-direct-min", type=int, default=0,
+                    help="continuous server: requests of at least this many rays take the full-device kernels "
+                         "(0 = the library default; 4294967295 = every request through the engine)")
     return ap.parse_args()
 
 
@@ -420,7 +423,7 @@ def run_serving(H, args):
         for name, server in (("plain", plain), ("continuous", None)):
             if server is None:
                 server = H.Server(key_mode=H.KEY_HCC, key_bits=32, max_group=16, streams=4,
-                                  batch=H.BatchOpts(0, 0, 0, H.TRACE_WIDE, 0))
+                                  batch=H.BatchOpts(0, 0, 0, H.TRACE_WIDE, 0), direct_min=args.serve_direct_min)
             lat, wall = serve(server, rate)
             row[name] = dict(p50_ms=round(float(np.percentile(lat, 50)) / 1e3, 3),
                              p99_ms=round(float(np.percentile(lat, 99)) / 1e3, 3),
