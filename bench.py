@@ -288,9 +288,7 @@ def main():
     if not args.no_grid and "hcc" in conf:
         grid = run_method_grid(H, bvh, rays, conf["hcc"]["opts"], args.grid_reps)
     del bufs
-    hcc_ck = ((conf["hcc"]["cut"], conf["hcc"]["key_bits"], conf["hcc"]["skip"]) if "hcc" in conf else (32, 32, 0),
-              conf["twopoint"]["skip"] if "twopoint" in conf else 0)
-    bounces = None if args.no_bounces else run_bounces(H, args, bvh, tris_h, sec, rays, hcc_ck)
+    bounces = None if args.no_bounces else run_bounces(H, args, bvh, tris_h, sec, rays)
     drift = None if args.no_drift else run_drift(H, args)
     batched = None if args.no_batched else run_batched(H, args)
     serve = None if args.no_serve else run_serving(H, args)
@@ -658,11 +656,11 @@ def run_method_grid(H, bvh, rays, opts, reps):
     return rows
 
 
-def run_bounces(H, args, bvh, tris_h, sec, rays, hcc_ck):
+def run_bounces(H, args, bvh, tris_h, sec, rays):
     """Bounces 2 and 3 of the frame workload: diffuse rays spawned at the previous bounce's
     closest hits (origins now scattered over the scene, directions random), each bounce's
-    NoSort, TwoPoint (K = 32) and HCC (the cut size, key length and skipped bits picked for
-    bounce 1) with trace options tuned on its NoSort order."""
+    NoSort, TwoPoint and HCC with trace options tuned on its NoSort order and each reordering's
+    key length, skipped bits (and HCC cut size) tuned on the bounce's own rays."""
     import torch
     import workloads as W
     from paper_2305_16652_amd import autotune as AT
@@ -675,9 +673,13 @@ def run_bounces(H, args, bvh, tris_h, sec, rays, hcc_ck):
                                  bounce=bounce - 1)
         rd = torch.from_numpy(nxt).to(rays.device)
         opts = AT.tune_trace(bvh, rd, None, candidates=AT.WIDE)[0]
+        tw, _ = AT.tune_reorder(bvh, rd, "twopoint", key_bits=(4, 8, 16, 32), skips=(0, 2, 4, 8, 16),
+                                paper_exact=False, candidates=[opts])
+        hc, _ = AT.tune_reorder(bvh, rd, "hcc", cuts=(256, 1024), key_bits=(4, 8, 16, 32), skips=(0, 2, 4, 8, 16),
+                                paper_exact=False, candidates=[opts])
         rows = [measure_variant(H, bvh, rd, v, opts, args.grid_reps)
-                for v in (dict(mode="nosort"), dict(mode="twopoint", K=32, skip=hcc_ck[1]),
-                          dict(mode="hcc", C=hcc_ck[0][0], K=hcc_ck[0][1], skip=hcc_ck[0][2]))]
+                for v in (dict(mode="nosort"), dict(mode="twopoint", K=tw.key_bits, skip=tw.skip),
+                          dict(mode="hcc", C=hc.cut, K=hc.key_bits, skip=hc.skip))]
         out[str(bounce)] = dict(rays=int(rd.shape[0]), trace_opts=AT.opts_dict(opts), rows=rows)
         log(f"frame bounce {bounce} ({rd.shape[0]} rays, {time.time() - t0:.1f}s): " +
             "; ".join(f"{r['method']} {r['mrays_s']:.0f} Mrays/s (trace {r['trace_ms']:.2f} ms, "
