@@ -596,9 +596,9 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
         const bool can_step = has && node != kNone && pmask == 0;
         const uint64_t waiting = __ballot(has && pmask != 0);
         const uint64_t stepping = __ballot(can_step);
-        // a leaf batch once half of the busy lanes wait on one (measured with chunks taken from the
-        // queue: 0.4-0.7% faster than a third, a quarter 1-2% slower)
-        if (waiting != 0 && (2 * __popcll(waiting) >= __popcll(busy) || stepping == 0)) {
+        // a leaf batch once a third of the busy lanes wait on one (measured: a half or two thirds
+        // leave too many lanes idle in the node steps; a quarter is no better, fewer is worse)
+        if (waiting != 0 && (3 * __popcll(waiting) >= __popcll(busy) || stepping == 0)) {
             const bool mine = has && pmask != 0;
             uint4 r = make_uint4(kNone, kNone, kNone, kNone);
             if (mine) r = s_leaf[__lane_id()];
