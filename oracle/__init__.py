@@ -352,3 +352,39 @@ def grid_boxes(scene_lohi, gx: int, gy: int, gz: int) -> np.ndarray:
     out = np.empty((gx * gy * gz, 6), np.float32)
     _load_extra().oracle_grid_boxes(_ptr(lohi), gx, gy, gz, _ptr(out))
     return out
+
+
+def wave_fetches(bvh: OracleBVH, rays, perm=None, width: int = 64, closest: bool = True, order: int = 1,
+                 waves=None, threads: int = 1):
+    """Lockstep wave model (the per-warp coherence argument of Section 3.1; Table 6 in
+    Section 6.5): rays in trace order, waves of ``width`` consecutive rays; per wave the
+    distinct nodes and distinct triangles fetched at each lockstep step, summed over the
+    steps.  ``order`` 0 is the traversal of ``trace``; 1 the child-test traversal (see
+    ``oracle_wave_fetches`` in the C file).  ``waves`` lists the wave indices to model
+    (default: all).  Returns (nodes, tris, steps), one entry per listed wave."""
+    rays = _f32(rays, 8)
+    n = rays.shape[0] if perm is None else len(perm)
+    p = None if perm is None else np.ascontiguousarray(perm, np.uint32)
+    n_w = (n + width - 1) // width
+    w = np.arange(n_w, dtype=np.uint32) if waves is None else np.ascontiguousarray(waves, np.uint32)
+    nodes = np.zeros(w.shape[0], np.uint64)
+    trisf = np.zeros(w.shape[0], np.uint64)
+    steps = np.zeros(w.shape[0], np.uint32)
+    lib = _load()
+    if not getattr(lib, "_wave", False):
+        P, u32 = C.c_void_p, C.c_uint32
+        lib.oracle_wave_fetches.argtypes = [u32, P, P, P, P, P, P, u32, u32, C.c_int, C.c_int, P, u32, P, P, P]
+        lib.oracle_wave_fetches.restype = C.c_int
+        lib._wave = True
+
+    def run(rng):
+        k0, k1 = rng
+        rc = lib.oracle_wave_fetches(bvh.n, _ptr(bvh.child), _ptr(bvh.leaf_prim), _ptr(bvh.boxes), _ptr(bvh.tris),
+                                     _ptr(rays), _ptr(p), n, width, 1 if closest else 0, order, _ptr(w[k0:k1]),
+                                     k1 - k0, _ptr(nodes[k0:k1]), _ptr(trisf[k0:k1]), _ptr(steps[k0:k1]))
+        if rc != 0:
+            raise RuntimeError(f"oracle_wave_fetches failed ({rc})")
+
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        list(ex.map(run, _chunks(w.shape[0], max(1, threads) * 8 if threads > 1 else 1)))
+    return nodes, trisf, steps

@@ -747,3 +747,211 @@ double oracle_anc(const uint64_t* keys, const uint32_t* perm, uint32_t n, uint32
     free(buf);
     return total / groups;
 }
+
+/* ------------------------------------------------------------------ O8: lockstep wave model
+ * Order-dependent fetch count behind the paper's coherence argument (Section 3.1: rays
+ * of one warp that walk similar paths share their node fetches; Table 6 in Section 6.5
+ * measures the same property as codes per warp).  Rays are taken in trace order
+ * (perm[k], or k when perm is NULL) and grouped into waves of `width` consecutive rays.
+ * Every ray's traversal is a sequence of steps.  In lockstep execution step s of a wave
+ * runs for every lane whose traversal has more than s steps, and each distinct node and
+ * each distinct triangle those lanes touch at step s is fetched once for the wave.  The
+ * wave's node (triangle) fetches are these distinct counts summed over its steps.
+ *
+ * Two traversal orders are modelled:
+ *   order 0 -- the traversal of O7 above: one step per popped node whose box passes the
+ *              segment [tmin, best t]; an internal node is a node fetch, a leaf is a
+ *              triangle fetch.
+ *   order 1 -- child-test traversal: a step fetches the current internal node and tests
+ *              both children's boxes against [tmin, best t] (tmax for any hit); the
+ *              triangle of every hit leaf child is tested in the same step (triangle
+ *              fetches); the step then continues with the hit internal child of smaller
+ *              entry distance (child 0 on a tie) and pushes the other hit internal
+ *              child, or, with no hit internal child, pops the stack, the popped node
+ *              being fetched at the next step without a new box test.  The traversal
+ *              ends when nothing is left to pop, and for any hit after the step that
+ *              found one.  A BVH of one triangle has no node fetch and one triangle
+ *              fetch at step 0.
+ * Node ids are unified ids (internal node i -> i, leaf j -> n-1+j); a triangle fetch is
+ * identified by its leaf.
+ * Metrics, not parity: pinned by hand-counted cases and an independent re-implementation
+ * in the tests. */
+
+typedef struct {
+    uint32_t* node;      /* per step: node id fetched, or MISS_PRIM for none */
+    uint32_t* leaf_a;    /* per step: first triangle (leaf id) fetched, or MISS_PRIM */
+    uint32_t* leaf_b;    /* per step: second triangle (order 1: the other child), or MISS_PRIM */
+    uint32_t len, cap;
+} step_list;
+
+static int steps_push(step_list* L, uint32_t node, uint32_t la, uint32_t lb) {
+    if (L->len == L->cap) {
+        uint32_t cap = L->cap ? 2 * L->cap : 64;
+        uint32_t* a = (uint32_t*)realloc(L->node, sizeof(uint32_t) * cap);
+        if (!a) return -1;
+        L->node = a;
+        a = (uint32_t*)realloc(L->leaf_a, sizeof(uint32_t) * cap);
+        if (!a) return -1;
+        L->leaf_a = a;
+        a = (uint32_t*)realloc(L->leaf_b, sizeof(uint32_t) * cap);
+        if (!a) return -1;
+        L->leaf_b = a;
+        L->cap = cap;
+    }
+    L->node[L->len] = node;
+    L->leaf_a[L->len] = la;
+    L->leaf_b[L->len] = lb;
+    ++L->len;
+    return 0;
+}
+
+/* Closest-hit bookkeeping shared by both orders: test the triangle of leaf `leaf`, keep the
+ * smallest (t, prim) pair; returns 1 on a hit in the segment. */
+static int model_leaf(const bvh_view* b, uint32_t leaf, const float o[3], const float d[3], float tmin,
+                      float tmax, int* found, float* best_t, uint32_t* best_prim) {
+    uint32_t prim = b->leaf_prim[leaf];
+    float t, u, v;
+    if (!tri_hit(b->tris + 9 * (size_t)prim, o, d, tmin, tmax, &t, &u, &v)) return 0;
+    if (!*found || t < *best_t || (t == *best_t && prim < *best_prim)) {
+        *best_t = t;
+        *best_prim = prim;
+        *found = 1;
+    }
+    return 1;
+}
+
+/* The steps of one ray's traversal in the given order (see above). */
+static int ray_steps(const bvh_view* b, const float* ray, int closest, int order, step_list* L) {
+    float o[3] = {ray[0], ray[1], ray[2]};
+    float d[3] = {ray[4], ray[5], ray[6]};
+    float inv[3] = {1.0f / d[0], 1.0f / d[1], 1.0f / d[2]};
+    float tmin = ray[3], tmax = ray[7];
+    float best_t = tmax;
+    uint32_t best_prim = MISS_PRIM;
+    int found = 0;
+    uint32_t stack[128];
+    int sp = 0;
+    const uint32_t n_int = b->n - 1;
+    L->len = 0;
+    if (b->n == 1) {   /* the root is the only leaf */
+        return steps_push(L, MISS_PRIM, 0, MISS_PRIM);
+    }
+    if (order == 0) {
+        stack[sp++] = 0;
+        while (sp > 0) {
+            uint32_t id = stack[--sp];
+            if (!slab_hit(o, inv, tmin, best_t, b->boxes + 6 * (size_t)id, 0)) continue;
+            if (id >= n_int) {
+                if (steps_push(L, MISS_PRIM, id, MISS_PRIM)) return -1;
+                int hit = model_leaf(b, id - n_int, o, d, tmin, tmax, &found, &best_t, &best_prim);
+                if (hit && !closest) break;
+                continue;
+            }
+            if (steps_push(L, id, MISS_PRIM, MISS_PRIM)) return -1;
+            uint32_t c0 = b->child[2 * (size_t)id], c1 = b->child[2 * (size_t)id + 1];
+            float n0, n1;
+            int h0 = slab_hit(o, inv, tmin, best_t, b->boxes + 6 * (size_t)c0, &n0);
+            int h1 = slab_hit(o, inv, tmin, best_t, b->boxes + 6 * (size_t)c1, &n1);
+            if (h0 && h1) {
+                if (n1 < n0) { stack[sp++] = c0; stack[sp++] = c1; }
+                else { stack[sp++] = c1; stack[sp++] = c0; }
+            } else if (h0) {
+                stack[sp++] = c0;
+            } else if (h1) {
+                stack[sp++] = c1;
+            }
+            if (sp > 126) return -2;
+        }
+        return 0;
+    }
+    /* order 1 */
+    uint32_t node = 0;
+    while (1) {
+        uint32_t c0 = b->child[2 * (size_t)node], c1 = b->child[2 * (size_t)node + 1];
+        float lim = closest ? best_t : tmax;
+        float n0, n1;
+        int h0 = slab_hit(o, inv, tmin, lim, b->boxes + 6 * (size_t)c0, &n0);
+        int h1 = slab_hit(o, inv, tmin, lim, b->boxes + 6 * (size_t)c1, &n1);
+        int leaf0 = h0 && c0 >= n_int, leaf1 = h1 && c1 >= n_int;
+        if (steps_push(L, node, leaf0 ? c0 : MISS_PRIM, leaf1 ? c1 : MISS_PRIM)) return -1;
+        int any = 0;
+        if (leaf0) any |= model_leaf(b, c0 - n_int, o, d, tmin, tmax, &found, &best_t, &best_prim);
+        if (leaf1) any |= model_leaf(b, c1 - n_int, o, d, tmin, tmax, &found, &best_t, &best_prim);
+        if (!closest && any) break;
+        int in0 = h0 && !leaf0, in1 = h1 && !leaf1;
+        if (in0 && in1) {
+            if (n1 < n0) { stack[sp++] = c0; node = c1; }
+            else { stack[sp++] = c1; node = c0; }
+            if (sp > 126) return -2;
+        } else if (in0) {
+            node = c0;
+        } else if (in1) {
+            node = c1;
+        } else {
+            if (sp == 0) break;
+            node = stack[--sp];
+        }
+    }
+    return 0;
+}
+
+/* Distinct values among v[0..m) that are not MISS_PRIM (m is at most a few hundred). */
+static uint32_t count_distinct(uint32_t* v, uint32_t m) {
+    uint32_t distinct = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        if (v[i] == MISS_PRIM) continue;
+        int seen = 0;
+        for (uint32_t j = 0; j < i; ++j)
+            if (v[j] == v[i]) { seen = 1; break; }
+        if (!seen) ++distinct;
+    }
+    return distinct;
+}
+
+/* Wave fetches of the listed waves: wave w holds trace positions [w*width, (w+1)*width)
+ * clipped to n.  out_nodes[i] / out_tris[i] receive the fetches of waves[i]; out_steps[i]
+ * (nullable) the number of lockstep steps (the longest traversal of the wave).
+ * Returns 0, or a negative value on a bad argument or exhausted memory. */
+int oracle_wave_fetches(uint32_t n_tris, const uint32_t* child, const uint32_t* leaf_prim, const float* boxes,
+                        const float* tris, const float* rays, const uint32_t* perm, uint32_t n, uint32_t width,
+                        int closest, int order, const uint32_t* waves, uint32_t n_waves, uint64_t* out_nodes,
+                        uint64_t* out_tris, uint32_t* out_steps) {
+    if (width == 0 || width > 1024 || n_tris == 0 || (order != 0 && order != 1)) return -3;
+    bvh_view b = {n_tris, child, leaf_prim, boxes, tris};
+    step_list* lanes = (step_list*)calloc(width, sizeof(step_list));
+    uint32_t* ids = (uint32_t*)malloc(sizeof(uint32_t) * 2 * width);
+    int rc = 0;
+    if (!lanes || !ids) { rc = -1; goto done; }
+    for (uint32_t i = 0; i < n_waves; ++i) {
+        uint64_t k0 = (uint64_t)waves[i] * width;
+        uint32_t m = k0 >= n ? 0 : (uint32_t)((n - k0 < width) ? n - k0 : width);
+        uint32_t longest = 0;
+        for (uint32_t l = 0; l < m; ++l) {
+            uint32_t r = perm ? perm[k0 + l] : (uint32_t)(k0 + l);
+            rc = ray_steps(&b, rays + 8 * (size_t)r, closest, order, &lanes[l]);
+            if (rc) goto done;
+            if (lanes[l].len > longest) longest = lanes[l].len;
+        }
+        uint64_t nodes = 0, trisf = 0;
+        for (uint32_t s = 0; s < longest; ++s) {
+            uint32_t c = 0;
+            for (uint32_t l = 0; l < m; ++l)
+                if (s < lanes[l].len) ids[c++] = lanes[l].node[s];
+            nodes += count_distinct(ids, c);
+            c = 0;
+            for (uint32_t l = 0; l < m; ++l)
+                if (s < lanes[l].len) { ids[c++] = lanes[l].leaf_a[s]; ids[c++] = lanes[l].leaf_b[s]; }
+            trisf += count_distinct(ids, c);
+        }
+        out_nodes[i] = nodes;
+        out_tris[i] = trisf;
+        if (out_steps) out_steps[i] = longest;
+    }
+done:
+    if (lanes) {
+        for (uint32_t l = 0; l < width; ++l) { free(lanes[l].node); free(lanes[l].leaf_a); free(lanes[l].leaf_b); }
+        free(lanes);
+    }
+    free(ids);
+    return rc;
+}
