@@ -44,7 +44,7 @@ def log(msg: str):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -54,28 +54,34 @@ def parse():
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--tune", type=int, default=1, help="autotune each method (0: use the flags below)")
     ap.add_argument("--cut", type=int, default=32)
-    ap.add_argument("--hcc-cuts", default="16,32,64,256,512,1024,2048,4096",
-                    help="cut sizes the HCC tuning tries (with each tuned key length K, C >= K)")
-    ap.add_argument("--paper-exact", action="store_true", help="HCC tuning only over C = K (the paper's pairs)")
-    ap.add_argument("--skips", default="0,2,4,6,8,12,14,16",
-                    help="low key bits the tuned sort may leave out (the paper's shortened sort; 0 = full key)")
+    ap.add_argument("--hcc-cuts", default="16,32,64", help="cut sizes the HCC tuning tries")
+    ap.add_argument("--truncate", action="store_true",
+                    help="HCC tuning also over C > K (the key holds the K cut nodes of highest HAD); "
+                         "by default C = K, the paper's hierarchy cut code")
+    ap.add_argument("--skips", default="0,2,4,8,16,32",
+                    help="low key bits the tuned sort may leave out (the paper's shortened sort)")
+    ap.add_argument("--min-sorted-frac", type=float, default=0.5,
+                    help="tuned sorts keep at least this fraction of the key's bits")
     ap.add_argument("--skip", type=int, default=0, help="skipped low key bits without tuning")
-    ap.add_argument("--tune-key-bits", default="2,4,8,16,32,64", help="key lengths the reordering tuning tries")
+    ap.add_argument("--tune-key-bits", default="16,32,64", help="key lengths the reordering tuning tries")
     ap.add_argument("--key-bits", type=int, default=32)
     ap.add_argument("--block", type=int, default=64)
-    ap.add_argument("--stack", type=int, default=0, help="0 scratch, 1 LDS, 2 LDS+scratch")
+    ap.add_argument("--stack", type=int, default=2, help="0 scratch, 1 LDS, 2 LDS+scratch")
     ap.add_argument("--persistent", type=int, default=1)
     ap.add_argument("--refill", type=int, default=32)
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--waves", type=int, default=8192)
-    ap.add_argument("--flags", type=int, default=1)
+    ap.add_argument("--flags", type=int, default=2)
     ap.add_argument("--remap", type=int, default=0, help="1 = XCD-contiguous block order")
-    ap.add_argument("--methods", default="nosort,twopoint,hcc")
-    ap.add_argument("--no-stats", action="store_true", help="skip the fetch-counting trace (roofline bytes)")
+    ap.add_argument("--methods", default="nosort,twopoint,hcc,hcc_paper_exact")
+    ap.add_argument("--no-stats", action="store_true", help="skip the fetch-counting trace (kernel-counted bytes)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (HBM counter calibration)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle leg (CPU baseline and the wave model behind the roofline)")
     ap.add_argument("--cpu-stride", type=int, default=8, help="oracle sample: every k-th secondary ray")
+    ap.add_argument("--model-wave-stride", type=int, default=8,
+                    help="the oracle's wave model runs on every k-th wavefront of each trace order")
     ap.add_argument("--no-shadow", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch engine workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server workload")
@@ -92,11 +98,24 @@ def parse():
     ap.add_argument("--serve-direct-min", type=int, default=0,
                     help="continuous server: requests of at least this many rays take the full-device kernels "
                          "(0 = the library default; 4294967295 = every request through the engine)")
-    return ap.parse_args()
+    ap.add_argument("--full-out", default="bench_full.json",
+                    help="file that receives the full record (every table); the last stdout line is a summary")
+    return ap.parse_args(argv)
 
 
-def main():
-    args = parse()
+def cut_composition(H, cut, n_tris: int, sorted_bits: int) -> dict:
+    """What the sorted key bits encode: of the cut nodes owning them, how many are leaves
+    (single triangles) and how many distinct boxes they have."""
+    ids, _, boxes = cut.export()
+    m = min(sorted_bits, ids.shape[0])
+    ids, boxes = ids[:m], boxes[:m]
+    leaves = int((ids >= max(n_tris - 1, 0)).sum()) if n_tris > 1 else m
+    distinct = len({b.tobytes() for b in boxes})
+    return dict(sorted_nodes=int(m), leaves=leaves, distinct_boxes=distinct)
+
+
+def main(argv=None):
+    args = parse(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(rays would be sharded by contiguous ranges with a BVH replica per GPU); run with --gpus 1",
@@ -155,31 +174,37 @@ def main():
     del prim, ph
 
     # ------------------------------------------------------------------ configuration per method
+    # nosort: trace options only.  twopoint / hcc: key length, skipped low bits (keeping at least
+    # --min-sorted-frac of the key in the sort) and trace options; hcc over C = K (a real cut whose
+    # every node owns a key bit).  hcc_paper_exact: C = K = 32, full 32-bit sort (the paper's
+    # configuration), trace options tuned.
     t0 = time.time()
     conf = {}
-    if "nosort" in methods:
-        o = AT.tune_trace(bvh, rays, None)[0] if args.tune else flag_opts
-        conf["nosort"] = dict(cut=0, key_bits=0, skip=0, opts=o)
-    for m in ("twopoint", "hcc"):
-        if m not in methods:
-            continue
-        if args.tune:
-            sk = tuple(int(x) for x in args.skips.split(","))
-            kb = tuple(int(x) for x in args.tune_key_bits.split(","))
-            if m == "hcc":
-                cs = tuple(int(c) for c in args.hcc_cuts.split(","))
-                ch, _ = AT.tune_reorder(bvh, rays, m, cuts=cs, key_bits=kb, paper_exact=args.paper_exact, skips=sk)
+    sk = tuple(int(x) for x in args.skips.split(","))
+    kb = tuple(int(x) for x in args.tune_key_bits.split(","))
+    for m in methods:
+        if m == "nosort":
+            o = AT.tune_trace(bvh, rays, None)[0] if args.tune else flag_opts
+            conf[m] = dict(cut=0, key_bits=0, skip=0, opts=o)
+        elif m == "hcc_paper_exact":
+            ch, _ = AT.tune_reorder(bvh, rays, "hcc", cuts=(32,), key_bits=(32,), skips=(0,)) if args.tune else \
+                (None, None)
+            conf[m] = dict(cut=32, key_bits=32, skip=0, opts=ch.opts if ch else flag_opts)
+        elif m in ("twopoint", "hcc"):
+            if args.tune:
+                cs = tuple(int(c) for c in args.hcc_cuts.split(",")) if m == "hcc" else (0,)
+                ch, _ = AT.tune_reorder(bvh, rays, m, cuts=cs, key_bits=kb, paper_exact=not args.truncate,
+                                        skips=sk, min_sorted_frac=args.min_sorted_frac)
+                conf[m] = dict(cut=ch.cut, key_bits=ch.key_bits, skip=ch.skip, opts=ch.opts)
             else:
-                ch, _ = AT.tune_reorder(bvh, rays, m, key_bits=kb, skips=sk)
-            conf[m] = dict(cut=ch.cut, key_bits=ch.key_bits, skip=ch.skip, opts=ch.opts)
-        else:
-            conf[m] = dict(cut=args.cut if m == "hcc" else 0, key_bits=args.key_bits, skip=args.skip, opts=flag_opts)
+                conf[m] = dict(cut=args.cut if m == "hcc" else 0, key_bits=args.key_bits, skip=args.skip,
+                               opts=flag_opts)
     if args.tune:
         log(f"autotuned in {time.time() - t0:.1f}s: " +
             "; ".join(f"{m} C={c['cut']} K={c['key_bits']} skip={c.get('skip', 0)} {AT.opts_dict(c['opts'])}"
                       for m, c in conf.items()))
     e0.record()
-    cuts = {m: H.select_cut(bvh, c["cut"]) for m, c in conf.items() if m == "hcc"}
+    cuts = {m: H.select_cut(bvh, c["cut"]) for m, c in conf.items() if m.startswith("hcc")}
     e1.record()
     torch.cuda.synchronize()
     cut_ms = e0.elapsed_time(e1)
@@ -204,8 +229,8 @@ def main():
         perm = None
         if method != "nosort":
             k = c["key_bits"]
-            if method == "hcc":
-                H.encode(bvh, cuts["hcc"], H.KEY_HCC, k, rr, out=b["keys"])
+            if method.startswith("hcc"):
+                H.encode(bvh, cuts[method], H.KEY_HCC, k, rr, out=b["keys"])
             else:
                 H.encode(bvh, None, H.KEY_TWOPOINT, k, rr, out=b["keys"])
             if evs:
@@ -245,8 +270,11 @@ def main():
             f"sort {res['sort_ms']:.3f} trace {res['trace_ms']:.3f} ms")
         return res
 
-    results = {m: timed(m) for m in ("nosort", "twopoint", "hcc") if m in conf}
+    results = {m: timed(m) for m in conf}
     hcc_hits = hits.clone()
+    head = "hcc" if "hcc" in results else next(iter(results))
+    composition = (cut_composition(H, cuts[head], tris_h.shape[0], conf[head]["key_bits"] - conf[head]["skip"])
+                   if head in cuts else None)
 
     # any-hit (shadow) rays, each method in its secondary-ray configuration
     shadow_res = None
@@ -275,14 +303,17 @@ def main():
             del sb
         log("shadow Mrays/s: " + ", ".join(f"{m} {shadow_res[m]['mrays_s']:.0f}" for m in conf))
 
-    roofline = None
-    if not args.no_stats and "hcc" in results:
-        roofline = roofline_of(H, bvh, rays, bufs["hcc"]["perm"], R, results["hcc"]["trace_ms_mean"],
-                               conf["hcc"]["opts"])
-    cpu = None
+    counted = None
+    if not args.no_stats:
+        counted = {m: kernel_counted_fetches(H, bvh, rays, bufs[m]["perm"] if m in bufs else None, conf[m]["opts"])
+                   for m in conf}
+    oracle_leg = None
     if not args.no_cpu and "hcc" in conf:
-        cpu = cpu_baseline(tris_h, sec, args, hcc_hits.cpu().numpy(), conf["hcc"]["cut"], conf["hcc"]["key_bits"],
-                           conf["hcc"]["skip"])
+        oracle_leg = run_oracle_leg(tris_h, sec, args, hcc_hits.cpu().numpy(), conf, head)
+    roofline = roofline_of(H, R, results[head]["trace_ms_mean"], conf[head]["opts"],
+                           oracle_leg["model"].get(head) if oracle_leg else None,
+                           counted.get(head) if counted else None)
+    cpu = oracle_leg["cpu_baseline"] if oracle_leg else None
 
     grid = None
     if not args.no_grid and "hcc" in conf:
@@ -293,41 +324,21 @@ def main():
     batched = None if args.no_batched else run_batched(H, args)
     serve = None if args.no_serve else run_serving(H, args)
 
-    head = "hcc" if "hcc" in results else next(iter(results))
-    hcc = results[head]
-    nos, tpt = results.get("nosort"), results.get("twopoint")
     hc = conf[head]
-    line = {
-        "metric": METRIC,
-        "value": round(hcc["mrays_s"], 2),
-        "unit": "Mrays/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(hcc["ms_per_step"], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": (f"frame: {tris_h.shape[0]:,}-triangle room with 100 icospheres + 100 tori, "
-                         f"{args.width}x{args.height}x{args.spp} spp, bounce-1 diffuse secondary rays; "
-                         f"{head} cut {hc['cut']} nodes, {hc['key_bits']}-bit keys"
-                         + (f", sorted on the top {hc['key_bits'] - hc['skip']} bits" if hc.get("skip") else "")),
-            "triangles": int(tris_h.shape[0]), "rays": int(R), "cut": hc["cut"], "key_bits": hc["key_bits"],
-            "skip_bits": hc.get("skip", 0),
-            "trace_opts": AT.opts_dict(hc["opts"]),
-        },
+    workload = (f"frame: {tris_h.shape[0]:,}-triangle room with 100 icospheres + 100 tori, "
+                f"{args.width}x{args.height}x{args.spp} spp, bounce-1 diffuse secondary rays")
+    full = {
+        "metric": METRIC, "workload": workload, "steps": args.steps, "warmup": args.warmup,
+        "triangles": int(tris_h.shape[0]), "rays": int(R), "headline": head,
         "methods": {m: dict({k: round(v, 4) for k, v in r.items()}, cut=conf[m]["cut"],
                             key_bits=conf[m]["key_bits"], skip_bits=conf[m].get("skip", 0),
                             trace_opts=AT.opts_dict(conf[m]["opts"]))
                     for m, r in results.items()},
-        "speedup_vs_nosort": round(hcc["mrays_s"] / nos["mrays_s"], 3) if nos else None,
-        "speedup_vs_twopoint": round(hcc["mrays_s"] / tpt["mrays_s"], 3) if tpt else None,
+        "cut_composition": composition,
         "shadow": shadow_res,
         "build_ms": round(build_ms, 2),
         "select_cut_ms": round(cut_ms, 2),
+        "fetches": dict(model=oracle_leg["model"] if oracle_leg else None, kernel_counted=counted),
         "method_grid": grid,
         "frame_bounces": bounces,
         "drift": drift,
@@ -336,7 +347,80 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
+    if args.full_out:
+        with open(args.full_out, "w") as f:
+            json.dump(full, f, indent=1)
+    line = compact_line(full, args, workload)
+    print(json.dumps(line, separators=(",", ":")), flush=True)
+
+
+def compact_line(full: dict, args, workload: str) -> dict:
+    """The one JSON line the benchmark prints last: the headline, every method's rate and stage
+    times, speedups, roofline, CPU baseline and one-number summaries of the other workloads.
+    The tables behind them are in the full record (args.full_out)."""
+    head = full["headline"]
+    res = full["methods"]
+    hc = res[head]
+
+    def mrow(m):
+        r = res[m]
+        out = dict(mrays_s=round(r["mrays_s"], 1), ms=round(r["ms_per_step"], 3), enc=round(r["encode_ms"], 3),
+                   sort=round(r["sort_ms"], 3), trace=round(r["trace_ms"], 3))
+        if m != "nosort":
+            out.update(C=r["cut"], K=r["key_bits"], skip=r["skip_bits"])
+        return out
+
+    def speed(a, b):
+        return round(res[a]["mrays_s"] / res[b]["mrays_s"], 3) if a in res and b in res else None
+
+    line = {
+        "metric": METRIC,
+        "value": round(hc["mrays_s"], 2),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(hc["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload + f"; {head} C={hc['cut']} K={hc['key_bits']}"
+                   + (f" sorted on the top {hc['key_bits'] - hc['skip_bits']} bits" if hc["skip_bits"] else ""),
+                   "triangles": full["triangles"], "rays": full["rays"], "cut": hc["cut"], "key_bits": hc["key_bits"],
+                   "skip_bits": hc["skip_bits"], "trace_opts": hc["trace_opts"]},
+        "methods": {m: mrow(m) for m in res},
+        "speedup_vs_nosort": speed(head, "nosort"),
+        "speedup_vs_twopoint": speed(head, "twopoint"),
+        "paper_exact_vs_nosort": speed("hcc_paper_exact", "nosort"),
+        "cut_composition": full.get("cut_composition"),
+    }
+    sh = full.get("shadow")
+    if sh:
+        line["shadow_mrays_s"] = {m: sh[m]["mrays_s"] for m in res if m in sh}
+    fm = (full.get("fetches") or {}).get("model")
+    if fm:
+        line["model_fetches_per_ray"] = {m: [v["node_fetches_per_ray"], v["tri_fetches_per_ray"]] for m, v in fm.items()}
+    b = full.get("frame_bounces")
+    if b:
+        line["bounces_mrays_s"] = {k: {r["method"]: r["mrays_s"] for r in v["rows"]} for k, v in b.items()}
+    bt = full.get("batched")
+    if bt:
+        line["batched_mrays_s"] = {k: bt[k] for k in ("engine_hcc_mrays_s", "plain_hcc_mrays_s",
+                                                     "engine_nosort_mrays_s", "plain_nosort_mrays_s") if k in bt}
+    sv = full.get("serve")
+    if sv:
+        line["serve_p50_p99_ms"] = {rho: {k: [v["p50_ms"], v["p99_ms"]] for k, v in row.items()}
+                                    for rho, row in sv["loads"].items()}
+    d = full.get("drift")
+    if d:
+        line["drift_best_mrays_s"] = {bn: list(max((r["mrays_s"], r["method"]) for r in v["rows"]))
+                                      for bn, v in d["bounces"].items()}
+    line["roofline"] = full.get("roofline")
+    line["cpu_baseline"] = full.get("cpu_baseline")
+    line["full_record"] = args.full_out
+    return line
 
 
 _SCENES = None
@@ -658,14 +742,18 @@ def run_method_grid(H, bvh, rays, opts, reps):
 
 def run_bounces(H, args, bvh, tris_h, sec, rays):
     """Bounces 2 and 3 of the frame workload: diffuse rays spawned at the previous bounce's
-    closest hits (origins now scattered over the scene, directions random), each bounce's
-    NoSort, TwoPoint and HCC with trace options tuned on its NoSort order and each reordering's
-    key length, skipped bits (and HCC cut size) tuned on the bounce's own rays."""
+    closest hits (origins now scattered over the scene, directions random).  Per bounce: trace
+    options tuned on its NoSort order; NoSort; TwoPoint and HCC (C = K) with key length and
+    skipped bits tuned on the bounce's own rays (at least half of the key sorted); and the
+    untuned rows HCC C = K = 32 and 64, MLHCC16 (8+8) and MLHCC32 (16+16), TwoPoint K = 32,
+    each with a full sort.  Node / triangle fetches per ray are the one-ray-per-lane kernel's
+    wavefront counts (equal to the oracle's wave model, see the tests)."""
     import torch
     import workloads as W
     from paper_2305_16652_amd import autotune as AT
     out = {}
     prev, prev_d = sec, rays
+    sk = tuple(int(x) for x in args.skips.split(","))
     for bounce in (2, 3):
         t0 = time.time()
         h = H.trace(bvh, prev_d, opts=H.TraceOpts(64, 2, 0, 1, 32, 128, 8192, H.TRACE_WIDE)).cpu().numpy()
@@ -673,13 +761,22 @@ def run_bounces(H, args, bvh, tris_h, sec, rays):
                                  bounce=bounce - 1)
         rd = torch.from_numpy(nxt).to(rays.device)
         opts = AT.tune_trace(bvh, rd, None, candidates=AT.WIDE)[0]
-        tw, _ = AT.tune_reorder(bvh, rd, "twopoint", key_bits=(4, 8, 16, 32), skips=(0, 2, 4, 8, 16),
-                                paper_exact=False, candidates=[opts])
-        hc, _ = AT.tune_reorder(bvh, rd, "hcc", cuts=(256, 1024), key_bits=(4, 8, 16, 32), skips=(0, 2, 4, 8, 16),
-                                paper_exact=False, candidates=[opts])
-        rows = [measure_variant(H, bvh, rd, v, opts, args.grid_reps)
-                for v in (dict(mode="nosort"), dict(mode="twopoint", K=tw.key_bits, skip=tw.skip),
-                          dict(mode="hcc", C=hc.cut, K=hc.key_bits, skip=hc.skip))]
+        tw, _ = AT.tune_reorder(bvh, rd, "twopoint", key_bits=(16, 32), skips=sk, candidates=[opts],
+                                min_sorted_frac=args.min_sorted_frac)
+        hc, _ = AT.tune_reorder(bvh, rd, "hcc", cuts=(16, 32), key_bits=(16, 32), skips=sk, paper_exact=True,
+                                candidates=[opts], min_sorted_frac=args.min_sorted_frac)
+        variants = [dict(mode="nosort"), dict(mode="twopoint", K=tw.key_bits, skip=tw.skip),
+                    dict(mode="hcc", C=hc.cut, K=hc.key_bits, skip=hc.skip),
+                    dict(mode="hcc", C=32, K=32), dict(mode="hcc", C=64, K=64),
+                    dict(mode="mlhcc", top=8, low=8, K=16), dict(mode="mlhcc", top=16, low=16, K=32),
+                    dict(mode="twopoint", K=32)]
+        seen, rows = set(), []
+        for v in variants:
+            name = variant_name(v)
+            if name in seen:
+                continue
+            seen.add(name)
+            rows.append(measure_variant(H, bvh, rd, v, opts, args.grid_reps))
         out[str(bounce)] = dict(rays=int(rd.shape[0]), trace_opts=AT.opts_dict(opts), rows=rows)
         log(f"frame bounce {bounce} ({rd.shape[0]} rays, {time.time() - t0:.1f}s): " +
             "; ".join(f"{r['method']} {r['mrays_s']:.0f} Mrays/s (trace {r['trace_ms']:.2f} ms, "
@@ -745,69 +842,131 @@ def measured_traffic(kernel: str):
     return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
 
 
-def roofline_of(H, bvh, rays, perm, R, trace_ms_mean, opts):
-    """Roofline of the trace kernel.  Algorithmic bytes per launch: for each wavefront and each
-    lockstep iteration of the launch as configured, every distinct node (64 B BVH2 node, or
-    128 B 4-wide node) and triangle (48 B) fetched, counted by the kernel itself
-    (hcc_trace_count), plus each ray's record, permutation entry and hit record."""
+def kernel_name(H, opts) -> str:
+    if opts.flags & H.TRACE_WIDE:
+        return "k_trace_wide"
+    return "k_trace_persistent" if opts.persistent else "k_trace"
+
+
+def kernel_counted_fetches(H, bvh, rays, perm, opts) -> dict:
+    """Wavefront-distinct node and triangle fetches per ray as the launch itself counts them
+    (hcc_trace_count for persistent and 4-wide launches, hcc_trace_stats otherwise)."""
     import torch
+    R = rays.shape[0]
     wide = bool(opts.flags & H.TRACE_WIDE)
     if wide or opts.persistent:
         _, nodes, tris = H.trace_count(bvh, rays, perm, opts=opts)
-        _, nodes0, _ = H.trace_count(bvh, rays, None, opts=opts)
-    else:   # one-ray-per-lane launch: its own per-wavefront counters
-        def wave_counts(p):
-            _, _, _, wn, wt = H.trace_stats(bvh, rays, p)
-            return int(wn.to(torch.int64).sum().item()), int(wt.to(torch.int64).sum().item())
-        nodes, tris = wave_counts(perm)
-        nodes0, _ = wave_counts(None)
+    else:
+        _, _, _, wn, wt = H.trace_stats(bvh, rays, perm)
+        nodes, tris = int(wn.to(torch.int64).sum().item()), int(wt.to(torch.int64).sum().item())
     node_bytes = WIDE_NODE_BYTES if wide else NODE_BYTES
-    bytes_per_launch = node_bytes * nodes + TRI_BYTES * tris + R * (RAY_BYTES + PERM_BYTES + HIT_BYTES)
+    return dict(node_fetches_per_ray=round(nodes / R, 3), tri_fetches_per_ray=round(tris / R, 3),
+                node_bytes=node_bytes, bytes_per_ray=round((node_bytes * nodes + TRI_BYTES * tris) / R, 1))
+
+
+def roofline_of(H, R, trace_ms_mean, opts, model, counted):
+    """Roofline of the headline's trace kernel.  Algorithmic bytes per launch: the oracle's
+    lockstep wave model of the rays in the launch's order (distinct 64-byte BVH2 nodes and
+    48-byte triangles per 64-lane wavefront and step, child-test traversal), plus each ray's
+    record, permutation entry and hit record; divided by the kernel's mean launch time over the
+    timed steps (HIP events on the launch stream).  The kernel's own fetch count is reported
+    beside it; without the oracle leg (--no-cpu) it takes the model's place."""
+    io = RAY_BYTES + PERM_BYTES + HIT_BYTES
+    if model is not None:
+        per_ray, numerator = model["bytes_per_ray"], "oracle wave model (BVH2 nodes, 64-lane waves)"
+    elif counted is not None:
+        per_ray, numerator = counted["bytes_per_ray"], "kernel-counted fetches"
+    else:
+        return None
+    bytes_per_launch = R * (per_ray + io)
     achieved = bytes_per_launch / (trace_ms_mean * 1e-3) / 1e9
-    kernel = "k_trace_wide" if wide else ("k_trace_persistent" if opts.persistent else "k_trace")
+    kernel = kernel_name(H, opts)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kernel),
-                    kernel=kernel + "<closest> on HCC-sorted rays",
-                    bytes_per_ray=round(bytes_per_launch / R, 1), node_bytes=node_bytes,
-                    node_fetches_per_ray=round(nodes / R, 3), tri_fetches_per_ray=round(tris / R, 3),
-                    node_fetches_per_ray_nosort=round(nodes0 / R, 3))
-    log(f"roofline: {achieved:.0f} GB/s of algorithmic traffic ({roofline['frac']:.3f} of HBM peak), "
-        f"wave node fetches/ray {roofline['node_fetches_per_ray']} ({node_bytes} B) vs NoSort "
-        f"{roofline['node_fetches_per_ray_nosort']}")
+                    kernel=kernel + "<closest>", launch_ms=round(trace_ms_mean, 4), bytes_per_ray=round(per_ray + io, 1),
+                    numerator=numerator)
+    if counted is not None:
+        roofline["kernel_counted_bytes_per_ray"] = round(counted["bytes_per_ray"] + io, 1)
+    log(f"roofline: {achieved:.0f} GB/s of algorithmic traffic ({roofline['frac']:.3f} of HBM peak) from the "
+        f"{numerator}; {per_ray + io:.0f} B/ray" +
+        (f" (kernel-counted {counted['bytes_per_ray'] + io:.0f} B/ray)" if counted else ""))
     return roofline
 
 
-def cpu_baseline(tris_h, sec, args, gpu_hits, cut_size, key_bits, skip=0):
-    """The oracle's encode + sort + trace on a strided sample of the same secondary rays."""
+def run_oracle_leg(tris_h, sec, args, gpu_hits, conf, head):
+    """The part of the benchmark that runs the CPU oracle: (1) its encode + sort + trace timed on
+    a strided sample of the secondary rays in the headline configuration (the CPU baseline), and
+    (2) its lockstep wave model over every k-th 64-ray wavefront of each method's trace order
+    (keys and sort computed by the oracle over all rays), which gives the roofline's numerator."""
     import oracle as O
     cores = len(os.sched_getaffinity(0))
+    R = sec.shape[0]
+    ob = O.build_bvh(tris_h)
+    had = O.had(ob)
+
+    def order(m):
+        c = conf[m]
+        if m == "nosort":
+            return None, None
+        k, skip = c["key_bits"], c["skip"]
+        if m.startswith("hcc"):
+            keys = O.encode_hcc(sec, O.cut_boxes(ob, O.select_cut(ob, had, c["cut"])), k, threads=cores)
+        else:
+            keys = O.encode_twopoint(sec, O.scene_box(tris_h), k, threads=cores)
+        return keys, (O.sort(keys) if skip == 0 else O.sort_prefix(keys, k, skip))
+
+    # (1) CPU baseline on the headline configuration
+    c = conf[head]
     sample = np.ascontiguousarray(sec[:: args.cpu_stride])
     n = sample.shape[0]
     log(f"CPU oracle on {n} rays with {cores} threads")
-    ob = O.build_bvh(tris_h)
-    cb = O.cut_boxes(ob, O.select_cut(ob, O.had(ob), cut_size))
+    cb = O.cut_boxes(ob, O.select_cut(ob, had, c["cut"])) if head.startswith("hcc") else None
     t0 = time.time()
-    keys = O.encode_hcc(sample, cb, key_bits, threads=cores)
-    perm = O.sort_prefix(keys, key_bits, skip)
+    if cb is not None:
+        keys = O.encode_hcc(sample, cb, c["key_bits"], threads=cores)
+        perm = O.sort_prefix(keys, c["key_bits"], c["skip"])
+    else:
+        perm = None
     h = O.trace(ob, sample, perm=perm, threads=cores)
     dt = time.time() - t0
     g = gpu_hits[:: args.cpu_stride]
     agree = float(np.mean(g[:, 1].copy().view(np.uint32) == h.prim))
     log(f"CPU oracle: {dt:.1f}s, {n / dt / 1e6:.3f} Mrays/s; prim agreement with GPU {agree:.6f}")
-    # the same oracle on one thread, over a sparser sample of the same rays
     one = np.ascontiguousarray(sec[:: args.cpu_stride * 8])
     t0 = time.time()
-    h1 = O.trace(ob, one, perm=O.sort_prefix(O.encode_hcc(one, cb, key_bits), key_bits, skip), threads=1)
+    p1 = O.sort_prefix(O.encode_hcc(one, cb, c["key_bits"]), c["key_bits"], c["skip"]) if cb is not None else None
+    O.trace(ob, one, perm=p1, threads=1)
     dt1 = time.time() - t0
     log(f"CPU oracle, 1 thread: {one.shape[0]} rays in {dt1:.1f}s, {one.shape[0] / dt1 / 1e6:.4f} Mrays/s")
-    del h1
-    return dict(value=round(n / dt / 1e6, 4), unit="Mrays/s", cores=cores, kind="oracle",
-                sample=f"every {args.cpu_stride}th bounce-1 secondary ray ({n} rays): HCC encode (C={cut_size}, "
-                       f"K={key_bits}) + stable sort (on the top {key_bits - skip} bits) + closest-hit trace, "
-                       f"{dt:.1f} s wall",
-                prim_agreement_with_gpu=agree,
-                single_thread=dict(value=round(one.shape[0] / dt1 / 1e6, 4), unit="Mrays/s", cores=1,
-                                   sample=f"every {args.cpu_stride * 8}th ray ({one.shape[0]} rays), {dt1:.1f} s"))
+    cpu = dict(value=round(n / dt / 1e6, 4), unit="Mrays/s", cores=cores, kind="oracle",
+               sample=f"every {args.cpu_stride}th bounce-1 secondary ray ({n} rays): {head} encode (C={c['cut']}, "
+                      f"K={c['key_bits']}) + stable sort (top {c['key_bits'] - c['skip']} bits) + closest-hit trace, "
+                      f"{dt:.1f} s wall",
+               prim_agreement_with_gpu=agree,
+               single_thread=dict(value=round(one.shape[0] / dt1 / 1e6, 4), cores=1,
+                                  sample=f"every {args.cpu_stride * 8}th ray ({one.shape[0]} rays), {dt1:.1f} s"))
+
+    # (2) wave model of each method's trace order
+    model = {}
+    n_waves = (R + 63) // 64
+    waves = np.arange(0, n_waves, args.model_wave_stride, dtype=np.uint32)
+    for m in conf:
+        t0 = time.time()
+        keys, perm = order(m)
+        nodes, tris, _ = O.wave_fetches(ob, sec, perm, 64, True, 1, waves, threads=cores)
+        # wavefronts modelled: every stride-th, the ragged last one counted at its own size
+        rays_modelled = sum(min(64, R - 64 * int(w)) for w in waves)
+        nf = float(nodes.sum()) / rays_modelled
+        tf = float(tris.sum()) / rays_modelled
+        model[m] = dict(node_fetches_per_ray=round(nf, 3), tri_fetches_per_ray=round(tf, 3),
+                        bytes_per_ray=round(NODE_BYTES * nf + TRI_BYTES * tf, 1),
+                        waves_modelled=int(waves.shape[0]), wave_stride=args.model_wave_stride)
+        if keys is not None:
+            model[m]["anc64"] = round(O.anc(keys, perm, 64), 3)
+            model[m]["anc32"] = round(O.anc(keys, perm, 32), 3)
+        log(f"wave model {m}: {nf:.2f} node + {tf:.2f} triangle fetches per ray "
+            f"({waves.shape[0]} wavefronts, {time.time() - t0:.1f}s)")
+    return dict(cpu_baseline=cpu, model=model)
 
 
 if __name__ == "__main__":

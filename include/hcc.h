@@ -311,6 +311,16 @@ hcc_status hcc_batch_run(const hcc_batch_desc* batches, uint32_t nb, hcc_key_mod
  * results of that run are not valid; this indicates a library fault, never a user error). */
 hcc_status hcc_batch_check(const void* d_ws, hcc_stream stream, uint32_t* h_ok);
 
+/* Inspection of a finished hcc_batch_run (parity checks of the in-launch encode and sort):
+ * stream-ordered copies of batch `batch`'s final permutation (d_perm: n uint32, the batch's ray
+ * indices in sorted order) and of its keys in that order (d_sorted_keys: n keys, uint32 when
+ * key_bits <= 32 else uint64), read from d_ws as the last run left it.  Pass the batch list,
+ * mode, key length and options of that run; another call on d_ws in between invalidates the
+ * result.  Either output may be NULL.  HCC_ERR_UNSUPPORTED for mode HCC_KEY_NONE. */
+hcc_status hcc_batch_export(const hcc_batch_desc* batches, uint32_t nb, hcc_key_mode mode, uint32_t key_bits,
+                            const hcc_batch_opts* opts, const void* d_ws, size_t ws_bytes, uint32_t batch,
+                            uint32_t* d_perm, void* d_sorted_keys, hcc_stream stream);
+
 /* ---------------------------------------------------------------------------------------
  * Request server with continuous batching (not in the paper: serving around its path).
  * A worker thread admits queued requests in arrival order while the device ray-state budget

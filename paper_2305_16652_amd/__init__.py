@@ -458,6 +458,25 @@ def batch_run(batches, mode: int, key_bits: int = 32, opts: BatchOpts | None = N
     return ws
 
 
+lib.hcc_batch_export.argtypes = [C.c_void_p, C.c_uint32, C.c_int, C.c_uint32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                 C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p]
+lib.hcc_batch_export.restype = C.c_int
+
+
+def batch_export(batches, mode: int, key_bits: int, ws, index: int, opts: BatchOpts | None = None, stream=None):
+    """Batch ``index``'s final permutation and sorted keys from the workspace of the last
+    batch_run with the same batches, mode, key length and options: (perm int32, keys)."""
+    arr = _descs(batches)
+    n = batches[index].rays.shape[0]
+    dev = batches[index].rays.device
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    keys = torch.empty(max(n, 1), dtype=torch.int32 if key_bits <= 32 else torch.int64, device=dev)
+    _check(lib.hcc_batch_export(C.cast(arr, C.c_void_p), len(batches), mode, key_bits,
+                                C.byref(opts) if opts is not None else None, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                index, _dptr(perm), _dptr(keys), _stream(stream)))
+    return perm[:n], keys[:n]
+
+
 lib.hcc_batch_check.argtypes = [_P, _P, C.POINTER(C.c_uint32)]
 lib.hcc_batch_check.restype = C.c_int
 

@@ -80,12 +80,14 @@ class Choice:
 
 
 def tune_reorder(bvh, rays, mode: str, cuts=(32, 64), key_bits=(32, 64), closest: bool = True,
-                 candidates=None, reps: int = 2, paper_exact: bool = True, skips=(0,)) -> tuple[Choice, list]:
+                 candidates=None, reps: int = 2, paper_exact: bool = True, skips=(0,),
+                 min_sorted_frac: float = 0.0) -> tuple[Choice, list]:
     """Best (cut, key length, skipped low bits, trace options) for a reordering method, by total
     encode + sort + trace time.  mode: 'hcc' or 'twopoint' (cut ignored).  With paper_exact only
     C = K pairs, otherwise every pair with C >= K (the key then holds the K cut nodes of highest
-    HAD).  skips: numbers of low key bits the sort may leave out (the paper's shortened sort);
-    the trace options are tuned on the first of them and reused for the others."""
+    HAD).  skips: numbers of low key bits the sort may leave out (the paper's shortened sort),
+    limited to those that keep at least min_sorted_frac of the key's bits in the sort; the trace
+    options are tuned on the first of them and reused for the others."""
     n = rays.shape[0]
     dev = rays.device
     results = []
@@ -104,7 +106,7 @@ def tune_reorder(bvh, rays, mode: str, cuts=(32, 64), key_bits=(32, 64), closest
         enc_ms = _time(lambda: encode(bvh, cut, m, k, rays, out=keys), reps)
         o = None
         for s in skips:
-            if s >= k:
+            if s >= k or (k - s) < min_sorted_frac * k:
                 continue
             sort_ms = _time(lambda: sort_ex(keys, k, s, 0, perm=perm, ws=ws), reps)
             if o is None:

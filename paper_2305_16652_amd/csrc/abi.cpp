@@ -39,6 +39,9 @@ hcc_status batch_workspace(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, 
 hcc_status batch_run(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits, const hcc_batch_opts& o,
                      void* d_ws, size_t ws_bytes, hipStream_t stream);
 hcc_status batch_check(const void* d_ws, hipStream_t stream, uint32_t* ok);
+hcc_status batch_export(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
+                        const hcc_batch_opts& o, const void* d_ws, size_t ws_bytes, uint32_t b, uint32_t* d_perm,
+                        void* d_sorted_keys, hipStream_t stream);
 
 namespace {
 thread_local std::string g_error;
@@ -492,6 +495,23 @@ __attribute__((visibility("default"))) hcc_status hcc_batch_run(const hcc_batch_
     if (o.direct_min != 0 && o.direct_min < 65536)
         return fail(HCC_ERR_INVALID, "hcc_batch_run: opts.direct_min must be 0 or at least 65536");
     return batch_run(batches, nb, mode, key_bits, o, d_ws, ws_bytes, S(stream));
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_batch_export(const hcc_batch_desc* batches, uint32_t nb,
+                                                                   hcc_key_mode mode, uint32_t key_bits,
+                                                                   const hcc_batch_opts* opts, const void* d_ws,
+                                                                   size_t ws_bytes, uint32_t batch, uint32_t* d_perm,
+                                                                   void* d_sorted_keys, hcc_stream stream) {
+    hcc_status st = check_batches(batches, nb, mode, key_bits);
+    if (st != HCC_OK) return st;
+    if (mode == HCC_KEY_NONE) return fail(HCC_ERR_UNSUPPORTED, "hcc_batch_export: a trace-only run has no keys");
+    if (!d_ws || ((uintptr_t)d_ws & 255u)) return fail(HCC_ERR_INVALID, "hcc_batch_export: workspace must be 256-byte aligned");
+    if (batch >= nb) return fail(HCC_ERR_INVALID, "hcc_batch_export: batch index out of range");
+    hcc_batch_opts o{};
+    if (opts) o = *opts;
+    if (o.direct_min != 0 && o.direct_min < 65536)
+        return fail(HCC_ERR_INVALID, "hcc_batch_export: opts.direct_min must be 0 or at least 65536");
+    return batch_export(batches, nb, mode, key_bits, o, d_ws, ws_bytes, batch, d_perm, d_sorted_keys, S(stream));
 }
 
 __attribute__((visibility("default"))) hcc_status hcc_batch_check(const void* d_ws, hcc_stream stream,

@@ -1026,6 +1026,72 @@ hcc_status graph_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uin
     return HCC_OK;
 }
 
+// Distinct (bvh, cut) pairs of a batch list, the scene table fill_tables builds.
+static uint32_t count_scenes(const hcc_batch_desc* d, uint32_t nb) {
+    std::vector<std::pair<const hcc_bvh_s*, const hcc_cut_s*>> seen;
+    for (uint32_t b = 0; b < nb; ++b) {
+        const auto key = std::make_pair((const hcc_bvh_s*)d[b].bvh, (const hcc_cut_s*)d[b].cut);
+        if (std::find(seen.begin(), seen.end(), key) == seen.end()) seen.push_back(key);
+    }
+    return (uint32_t)seen.size();
+}
+
+template <typename K>
+__global__ void k_gather_keys(const K* __restrict__ keys, const uint32_t* __restrict__ perm, uint32_t n,
+                              K* __restrict__ out) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = keys[perm[i]];
+}
+
+// Batch b's final permutation and its keys in that order, as the last run on d_ws (with the
+// same batch list, mode, key length and options) left them: for an engine batch the last sort
+// pass's output buffers, for a direct launch its permutation and its keys gathered through it.
+hcc_status batch_export(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uint32_t key_bits,
+                        const hcc_batch_opts& o, const void* d_ws, size_t ws_bytes, uint32_t b, uint32_t* d_perm,
+                        void* d_sorted_keys, hipStream_t stream) {
+    const uint32_t n = d[b].n;
+    if (n == 0) return HCC_OK;
+    const size_t ks = key_bits <= 32 ? 4 : 8;
+    const char* ws = (const char*)d_ws;
+    if (o.direct_min != 0 && n >= o.direct_min) {
+        size_t off = al(plan_batches(d, nb, nb, mode, key_bits, 0).total);
+        for (uint32_t i = 0; i < b; ++i)
+            if (d[i].n >= o.direct_min) off += direct_bytes(d[i].n, mode, key_bits);
+        if (off + direct_bytes(n, mode, key_bits) > ws_bytes) return fail(HCC_ERR_INVALID, "hcc_batch_export: workspace too small");
+        const void* keys = ws + off;
+        const uint32_t* pm = (const uint32_t*)(ws + off + al((size_t)n * ks));
+        if (d_perm) HCC_HIP(hipMemcpyAsync(d_perm, pm, (size_t)n * 4, hipMemcpyDeviceToDevice, stream));
+        if (d_sorted_keys) {
+            const unsigned grid = std::min<unsigned>(4096u, (n + 255) / 256);
+            if (ks == 4) k_gather_keys<uint32_t><<<grid, 256, 0, stream>>>((const uint32_t*)keys, pm, n, (uint32_t*)d_sorted_keys);
+            else k_gather_keys<uint64_t><<<grid, 256, 0, stream>>>((const uint64_t*)keys, pm, n, (uint64_t*)d_sorted_keys);
+            HCC_HIP(hipGetLastError());
+        }
+        return HCC_OK;
+    }
+    // engine batch: offsets within the plan of the list the engine launch received
+    std::vector<hcc_batch_desc> list;
+    uint32_t at = b;
+    if (o.direct_min != 0) {
+        for (uint32_t i = 0; i < nb; ++i) {
+            if (d[i].n >= o.direct_min) continue;
+            if (i == b) at = (uint32_t)list.size();
+            list.push_back(d[i]);
+        }
+    } else {
+        list.assign(d, d + nb);
+    }
+    const uint32_t nl = (uint32_t)list.size();
+    const Plan P = plan_batches(list.data(), nl, count_scenes(list.data(), nl), mode, key_bits, 0);
+    if (P.total > ws_bytes) return fail(HCC_ERR_INVALID, "hcc_batch_export: workspace too small");
+    const uint32_t passes = (key_bits + 7) / 8;
+    const bool in_a = ((passes - 1) & 1) != 0;
+    const void* keys = ws + (in_a ? P.keys_a[at] : P.keys_b[at]);
+    const void* vals = ws + (in_a ? P.vals_a[at] : P.vals_b[at]);
+    if (d_perm) HCC_HIP(hipMemcpyAsync(d_perm, vals, (size_t)n * 4, hipMemcpyDeviceToDevice, stream));
+    if (d_sorted_keys) HCC_HIP(hipMemcpyAsync(d_sorted_keys, keys, (size_t)n * ks, hipMemcpyDeviceToDevice, stream));
+    return HCC_OK;
+}
+
 // The engine's error flag (word 1 of every workspace): nonzero when a bounded wait gave up.
 hcc_status batch_check(const void* d_ws, hipStream_t stream, uint32_t* ok) {
     uint32_t flag = 0;

@@ -36,6 +36,36 @@ def scenes(H):
 
 
 SIZES = [0, 1, 63, 64, 1023, 1024, 1025, 4097, 9000]
+_ORACLE_CUTS = {}
+
+
+def _oracle_keys(s, mode, key_bits, cut_size, rays):
+    """The oracle's keys of a batch (its own cut of the scene for HCC)."""
+    ob = s["ob"]
+    if mode == "hcc":
+        k = (id(ob), cut_size)
+        if k not in _ORACLE_CUTS:
+            _ORACLE_CUTS[k] = O.cut_boxes(ob, O.select_cut(ob, O.had(ob), cut_size))
+        return O.encode_hcc(rays, _ORACLE_CUTS[k], key_bits)
+    return O.encode_twopoint(rays, O.scene_box(ob.tris), key_bits)
+
+
+def check_engine_order(H, items, mode, key_bits, cut_size, ws, opts=None):
+    """Every batch's final permutation and sorted keys inside the engine workspace equal the
+    oracle's stable sort of the oracle's keys, bit for bit."""
+    key_mode = {"hcc": H.KEY_HCC, "twopoint": H.KEY_TWOPOINT}[mode]
+    batches = [it[1] for it in items]
+    for i, it in enumerate(items):
+        s, b = it[0], it[1]
+        rays = b.rays.cpu().numpy()
+        if rays.shape[0] == 0:
+            continue
+        perm, keys = H.batch_export(batches, key_mode, key_bits, ws, i, opts=opts)
+        ref_keys = _oracle_keys(s, mode, key_bits, cut_size, rays)
+        ref_perm = O.sort(ref_keys)
+        kd = np.uint32 if key_bits <= 32 else np.uint64
+        assert np.array_equal(perm.cpu().numpy().view(np.uint32), ref_perm), f"batch {i}: permutation"
+        assert np.array_equal(keys.cpu().numpy().view(kd), ref_keys[ref_perm]), f"batch {i}: sorted keys"
 
 
 def _batches(H, scenes, seed, key_cut):
@@ -63,6 +93,8 @@ def test_engine_matches_oracle_and_plain_path(H, scenes, mode, key_bits, cut, op
     ws = H.batch_run([b for _, b, _ in items], key_mode, key_bits, opts=o)
     assert H.batch_check(ws)
     torch.cuda.synchronize()
+    if mode != "none":
+        check_engine_order(H, items, mode, key_bits, {"cut32": 32, "cut64": 64}.get(cut, 0), ws, o)
     for s, b, rays in items:
         n = rays.shape[0]
         if n == 0:
@@ -96,8 +128,11 @@ def test_engine_direct_launches_for_large_batches(H, scenes, mode):
         rays = np.ascontiguousarray(np.resize(pool, (n, 8)), np.float32)
         items.append((s, H.Batch(s["bvh"], torch.from_numpy(rays).cuda(), closest,
                                  cut=s["cut32"] if mode == "hcc" else None), rays))
-    ws = H.batch_run([b for _, b, _ in items], key_mode, 32, opts=H.BatchOpts(0, 0, 0, 0, 65536))
+    od = H.BatchOpts(0, 0, 0, 0, 65536)
+    ws = H.batch_run([b for _, b, _ in items], key_mode, 32, opts=od)
     assert H.batch_check(ws)
+    if mode != "none":   # engine batches and direct launches alike
+        check_engine_order(H, items, mode, 32, 32, ws, od)
     big = [b for _, b, _ in items if b.rays.shape[0] >= 65536]
     assert H.batch_check(H.batch_run(big, key_mode, 32, opts=H.BatchOpts(0, 0, 0, 0, 65536)))   # no engine part
     torch.cuda.synchronize()
@@ -167,8 +202,9 @@ def test_engine_large_batches_across_phases(H, scenes, mode, key_bits, cut):
     for rep in range(2):
         for _, b in items:
             b.out.fill_(float("nan") if b.out.dtype == torch.float32 else 7)
-        ws = H.batch_run([b for _, b in items], key_mode, key_bits, opts=H.BatchOpts(256, 32, 0, H.TRACE_WIDE),
-                         ws=ws)
+        o = H.BatchOpts(256, 32, 0, H.TRACE_WIDE)
+        ws = H.batch_run([b for _, b in items], key_mode, key_bits, opts=o, ws=ws)
         assert H.batch_check(ws)
+        check_engine_order(H, items, mode, key_bits, 32, ws, o)
         for (_, b), ref in zip(items, refs):
             assert np.array_equal(b.out.cpu().numpy().view(np.uint8), ref.view(np.uint8)), f"run {rep}"

@@ -34,7 +34,7 @@ def _keys(t, kb):
     return a.view(np.uint32) if kb <= 32 else a.view(np.uint64)
 
 
-@pytest.mark.parametrize("top,low", [(8, 8), (16, 16), (4, 32), (30, 2), (1, 64), (64, 32)])
+@pytest.mark.parametrize("top,low", [(8, 8), (16, 16), (4, 32), (30, 2), (1, 64), (64, 32), (32, 32), (40, 24)])
 def test_mlhcc_cut_and_keys_bit_exact(H, tiny, top, low):
     cut = H.select_mlhcc_cut(tiny["bvh"], top, low)
     kind, t_eff, l = H.cut_shape(cut)
@@ -46,9 +46,13 @@ def test_mlhcc_cut_and_keys_bit_exact(H, tiny, top, low):
     assert np.array_equal(low_ids, rl)
     assert np.array_equal(low_boxes.reshape(-1, 6), tiny["ob"].boxes[rl.reshape(-1)])
     kb = min(64, top + low)
-    if t_eff + low > kb:
-        pytest.skip("key too short for this cut")
     rays = tiny["rays"]
+    if t_eff + low > kb:
+        # the cut is valid, but its top bits and low bits cannot share one 64-bit key
+        with pytest.raises(H.HCCError):
+            H.encode(tiny["bvh"], cut, H.KEY_MLHCC, kb, torch.from_numpy(rays).cuda())
+        return
+    # (32, 32): 1,024 low-level boxes staged in LDS, the most a 64-bit key can use
     keys = H.encode(tiny["bvh"], cut, H.KEY_MLHCC, kb, torch.from_numpy(rays).cuda())
     ref = O.encode_mlhcc(rays, tiny["ob"].boxes[rt], tiny["ob"].boxes[rl.reshape(-1)], low, kb)
     assert np.array_equal(_keys(keys, kb), ref)
