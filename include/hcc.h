@@ -222,7 +222,7 @@ hcc_status hcc_sort_workspace(uint32_t n, uint32_t key_bits, size_t* bytes);
 hcc_status hcc_sort(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm, void* d_sorted_keys,
                     void* d_ws, size_t ws_bytes, hcc_stream stream);
 
-/* hcc_sort_ex -- shorter sorts for the reorder overhead (Section 6.7: rays within one warp need
+/* hcc_sort_ex -- shorter sorts for the reorder overhead (Sections 6.5 and 6.6.1: rays within one warp need
  * no order among themselves, so the sort may skip the key's last bits or stop early).
  *   skip_bits: the low skip_bits bits take no part: stable ascending by key >> skip_bits, in
  *              ceil((key_bits - skip_bits) / 8) passes.  0 <= skip_bits < key_bits.

@@ -313,7 +313,7 @@ def encode_ppc(bvh: OracleBVH, rays, key_bits: int, threads: int = 1) -> np.ndar
 
 
 def sort_prefix(keys, key_bits: int, skip_bits: int) -> np.ndarray:
-    """Early-terminated sort (Section 6.7's overhead discussion: skip the last bits): the stable
+    """Early-terminated sort (Sections 6.5 and 6.6.1: the order inside one warp does not matter, so the last bits may be skipped): the stable
     ascending permutation by the key's top key_bits - skip_bits bits; the low skip_bits bits do
     not take part."""
     k = np.ascontiguousarray(keys).astype(np.uint64) >> np.uint64(skip_bits)

@@ -724,7 +724,7 @@ void oracle_brute_force(const float* tris, uint32_t n_tris, const float* rays, u
 
 /* ------------------------------------------------------------------ O8: wave model, ANC
  * Metrics, not parity.  Average number of distinct codes per group of 'width'
- * consecutive rays in trace order (Section 6.6, Table 6: per warp). */
+ * consecutive rays in trace order (Section 6.5, Table 6: per warp). */
 double oracle_anc(const uint64_t* keys, const uint32_t* perm, uint32_t n, uint32_t width) {
     if (n == 0 || width == 0) return 0.0;
     uint64_t* buf = (uint64_t*)malloc(sizeof(uint64_t) * width);
