@@ -407,8 +407,10 @@ def compact_line(full: dict, args, workload: str) -> dict:
         line["bounces_mrays_s"] = {k: {r["method"]: r["mrays_s"] for r in v["rows"]} for k, v in b.items()}
     bt = full.get("batched")
     if bt:
-        line["batched_mrays_s"] = {k: bt[k] for k in ("engine_hcc_mrays_s", "plain_hcc_mrays_s",
-                                                     "engine_nosort_mrays_s", "plain_nosort_mrays_s") if k in bt}
+        line["batched_mrays_s"] = {k.replace("_mrays_s", ""): bt[k] for k in (
+            "engine_hcc_mrays_s", "plain_hcc_mrays_s", "engine_hcc_real_cut_mrays_s", "plain_hcc_real_cut_mrays_s",
+            "engine_nosort_mrays_s", "plain_nosort_mrays_s") if k in bt}
+        line["batched_mrays_s"]["pick"] = f"C={bt.get('cut')} K={bt.get('key_bits')}"
     sv = full.get("serve")
     if sv:
         line["serve_p50_p99_ms"] = {rho: {k: [v["p50_ms"], v["p99_ms"]] for k, v in row.items()}
@@ -574,29 +576,50 @@ def run_batched(H, args):
 
     res = {}
     cuts = {}
-    # engine options: autotuned over key length K, cut size C (C = K, or a 256-node cut whose K
-    # cut nodes of highest HAD form the key), chunk, refill and the trace flags
+    # engine tuning in two stages: key length K and cut size C (C = K, or a 256-node cut whose K
+    # nodes of highest HAD form the key) under default options; then, for the best pair and for
+    # the best real cut (C = K >= 16), rays per trace item (chunk), refill, trace flags and the
+    # 4-wide trace phase's stack placement
     pairs = [(K, C) for K in (2, 4, 8, 16, 24, 32) for C in sorted({K, 256})]
     for K, C in pairs:
         cuts[C] = cuts.get(C) or [H.select_cut(s["bvh"], C) for s in scenes]
-    best = None
-    table = []
-    for K, C in pairs:
+
+    def set_cut(C):
         for b, p in zip(batches, plan):
             b.cut = cuts[C][p["scene"]]
+
+    stage1 = []
+    for K, C in pairs:
+        set_cut(C)
         ws = H.batch_run(batches, H.KEY_HCC, K)
+        o = H.BatchOpts(256, 32, 8192, H.TRACE_WIDE)
+        stage1.append((timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws), reps=2), K, C))
+    table = []
+
+    def tune_opts(K, C):
+        set_cut(C)
+        ws = H.batch_run(batches, H.KEY_HCC, K)
+        best = None
         for chunk in (128, 256, 512):
             for refill in (24, 32):
-                for flags in (0, H.TRACE_WIDE, H.TRACE_WIDE | H.TRACE_SLAB):
-                    o = H.BatchOpts(chunk, refill, 8192, flags)
-                    ms = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws), reps=2)
-                    table.append((ms, K, C, chunk, refill, flags))
-                    if best is None or ms < best[0]:
-                        best = (ms, K, C, chunk, refill, flags)
-    _, K, C, chunk, refill, flags = best
-    for b, p in zip(batches, plan):
-        b.cut = cuts[C][p["scene"]]
-    o = H.BatchOpts(chunk, refill, 8192, flags, 0)
+                for flags, stacks in ((0, (0,)), (H.TRACE_WIDE, (0, H.STACK_LDS, H.BATCH_STACK_SCRATCH)),
+                                      (H.TRACE_WIDE | H.TRACE_SLAB, (0,))):
+                    for st in stacks:
+                        o = H.BatchOpts(chunk, refill, 8192, flags, 0, st)
+                        ms = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws), reps=2)
+                        table.append((ms, K, C, chunk, refill, flags, st))
+                        if best is None or ms < best[0]:
+                            best = (ms, K, C, chunk, refill, flags, st)
+        return best
+
+    _, K1, C1 = min(stage1)
+    best = tune_opts(K1, C1)
+    real = [t for t in stage1 if t[1] >= 16 and t[1] == t[2]]
+    _, Kr, Cr = min(real)
+    best_real = tune_opts(Kr, Cr) if (Kr, Cr) != (K1, C1) else best
+    _, K, C, chunk, refill, flags, st = best
+    set_cut(C)
+    o = H.BatchOpts(chunk, refill, 8192, flags, 0, st)
     ws = H.batch_run(batches, H.KEY_HCC, K, opts=o)
     res["engine_hcc_ms"] = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws))
     wsn = H.batch_run(batches, 0, K, opts=o)
@@ -604,22 +627,32 @@ def run_batched(H, args):
     # the same call with large batches sent through the full-device kernels (direct_min tuned)
     hyb = []
     for dmin in (65536, 262144, 1048576):
-        od = H.BatchOpts(chunk, refill, 8192, flags, dmin)
+        od = H.BatchOpts(chunk, refill, 8192, flags, dmin, st)
         hyb.append((timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=od, ws=ws), reps=3), dmin))
     res["hybrid_hcc_ms"], direct_min = min(hyb)
-    od = H.BatchOpts(chunk, refill, 8192, flags, direct_min)
+    od = H.BatchOpts(chunk, refill, 8192, flags, direct_min, st)
     res["hybrid_nosort_ms"] = timeit(lambda: H.batch_run(batches, 0, K, opts=od, ws=wsn))
     res["plain_hcc_ms"] = timeit(lambda: plain(H.KEY_HCC, K))
     res["plain_nosort_ms"] = timeit(lambda: plain(0, K))
+    # the best real cut (C = K >= 16) in its own tuned options, and the plain path with its keys
+    _, Kr, Cr, chr_, rfr, flr, str_ = best_real
+    set_cut(Cr)
+    o_r = H.BatchOpts(chr_, rfr, 8192, flr, 0, str_)
+    ws_r = H.batch_run(batches, H.KEY_HCC, Kr, opts=o_r)
+    res["engine_hcc_real_cut_ms"] = timeit(lambda: H.batch_run(batches, H.KEY_HCC, Kr, opts=o_r, ws=ws_r))
+    res["plain_hcc_real_cut_ms"] = timeit(lambda: plain(H.KEY_HCC, Kr))
+    set_cut(C)
     out = {k.replace("_ms", "_mrays_s"): round(total / (v * 1e-3) / 1e6, 1) for k, v in res.items()}
     out.update({k: round(v, 3) for k, v in res.items()})
     out.update(dict(batches=len(plan), rays=total, key_bits=K, cut=C,
-                    engine_opts=dict(chunk=chunk, refill=refill, flags=flags), hybrid_direct_min=direct_min,
+                    engine_opts=dict(chunk=chunk, refill=refill, flags=flags, stack=st), hybrid_direct_min=direct_min,
+                    real_cut=dict(key_bits=Kr, cut=Cr, chunk=chr_, refill=rfr, flags=flr, stack=str_),
                     plain_trace_opts=AT.opts_dict(topts),
                     speedup_engine_vs_plain_hcc=round(res["plain_hcc_ms"] / res["engine_hcc_ms"], 3),
                     scenes="cluster 10K/100K/1M/2M triangles",
-                    tuning=[dict(ms=round(t[0], 3), key_bits=t[1], cut=t[2], chunk=t[3], refill=t[4], flags=t[5])
-                            for t in sorted(table)[:5]]))
+                    key_tuning=[dict(ms=round(t[0], 3), key_bits=t[1], cut=t[2]) for t in sorted(stage1)],
+                    tuning=[dict(ms=round(t[0], 3), key_bits=t[1], cut=t[2], chunk=t[3], refill=t[4], flags=t[5],
+                                 stack=t[6]) for t in sorted(table)[:8]]))
     log(f"batched: engine HCC {out['engine_hcc_mrays_s']} Mrays/s (with direct launches >= {direct_min} rays: "
         f"{out['hybrid_hcc_mrays_s']}) vs plain {out['plain_hcc_mrays_s']}; NoSort engine "
         f"{out['engine_nosort_mrays_s']} ({out['hybrid_nosort_mrays_s']}) vs plain {out['plain_nosort_mrays_s']}")

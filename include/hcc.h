@@ -292,7 +292,13 @@ typedef struct hcc_batch_opts {
     uint32_t direct_min;      /* 0 = every batch in the one engine launch (default); else >= 65536:
                                  batches of at least this many rays run afterwards through the
                                  full-device encode / sort / trace kernels on the same stream */
+    uint32_t stack;           /* stack placement of the 4-wide trace phase: 0 or HCC_STACK_SHORT = the
+                                 first 12 entries per lane in LDS, deeper ones in scratch (default);
+                                 HCC_STACK_LDS = the first 24 in LDS; 3 = every entry in scratch.
+                                 The BVH2 trace phase keeps its stack in scratch. */
 } hcc_batch_opts;
+
+#define HCC_BATCH_STACK_SCRATCH 3u   /* hcc_batch_opts.stack: the 4-wide trace phase's stack in scratch only */
 
 /* Device workspace needed by hcc_batch_run for this batch list, key mode and key length (for
  * any opts.direct_min). */

@@ -345,6 +345,7 @@ def trace(bvh: BVH, rays: torch.Tensor, perm=None, closest: bool = True, out=Non
 
 
 TRACE_SPECULATE, TRACE_WIDE, TRACE_SLAB = 1, 2, 4
+BATCH_STACK_SCRATCH = 3
 lib.hcc_trace_count.argtypes = [_H, _P, _P, _U32, C.c_int, _P, _P, C.POINTER(TraceOpts), _P, _P]
 lib.hcc_trace_count.restype = C.c_int
 
@@ -400,9 +401,10 @@ class BatchDesc(C.Structure):
 class BatchOpts(C.Structure):
     """hcc_batch_opts: chunk (rays per trace item), refill, waves (0 = default), flags (TRACE_WIDE),
     direct_min (0 = one engine launch for all; else batches of at least this many rays, >= 65536,
-    run through the full-device kernels)."""
+    run through the full-device kernels), stack (4-wide trace phase: 0 / STACK_SHORT 12 LDS
+    entries, STACK_LDS 24, BATCH_STACK_SCRATCH none)."""
     _fields_ = [("chunk", C.c_uint32), ("refill", C.c_uint32), ("waves", C.c_uint32), ("flags", C.c_uint32),
-                ("direct_min", C.c_uint32)]
+                ("direct_min", C.c_uint32), ("stack", C.c_uint32)]
 
 
 lib.hcc_batch_workspace.argtypes = [C.c_void_p, C.c_uint32, C.c_int, C.c_uint32, C.POINTER(C.c_size_t)]

@@ -494,6 +494,7 @@ __attribute__((visibility("default"))) hcc_status hcc_batch_run(const hcc_batch_
         return fail(HCC_ERR_INVALID, "hcc_batch_run: unknown opts.flags bits");
     if (o.direct_min != 0 && o.direct_min < 65536)
         return fail(HCC_ERR_INVALID, "hcc_batch_run: opts.direct_min must be 0 or at least 65536");
+    if (o.stack > HCC_BATCH_STACK_SCRATCH) return fail(HCC_ERR_INVALID, "hcc_batch_run: opts.stack must be 0..3");
     return batch_run(batches, nb, mode, key_bits, o, d_ws, ws_bytes, S(stream));
 }
 

@@ -67,7 +67,13 @@ namespace {
 
 constexpr uint32_t kTile = 1024;      // keys per encode / sort tile (64 lanes x 16)
 constexpr uint32_t kDirectFloor = 65536;   // smallest batch that may take a direct launch
-constexpr int kEngShort = 12;              // 4-wide trace: stack entries per lane kept in LDS
+constexpr int kEngShort = 12;              // 4-wide trace: default stack entries per lane kept in LDS
+constexpr int kEngLds = 24;                // 4-wide trace with HCC_STACK_LDS: LDS entries per lane
+
+// LDS stack entries per lane of the engine's 4-wide trace phase for an hcc_stack_mode.
+inline int engine_stack_entries(uint32_t stack) {
+    return stack == HCC_BATCH_STACK_SCRATCH ? 0 : (stack == HCC_STACK_LDS ? kEngLds : kEngShort);
+}
 constexpr uint32_t kPerLane = 16;
 constexpr uint32_t kRadix = 256;
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagIncl = 2u << 30, kCountMask = (1u << 30) - 1u;
@@ -438,18 +444,18 @@ __device__ __forceinline__ void cswap4(float& ka, uint32_t& ia, float& kb, uint3
 
 // ---- T over the 4-wide nodes (the persistent 4-wide trace kernel's step, for rays
 // [begin, end) of the batch's order)
-template <bool closest>
+template <bool closest, int kShort>
 __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const uint32_t* perm, uint32_t begin,
                                    uint32_t end, uint32_t refill, uint32_t slab, uint32_t* s_stk) {
     const uint64_t below = below_mask();
-    // first kEngShort entries per lane in LDS (lane-interleaved), deeper ones in scratch
-    uint32_t deep[kWideStack - kEngShort];
+    // first kShort entries per lane in LDS (lane-interleaved), deeper ones in scratch
+    uint32_t deep[kWideStack - kShort];
     uint32_t* lds = s_stk + __lane_id();
     auto push = [&](uint32_t i, uint32_t x) {
-        if (i < (uint32_t)kEngShort) lds[i * 64] = x;
-        else deep[i - kEngShort] = x;
+        if (i < (uint32_t)kShort) lds[i * 64] = x;
+        else deep[i - kShort] = x;
     };
-    auto pop = [&](uint32_t i) { return i < (uint32_t)kEngShort ? lds[i * 64] : deep[i - kEngShort]; };
+    auto pop = [&](uint32_t i) { return i < (uint32_t)kShort ? lds[i * 64] : deep[i - kShort]; };
     uint32_t next = begin;
     bool has = false;
     uint32_t rid = 0, node = kNone, sp = 0, best_prim = kMissPrim, pnode = 0, pmask = 0;
@@ -532,7 +538,7 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
             cswap4(k0, i0, k2, i2);
             cswap4(k1, i1, k3, i3);
             cswap4(k1, i1, k2, i2);
-            if (__ballot(sp + 3 > (uint32_t)kEngShort) == 0) {
+            if (kShort >= 3 && __ballot(sp + 3 > (uint32_t)kShort) == 0) {
                 // every stepping lane has three free LDS slots above its stack top: candidates
                 // are written there and kept if valid, and the top is read back for the pop
                 lds[sp * 64] = i3;
@@ -596,14 +602,15 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
     }
 }
 
+template <int kShort>
 __device__ __forceinline__ void trace_range_wide(const EngScene& sc, const EngBatch& bt, const uint32_t* perm,
                                                  uint32_t begin, uint32_t end, uint32_t refill, uint32_t slab,
                                                  uint32_t* s_stk) {
-    if (bt.closest) trace_range_wide_t<true>(sc, bt, perm, begin, end, refill, slab, s_stk);
-    else trace_range_wide_t<false>(sc, bt, perm, begin, end, refill, slab, s_stk);
+    if (bt.closest) trace_range_wide_t<true, kShort>(sc, bt, perm, begin, end, refill, slab, s_stk);
+    else trace_range_wide_t<false, kShort>(sc, bt, perm, begin, end, refill, slab, s_stk);
 }
 
-template <typename K, bool kWide>
+template <typename K, bool kWide, int kShort>
 __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
                                             uint32_t nb, uint32_t total_items, uint32_t total_tiles, uint32_t* queue,
                                             uint32_t mode, uint32_t key_bits, uint32_t passes, uint32_t refill,
@@ -612,7 +619,7 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
     __shared__ uint32_t s_whist[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
     // the scatter's ranks and the 4-wide trace's short stacks are never live at the same time
-    __shared__ uint32_t s_share[kTile / 2 > kEngShort * 64 ? kTile / 2 : kEngShort * 64];
+    __shared__ uint32_t s_share[kTile / 2 > kShort * 64 ? kTile / 2 : kShort * 64];
     uint16_t* s_rank = reinterpret_cast<uint16_t*>(s_share);
     uint32_t* s_stk = s_share;
     __shared__ uint32_t s_item;
@@ -646,7 +653,8 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
                 perm = ((passes - 1) & 1) ? bt.vals_a : bt.vals_b;
             }
             if (kWide)
-                trace_range_wide(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill, slab, s_stk);
+                trace_range_wide<kShort>(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill, slab,
+                                         s_stk);
             else
                 trace_range(sc, bt, perm, c * bt.chunk, min(bt.n, (c + 1) * bt.chunk), refill);
             continue;
@@ -664,13 +672,13 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
     }
 }
 
-template <typename K, bool kWide>
+template <typename K, bool kWide, int kShort>
 __global__ __launch_bounds__(64) void k_engine(const EngScene* __restrict__ scenes, const EngBatch* __restrict__ batches,
                                                uint32_t nb, uint32_t total_items, uint32_t total_tiles,
                                                uint32_t* queue, uint32_t mode,
                                                uint32_t key_bits, uint32_t passes, uint32_t refill, uint32_t slab) {
-    engine_loop<K, kWide>(scenes, batches, nb, total_items, total_tiles, queue, mode, key_bits, passes, refill,
-                          slab);
+    engine_loop<K, kWide, kShort>(scenes, batches, nb, total_items, total_tiles, queue, mode, key_bits, passes,
+                                  refill, slab);
 }
 
 __global__ void k_zero(uint32_t* p, size_t n) {
@@ -680,10 +688,10 @@ __global__ void k_zero(uint32_t* p, size_t n) {
 // Graph-launched form: the launch parameters that change from group to group come from a
 // header the same graph copies to the device first, so one captured graph (copy, clear,
 // engine) serves every group.
-template <typename K, bool kWide>
+template <typename K, bool kWide, int kShort>
 __global__ __launch_bounds__(64) void k_engine_hdr(const EngHeader* __restrict__ h, const EngScene* __restrict__ scenes,
                                                    const EngBatch* __restrict__ batches) {
-    engine_loop<K, kWide>(scenes, batches, h->nb, h->total_items, h->total_tiles, h->queue, h->mode, h->key_bits,
+    engine_loop<K, kWide, kShort>(scenes, batches, h->nb, h->total_items, h->total_tiles, h->queue, h->mode, h->key_bits,
                           h->passes,
                           h->refill, h->slab);
 }
@@ -951,14 +959,21 @@ static hcc_status engine_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t m
     const uint32_t waves = o.waves ? o.waves : 8192u;
     const unsigned grid = std::max(1u, std::min(waves, h.total_items));
     const bool wide = (o.flags & HCC_TRACE_WIDE) != 0;
-#define HCC_ENGINE(KT, WD)                                                                                        \
-    k_engine<KT, WD><<<grid, 64, 0, stream>>>(dsc, dbt, nb, h.total_items, h.total_tiles, h.queue, mode,       \
-                                              key_bits, h.passes, h.refill, h.slab)
+    const int lds = engine_stack_entries(o.stack);
+#define HCC_ENGINE(KT, WD, SH)                                                                                    \
+    k_engine<KT, WD, SH><<<grid, 64, 0, stream>>>(dsc, dbt, nb, h.total_items, h.total_tiles, h.queue, mode,   \
+                                                  key_bits, h.passes, h.refill, h.slab)
+#define HCC_ENGINE_K(KT)                                                                                          \
+    if (!wide) HCC_ENGINE(KT, false, kEngShort);                                                                  \
+    else if (lds == 0) HCC_ENGINE(KT, true, 0);                                                                   \
+    else if (lds == kEngLds) HCC_ENGINE(KT, true, kEngLds);                                                       \
+    else HCC_ENGINE(KT, true, kEngShort)
     if (key_bits <= 32) {
-        if (wide) HCC_ENGINE(uint32_t, true); else HCC_ENGINE(uint32_t, false);
+        HCC_ENGINE_K(uint32_t);
     } else {
-        if (wide) HCC_ENGINE(uint64_t, true); else HCC_ENGINE(uint64_t, false);
+        HCC_ENGINE_K(uint64_t);
     }
+#undef HCC_ENGINE_K
 #undef HCC_ENGINE
     HCC_HIP(hipGetLastError());
     return HCC_OK;
@@ -984,17 +999,24 @@ hcc_status graph_capture(uint32_t max_batches, uint32_t key_bits, const hcc_batc
     const EngBatch* dbt = (const EngBatch*)(dt + al(sizeof(EngHeader)) + al(sizeof(EngScene) * max_batches));
     const unsigned grid = o.waves ? o.waves : 8192u;
     const bool wide = (o.flags & HCC_TRACE_WIDE) != 0;
+    const int lds = engine_stack_entries(o.stack);
     HCC_HIP(hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipMemcpyAsync(dt, pinned, bytes, hipMemcpyHostToDevice, capture_stream);
     if (e == hipSuccess) {
         k_zero_hdr<<<512, 256, 0, capture_stream>>>(dh);
+#define HCC_ENGINE_HDR(KT, WD, SH) k_engine_hdr<KT, WD, SH><<<grid, 64, 0, capture_stream>>>(dh, dsc, dbt)
+#define HCC_ENGINE_HDR_K(KT)                                                                                      \
+    if (!wide) HCC_ENGINE_HDR(KT, false, kEngShort);                                                              \
+    else if (lds == 0) HCC_ENGINE_HDR(KT, true, 0);                                                               \
+    else if (lds == kEngLds) HCC_ENGINE_HDR(KT, true, kEngLds);                                                   \
+    else HCC_ENGINE_HDR(KT, true, kEngShort)
         if (key_bits <= 32) {
-            if (wide) k_engine_hdr<uint32_t, true><<<grid, 64, 0, capture_stream>>>(dh, dsc, dbt);
-            else k_engine_hdr<uint32_t, false><<<grid, 64, 0, capture_stream>>>(dh, dsc, dbt);
+            HCC_ENGINE_HDR_K(uint32_t);
         } else {
-            if (wide) k_engine_hdr<uint64_t, true><<<grid, 64, 0, capture_stream>>>(dh, dsc, dbt);
-            else k_engine_hdr<uint64_t, false><<<grid, 64, 0, capture_stream>>>(dh, dsc, dbt);
+            HCC_ENGINE_HDR_K(uint64_t);
         }
+#undef HCC_ENGINE_HDR_K
+#undef HCC_ENGINE_HDR
         e = hipGetLastError();
     }
     hipGraph_t graph = nullptr;

@@ -392,7 +392,8 @@ __attribute__((visibility("default"))) hcc_status hcc_server_create(const hcc_se
     if (o.direct_min == 0) o.direct_min = 65536;
     if (o.streams == 0) o.streams = 4;
     if (o.key_bits == 0) o.key_bits = 32;
-    if (o.key_bits > 64 || o.streams > 32 || o.key_mode > HCC_KEY_TWOPOINT || (o.batch.flags & ~(HCC_TRACE_WIDE | HCC_TRACE_SLAB)))
+    if (o.key_bits > 64 || o.streams > 32 || o.key_mode > HCC_KEY_TWOPOINT || (o.batch.flags & ~(HCC_TRACE_WIDE | HCC_TRACE_SLAB)) ||
+        o.batch.stack > HCC_BATCH_STACK_SCRATCH)
         return fail(HCC_ERR_INVALID, "hcc_server_create: bad options");
     o.batch.direct_min = 0;   // large requests are routed by the server itself (direct_min above)
     hcc_server_s* s = new hcc_server_s();

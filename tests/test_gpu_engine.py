@@ -85,7 +85,7 @@ def _batches(H, scenes, seed, key_cut):
 @pytest.mark.parametrize("mode,key_bits,cut", [("hcc", 32, "cut32"), ("hcc", 64, "cut64"), ("hcc", 16, "cut32"),
                                                ("twopoint", 32, None), ("twopoint", 64, None), ("none", 32, None)])
 @pytest.mark.parametrize("opts", [None, (64, 1, 7, 0), (1000, 64, 3, 0), (256, 32, 0, 2), (64, 5, 11, 2),
-                                  (128, 24, 0, 6)])
+                                  (128, 24, 0, 6), (256, 32, 0, 2, 0, 3), (64, 9, 13, 6, 0, 1)])
 def test_engine_matches_oracle_and_plain_path(H, scenes, mode, key_bits, cut, opts):
     key_mode = {"hcc": H.KEY_HCC, "twopoint": H.KEY_TWOPOINT, "none": 0}[mode]
     items = _batches(H, scenes, seed=key_bits + (opts[0] if opts else 0), key_cut=cut if mode == "hcc" else None)
@@ -176,6 +176,8 @@ def test_engine_invalid_arguments(H, scenes):
         H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 1))
     with pytest.raises(H.HCCError):
         H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 8))
+    with pytest.raises(H.HCCError):
+        H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 2, 0, 4))
 
 
 @pytest.mark.parametrize("mode,key_bits,cut", [("hcc", 8, "cut32"), ("hcc", 16, "cut32"), ("twopoint", 32, None)])
@@ -199,10 +201,11 @@ def test_engine_large_batches_across_phases(H, scenes, mode, key_bits, cut):
         perm = H.sort(H.encode(s["bvh"], b.cut, key_mode, key_bits, b.rays), key_bits)
         refs.append(H.trace(s["bvh"], b.rays, perm, closest=b.closest).cpu().numpy())
     ws = None
-    for rep in range(2):
+    for rep in range(3):
         for _, b in items:
             b.out.fill_(float("nan") if b.out.dtype == torch.float32 else 7)
-        o = H.BatchOpts(256, 32, 0, H.TRACE_WIDE)
+        # default stack, then the scratch-only and 24-entry LDS stacks of the 4-wide trace phase
+        o = H.BatchOpts(256, 32, 0, H.TRACE_WIDE, 0, (0, H.BATCH_STACK_SCRATCH, H.STACK_LDS)[rep])
         ws = H.batch_run([b for _, b in items], key_mode, key_bits, opts=o, ws=ws)
         assert H.batch_check(ws)
         check_engine_order(H, items, mode, key_bits, 32, ws, o)
