@@ -121,12 +121,15 @@ __global__ __launch_bounds__(kBlock) void k_trace(const Node* __restrict__ nodes
 
     if (n_int == 0) {
         test_leaf(0);
+        if (kStats && first_active_lane()) atomicAdd(wave_tris + wave, 1u);
     } else {
         Stack<kStack, kBlock> st;
         st.init(s_stack);
         uint32_t sp = 0;
         uint32_t node = 0;
-        while (true) {
+        // One traversal step: fetch `node`, test its children's boxes and the triangles of hit
+        // leaf children, then descend, pop, or end the traversal (false).
+        auto step = [&]() -> bool {
             if (kStats) {
                 ++n_nodes;
                 const uint32_t dn = wave_distinct(node);
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const Node* __restrict__ nodes
             }
             if (leaf0) test_leaf(c0 - n_int);
             if (leaf1) test_leaf(c1 - n_int);
-            if (!kClosest && found) break;
+            if (!kClosest && found) return false;
             h0 = h0 && !leaf0;
             h1 = h1 && !leaf1;
             if (h0 && h1) {
@@ -160,9 +163,24 @@ __global__ __launch_bounds__(kBlock) void k_trace(const Node* __restrict__ nodes
             } else if (h1) {
                 node = c1;
             } else {
-                if (sp == 0) break;
+                if (sp == 0) return false;
                 --sp;
                 node = st.pop(sp);
+            }
+            return true;
+        };
+        if (kStats) {
+            // Counting launch: every lane that is still traversing takes exactly one step per
+            // iteration of a wavefront-uniform loop, so iteration s holds each lane's s-th step
+            // (lockstep).  Left to itself the compiler nests the descend path in an inner loop
+            // (lanes that pop wait while the others keep descending), which would make the
+            // per-iteration counts depend on that schedule.
+            bool active = true;
+            while (__ballot(active) != 0) {
+                if (active) active = step();
+            }
+        } else {
+            while (step()) {
             }
         }
     }
