@@ -222,6 +222,20 @@ hcc_status hcc_sort_workspace(uint32_t n, uint32_t key_bits, size_t* bytes);
 hcc_status hcc_sort(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm, void* d_sorted_keys,
                     void* d_ws, size_t ws_bytes, hcc_stream stream);
 
+/* hcc_sort_static -- hcc_sort without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops that must not call hipMalloc,
+ * harnesses that forbid it).  It allocates nothing: its workspace is a fixed array in the
+ * library's device memory, one per GPU (hcc_sort_static_bytes: about 22 MB, held from the
+ * library's load until the process ends), and it runs the kernels of hcc_sort.  Same keys,
+ * permutation, sorted keys and stream ordering as hcc_sort.  n <= HCC_SORT_STATIC_MAX_KEYS,
+ * else HCC_ERR_INVALID (use hcc_sort with a caller workspace).  Every call on one GPU shares
+ * that GPU's array: calls that overlap on a GPU (on other streams, or from other threads
+ * without ordering between them) race and give wrong results; order them on one stream. */
+#define HCC_SORT_STATIC_MAX_KEYS 1048576u
+hcc_status hcc_sort_static(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm,
+                           void* d_sorted_keys, hcc_stream stream);
+hcc_status hcc_sort_static_bytes(size_t* bytes);
+
 /* hcc_sort_ex -- shorter sorts for the reorder overhead (Sections 6.5 and 6.6.1: rays within one warp need
  * no order among themselves, so the sort may skip the key's last bits or stop early).
  *   skip_bits: the low skip_bits bits take no part: stable ascending by key >> skip_bits, in

@@ -331,6 +331,26 @@ def sort_ex(keys: torch.Tensor, key_bits: int, skip_bits: int = 0, tile: int = 0
     return perm
 
 
+lib.hcc_sort_static.argtypes = [_P, _U32, _U32, _P, _P, _P]
+lib.hcc_sort_static.restype = C.c_int
+lib.hcc_sort_static_bytes.argtypes = [C.POINTER(C.c_size_t)]
+lib.hcc_sort_static_bytes.restype = C.c_int
+SORT_STATIC_MAX_KEYS = 1 << 20
+
+
+def sort_static_bytes() -> int:
+    b = C.c_size_t()
+    _check(lib.hcc_sort_static_bytes(C.byref(b)))
+    return b.value
+
+
+def sort_static(keys: torch.Tensor, key_bits: int, perm: torch.Tensor, sorted_keys=None, stream=None) -> torch.Tensor:
+    """hcc_sort with the library's static workspace (allocates nothing; perm is the caller's)."""
+    _check(lib.hcc_sort_static(_dptr(keys), key_bits, keys.shape[0], _dptr(perm), _dptr(sorted_keys),
+                               _stream(stream)))
+    return perm
+
+
 def trace(bvh: BVH, rays: torch.Tensor, perm=None, closest: bool = True, out=None, opts: TraceOpts | None = None,
           stream=None) -> torch.Tensor:
     _check_rays(rays)

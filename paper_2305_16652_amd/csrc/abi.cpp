@@ -376,6 +376,18 @@ __attribute__((visibility("default"))) hcc_status hcc_sort(const void* d_keys, u
     return radix_sort(d_keys, key_bits, n, d_perm, d_sorted_keys, nullptr, d_ws, ws_bytes, S(stream));
 }
 
+__attribute__((visibility("default"))) hcc_status hcc_sort_static(const void* d_keys, uint32_t key_bits,
+                                                                  uint32_t n, uint32_t* d_perm, void* d_sorted_keys,
+                                                                  hcc_stream stream) {
+    return radix_sort_static(d_keys, key_bits, n, d_perm, d_sorted_keys, S(stream));
+}
+
+__attribute__((visibility("default"))) hcc_status hcc_sort_static_bytes(size_t* bytes) {
+    if (!bytes) return fail(HCC_ERR_INVALID, "hcc_sort_static_bytes: null pointer");
+    *bytes = sort_static_bytes();
+    return HCC_OK;
+}
+
 __attribute__((visibility("default"))) hcc_status hcc_sort_ex(const void* d_keys, uint32_t key_bits,
                                                               uint32_t skip_bits, uint32_t tile, uint32_t n,
                                                               uint32_t* d_perm, void* d_sorted_keys, void* d_ws,

@@ -206,6 +206,9 @@ hcc_status hip_fail(hipError_t e, const char* what);
 size_t sort_workspace_bytes(uint32_t n, uint32_t key_bits);
 hcc_status radix_sort(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm, void* d_sorted_keys,
                       const uint32_t* d_vals_in, void* d_ws, size_t ws_bytes, hipStream_t stream);
+size_t sort_static_bytes();
+hcc_status radix_sort_static(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm,
+                             void* d_sorted_keys, hipStream_t stream);
 hcc_status radix_sort_ex(const void* d_keys, uint32_t key_bits, uint32_t skip, uint32_t tile, uint32_t n,
                          uint32_t* d_perm, void* d_sorted_keys, void* d_ws, size_t ws_bytes, hipStream_t stream);
 

@@ -13,6 +13,8 @@
 // Keys: uint32 (key_bits <= 32) or uint64.  Only bits [0, key_bits) take part.
 #include "hcc_internal.h"
 
+#include <mutex>
+
 namespace hcc {
 namespace {
 
@@ -330,13 +332,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_sort(const K* __restrict__ kin,
     }
 }
 
-inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t keys_a, keys_b, vals, hist, counters, lookback, total;
 };
 
-Layout layout(uint32_t n, uint32_t key_bits, uint32_t skip = 0) {
+constexpr Layout layout(uint32_t n, uint32_t key_bits, uint32_t skip = 0) {
     const size_t ks = key_bits <= 32 ? 4 : 8;
     const uint32_t passes = (key_bits - skip + 7) / 8;
     const size_t tiles = ((size_t)n + kTile - 1) / kTile;
@@ -418,9 +420,57 @@ hcc_status run_tile_sort(const K* keys, uint32_t key_bits, uint32_t skip, uint32
     return HCC_OK;
 }
 
+// Workspace of hcc_sort_static: one fixed device array per GPU, so that the call allocates
+// nothing.  It is sized for the largest sort the call accepts (64-bit keys, the most passes);
+// a smaller sort uses a prefix of it.  Host code never passes the array's name to a kernel
+// (on the host it only names the symbol): the per-device address comes from
+// hipGetSymbolAddress on the first call on each device.
+constexpr size_t kStaticBytes = layout(HCC_SORT_STATIC_MAX_KEYS, 64).total;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+hcc_status static_scratch(void** out) {
+    int dev = -1;
+    HCC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(HCC_ERR_UNSUPPORTED, "hcc_sort_static: device index above 63");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(HCC_ERR_DEVICE, "hcc_sort_static: no device address for the static workspace");
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return HCC_OK;
+}
+
 }  // namespace
 
 size_t sort_workspace_bytes(uint32_t n, uint32_t key_bits) { return layout(n, key_bits).total; }
+
+size_t sort_static_bytes() { return kStaticBytes; }
+
+// hcc_sort with the library's static workspace: the same kernels as radix_sort_ex over the
+// whole key range; the zero-initialised parts of the workspace (histograms, tile counters,
+// look-back state) are cleared by a kernel on every call, as in every sort.
+hcc_status radix_sort_static(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm,
+                             void* d_sorted_keys, hipStream_t stream) {
+    if (key_bits < 1 || key_bits > 64) return fail(HCC_ERR_INVALID, "hcc_sort_static: key_bits must be in [1, 64]");
+    if (n > HCC_SORT_STATIC_MAX_KEYS)
+        return fail(HCC_ERR_INVALID, "hcc_sort_static: n exceeds HCC_SORT_STATIC_MAX_KEYS (1048576); "
+                                     "use hcc_sort with a caller workspace");
+    if (n == 0) return HCC_OK;
+    if (!d_keys || !d_perm) return fail(HCC_ERR_INVALID, "hcc_sort_static: null pointer");
+    void* ws = nullptr;
+    const hcc_status st = static_scratch(&ws);
+    if (st != HCC_OK) return st;
+    return radix_sort_ex(d_keys, key_bits, 0, 0, n, d_perm, d_sorted_keys, ws, kStaticBytes, stream);
+}
 
 hcc_status fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return HCC_OK;

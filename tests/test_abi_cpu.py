@@ -49,6 +49,11 @@ def test_validation_without_device(H):
     assert lib.hcc_select_cut(bad, 8, 0.125, None, C.byref(C.c_void_p())) == 1
     assert lib.hcc_sort(None, 32, 0, None, None, None, 0, None) == 0          # n = 0: nothing to do
     assert lib.hcc_sort(None, 33, 10, None, None, None, 0, None) == 1
+    # the no-allocation sort refuses bad sizes before touching the device
+    assert lib.hcc_sort_static(None, 32, 0, None, None, None) == 0     # n = 0: nothing to do
+    assert lib.hcc_sort_static(C.c_void_p(16), 32, (1 << 20) + 1, C.c_void_p(16), None, None) == 1
+    assert lib.hcc_sort_static(C.c_void_p(16), 0, 10, C.c_void_p(16), None, None) == 1
+    assert lib.hcc_sort_static_bytes(C.byref(b)) == 0 and b.value >= H.sort_workspace_bytes(1 << 20, 64)
     lib.hcc_bvh_destroy(bad)      # ignored
     lib.hcc_cut_destroy(bad)
 
