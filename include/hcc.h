@@ -225,7 +225,7 @@ hcc_status hcc_sort(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t*
 /* hcc_sort_static -- hcc_sort without a workspace argument, for callers that cannot allocate
  * device memory (code under HIP graph capture, serving loops that must not call hipMalloc,
  * harnesses that forbid it).  It allocates nothing: its workspace is a fixed array in the
- * library's device memory, one per GPU (hcc_sort_static_bytes: about 22 MB, held from the
+ * library's device memory, one per GPU (hcc_sort_static_bytes: about 21 MB, held from the
  * library's load until the process ends), and it runs the kernels of hcc_sort.  Same keys,
  * permutation, sorted keys and stream ordering as hcc_sort.  n <= HCC_SORT_STATIC_MAX_KEYS,
  * else HCC_ERR_INVALID (use hcc_sort with a caller workspace).  Every call on one GPU shares

@@ -1,15 +1,20 @@
 // Stable LSD radix sort of (key, index) pairs for gfx950, 8-bit digits.
 //
 // Sorting the ray keys as unsigned integers and handing the trace kernel the sorted
-// ray indices is the reorder step of the method (Sections 4.2.3 and 5).  Design:
-//   1. one read of the keys builds the digit histograms of every pass at once;
-//   2. per pass, one kernel ranks a tile of 4096 keys (4 wavefronts x 16 keys per lane)
-//      with wavefront ballots: the lanes holding the same digit are found from one
-//      ballot per digit bit, and their count below a lane gives its stable rank;
-//      the tile's per-digit totals are combined with earlier tiles by a decoupled
-//      look-back (tiles are numbered in the order blocks start, so every tile waited
-//      on is already running); the tile is reordered in LDS and written out so that
-//      equal digits land on consecutive addresses.
+// ray indices is the reorder step of the method (Sections 4.2.3 and 5).  Each pass over one
+// 8-bit digit is a reduce-then-scan over tiles of kTile consecutive keys, three launches with
+// no waiting between workgroups:
+//   1. k_count: each tile's digit counts (one read of the keys, every load of a thread issued
+//      at once; runs of equal digits added to LDS with one atomic), stored digit-major;
+//   2. k_scan: per digit, the exclusive scan of its counts over the tiles (in place) and the
+//      digit's total;
+//   3. k_scatter: each tile ranks its keys with wavefront ballots (the lanes holding the same
+//      digit are found from one ballot per digit bit; their count below a lane is its stable
+//      rank), reorders (key, value) pairs in LDS so that equal digits are consecutive, and
+//      writes them at (keys of smaller digits) + (this digit in earlier tiles) + rank.
+// Tiles are dealt to the eight XCDs in contiguous ranges (the hardware deals workgroups round
+// robin): the runs that consecutive tiles write for one digit are adjacent, and when the
+// tiles sit on one XCD its L2 merges them into whole lines before they reach HBM.
 // Keys: uint32 (key_bits <= 32) or uint64.  Only bits [0, key_bits) take part.
 #include "hcc_internal.h"
 
@@ -19,11 +24,9 @@ namespace hcc {
 namespace {
 
 constexpr uint32_t kBlock = 256;          // 4 wavefronts
-constexpr uint32_t kItems = 16;
+constexpr uint32_t kItems = 16;           // keys per thread and tile
 constexpr uint32_t kTile = kBlock * kItems;
 constexpr uint32_t kRadix = 256;
-constexpr uint32_t kMaxPasses = 8;
-constexpr uint32_t kFlagAgg = 1u << 30, kFlagIncl = 2u << 30, kCountMask = (1u << 30) - 1u;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     const uint32_t lane = __lane_id();
@@ -70,102 +73,165 @@ __global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
     for (; i < n; i += stride) p[i] = v;
 }
 
-// Digit histograms of every pass in one read of the keys.  Thread g takes the four consecutive
-// keys 4g .. 4g+3 and, per pass, adds each run of equal digits among them with one LDS atomic;
-// when all 256 keys of a full wavefront share the digit, one lane adds 256.  Keys are skewed
-// and locally coherent (many rays share a code, neighbours often do), so this keeps most
-// lanes of a wavefront from hitting one bin in the same atomic.
+// Digit counts of one tile per block: counts[d * T + tile].  Thread t reads the kItems
+// consecutive keys starting at t * kItems of its tile with 16-byte loads, all in flight
+// together, and adds each run of equal digits among them to its wavefront's LDS histogram
+// with one atomic (keys of coherent rays repeat: few atomics, little contention).
 template <typename K>
-__global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint32_t n, uint32_t key_bits,
-                                                 uint32_t skip, uint32_t passes, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t s_h[kMaxPasses * kRadix];
-    const uint32_t t = threadIdx.x;
-    for (uint32_t i = t; i < passes * kRadix; i += kBlock) s_h[i] = 0;
-    __syncthreads();
-    const uint32_t groups = (n + 3u) / 4u, full = n / 4u;
-    const bool aligned = ((uintptr_t)keys & 15u) == 0;
-    for (uint32_t base = blockIdx.x * kBlock; base < groups; base += gridDim.x * kBlock) {
-        const uint32_t g = base + t;
-        // keys of this thread: a prefix of the four is valid
-        const uint32_t nv = g < full ? 4u : (g < groups ? n - 4u * g : 0u);
-        K kk[4];
-        if (nv == 4u && aligned && sizeof(K) == 4) {
-            const uint4 q = *reinterpret_cast<const uint4*>(keys + 4 * (size_t)g);
-            kk[0] = (K)q.x; kk[1] = (K)q.y; kk[2] = (K)q.z; kk[3] = (K)q.w;
-        } else {
+__global__ __launch_bounds__(kBlock) void k_count(const K* __restrict__ keys, uint32_t n, uint32_t shift,
+                                                  uint32_t nbits, uint32_t* __restrict__ counts) {
+    constexpr uint32_t kPerLoad = 16 / sizeof(K);
+    __shared__ uint32_t s_h[4 * kRadix];
+    const uint32_t t = threadIdx.x, w = t >> 6;
+    const uint32_t T = gridDim.x;
+    const uint32_t tile = xcd_block(blockIdx.x, T);
+    for (uint32_t i = t; i < 4 * kRadix; i += kBlock) s_h[i] = 0;
+    const uint32_t mask = (1u << nbits) - 1u;
+    const size_t first = (size_t)tile * kTile + (size_t)t * kItems;
+    const uint32_t nv = first >= n ? 0u : ((size_t)n - first >= kItems ? kItems : (uint32_t)((size_t)n - first));
+    K k[kItems];
+    if (nv == kItems && ((uintptr_t)keys & 15u) == 0) {
 #pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) kk[j] = j < nv ? keys[4 * (size_t)g + j] : K(0);
-        }
-        // this thread's wavefront covers 64 full groups
-        const bool wave_full = (base + (t & ~63u) + 64u) <= full;
-        for (uint32_t p = 0; p < passes; ++p) {
-            const uint32_t sh = skip + 8u * p;
-            const uint32_t msk = (1u << min(8u, key_bits - sh)) - 1u;
-            uint32_t d[4];
-#pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) d[j] = (uint32_t)(kk[j] >> sh) & msk;
-            uint32_t* h = s_h + p * kRadix;
-            const uint32_t v0 = __builtin_amdgcn_readfirstlane(d[0]);
-            const bool same = d[0] == v0 && d[1] == v0 && d[2] == v0 && d[3] == v0;
-            if (wave_full && __ballot(same) == ~0ull) {
-                if ((t & 63u) == 0) atomicAdd(&h[v0], 256u);
-                continue;
+        for (uint32_t q = 0; q < kItems / kPerLoad; ++q) {
+            const uint4 v = *reinterpret_cast<const uint4*>(keys + first + kPerLoad * q);
+            if (sizeof(K) == 4) {
+                k[4 * q] = (K)v.x; k[4 * q + 1] = (K)v.y; k[4 * q + 2] = (K)v.z; k[4 * q + 3] = (K)v.w;
+            } else {
+                k[2 * q] = (K)(((uint64_t)v.y << 32) | v.x);
+                k[2 * q + 1] = (K)(((uint64_t)v.w << 32) | v.z);
             }
-            uint32_t cur = d[0], run = nv ? 1u : 0u;
-#pragma unroll
-            for (uint32_t j = 1; j < 4; ++j) {
-                if (j < nv) {
-                    if (d[j] == cur) {
-                        ++run;
-                    } else {
-                        atomicAdd(&h[cur], run);
-                        cur = d[j];
-                        run = 1u;
-                    }
-                }
-            }
-            if (run) atomicAdd(&h[cur], run);
         }
+    } else {
+#pragma unroll
+        for (uint32_t i = 0; i < kItems; ++i) k[i] = i < nv ? keys[first + i] : K(0);
     }
     __syncthreads();
-    for (uint32_t i = t; i < passes * kRadix; i += kBlock)
-        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+    uint32_t* h = s_h + w * kRadix;
+    uint32_t cur = (uint32_t)(k[0] >> shift) & mask, run = nv ? 1u : 0u;
+#pragma unroll
+    for (uint32_t i = 1; i < kItems; ++i) {
+        if (i < nv) {
+            const uint32_t d = (uint32_t)(k[i] >> shift) & mask;
+            if (d == cur) {
+                ++run;
+            } else {
+                atomicAdd(&h[cur], run);
+                cur = d;
+                run = 1u;
+            }
+        }
+    }
+    if (run) atomicAdd(&h[cur], run);
+    __syncthreads();
+    counts[(size_t)t * T + tile] = s_h[t] + s_h[kRadix + t] + s_h[2 * kRadix + t] + s_h[3 * kRadix + t];
 }
+
+// Block d: exclusive scan of digit d's tile counts (row d of counts, T entries, in place),
+// staged through LDS in segments of 4096 (padded one word in 16 so that a thread's 16
+// consecutive entries sit in different banks); the digit's total goes to tot[d].
+__global__ __launch_bounds__(kBlock) void k_scan(uint32_t* __restrict__ counts, uint32_t T, uint32_t* __restrict__ tot) {
+    constexpr uint32_t kSeg = 4096;
+    __shared__ uint32_t s[kSeg + kSeg / 16];
+    __shared__ uint32_t s_scan[4];
+    __shared__ uint32_t s_total;
+    const uint32_t t = threadIdx.x, d = blockIdx.x;
+    uint32_t* row = counts + (size_t)d * T;
+    uint32_t carry = 0;
+    for (uint32_t seg = 0; seg < T; seg += kSeg) {
+        const uint32_t m = min(kSeg, T - seg);
+#pragma unroll
+        for (uint32_t j = 0; j < 16; ++j) {
+            const uint32_t i = t + 256 * j;
+            s[i + (i >> 4)] = i < m ? row[seg + i] : 0u;
+        }
+        __syncthreads();
+        uint32_t x[16], sum = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < 16; ++j) {
+            x[j] = s[17 * t + j];
+            sum += x[j];
+        }
+        uint32_t run = block_excl_scan256(sum, s_scan) + carry;
+        if (t == kBlock - 1) s_total = run + sum;
+#pragma unroll
+        for (uint32_t j = 0; j < 16; ++j) {
+            s[17 * t + j] = run;
+            run += x[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t j = 0; j < 16; ++j) {
+            const uint32_t i = t + 256 * j;
+            if (i < m) row[seg + i] = s[i + (i >> 4)];
+        }
+        carry = s_total;
+        __syncthreads();
+    }
+    if (t == 0) tot[d] = carry;
+}
+
+// LDS staging of a tile's reordered pairs: one 8-byte record per pair for 32-bit keys,
+// separate key and value arrays for 64-bit keys.
+template <typename K>
+struct TileStage {
+    K key[kTile];
+    uint32_t val[kTile];
+    __device__ void put(uint32_t i, K k, uint32_t v) { key[i] = k; val[i] = v; }
+    __device__ void get(uint32_t i, K& k, uint32_t& v) const { k = key[i]; v = val[i]; }
+};
+template <>
+struct TileStage<uint32_t> {
+    uint2 kv[kTile];
+    __device__ void put(uint32_t i, uint32_t k, uint32_t v) { kv[i] = make_uint2(k, v); }
+    __device__ void get(uint32_t i, uint32_t& k, uint32_t& v) const {
+        const uint2 p = kv[i];
+        k = p.x;
+        v = p.y;
+    }
+};
 
 template <typename K, bool kIota, bool kWriteKeys>
 __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                     K* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
-                                                    uint32_t shift, uint32_t nbits,
-                                                    const uint32_t* __restrict__ hist, uint32_t* lookback,
-                                                    uint32_t* counter) {
+                                                    uint32_t shift, uint32_t nbits, const uint32_t* __restrict__ offs,
+                                                    const uint32_t* __restrict__ tot) {
     __shared__ uint32_t s_whist[4 * kRadix];
-    __shared__ uint32_t s_dexcl[kRadix];
-    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_gofs[kRadix];
     __shared__ uint32_t s_scan[8];
-    __shared__ uint32_t s_tile;
-    __shared__ K s_keys[kTile];
-    __shared__ uint32_t s_vals[kTile];
-
+    __shared__ TileStage<K> s_tile;
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
-    if (t == 0) s_tile = atomicAdd(counter, 1u);
-    for (uint32_t i = t; i < 4 * kRadix; i += kBlock) s_whist[i] = 0;
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint32_t base = tile * kTile + w * (64u * kItems) + lane;
+    const uint32_t T = gridDim.x;
+    const uint32_t tile = xcd_block(blockIdx.x, T);
     const uint32_t mask = (1u << nbits) - 1u;
+    for (uint32_t i = t; i < 4 * kRadix; i += kBlock) s_whist[i] = 0;
+    const uint32_t base = tile * kTile + w * (64u * kItems) + lane;
     const uint64_t lt = lanemask_lt();
     uint32_t* wh = s_whist + w * kRadix;
 
     K k[kItems];
     uint32_t v[kItems];
     uint32_t r[kItems];
+    if ((tile + 1) * kTile <= n) {
 #pragma unroll
-    for (uint32_t i = 0; i < kItems; ++i) {
-        const uint32_t idx = base + i * 64u;
-        const bool valid = idx < n;
-        k[i] = valid ? kin[idx] : K(0);
-        v[i] = kIota ? idx : (valid ? vin[idx] : 0u);
+        for (uint32_t i = 0; i < kItems; ++i) {
+            const uint32_t idx = base + i * 64u;
+            k[i] = kin[idx];
+            v[i] = kIota ? idx : vin[idx];
+        }
+    } else {
+#pragma unroll
+        for (uint32_t i = 0; i < kItems; ++i) {
+            const uint32_t idx = base + i * 64u;
+            const bool valid = idx < n;
+            k[i] = valid ? kin[idx] : K(0);
+            v[i] = kIota ? idx : (valid ? vin[idx] : 0u);
+        }
     }
+    // the tile's global offsets do not depend on its keys: read them while the keys load
+    const uint32_t gtot = tot[t];
+    const uint32_t gofs = offs[(size_t)t * T + tile];
+    __syncthreads();
+
     // stable rank of every key among the keys of its wavefront with the same digit
 #pragma unroll
     for (uint32_t i = 0; i < kItems; ++i) {
@@ -181,76 +247,40 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ kin, c
     }
     __syncthreads();
 
-    // thread t owns digit t: tile total, per-wavefront exclusive offsets
+    // thread t owns digit t: where each wavefront's keys of digit t start in the tile, and the
+    // distance from a position in the tile to its position in the output
     const uint32_t d = t;
     const uint32_t c0 = s_whist[d], c1 = s_whist[kRadix + d], c2 = s_whist[2 * kRadix + d],
                    c3 = s_whist[3 * kRadix + d];
-    const uint32_t cnt = c0 + c1 + c2 + c3;
-    s_whist[d] = 0;
-    s_whist[kRadix + d] = c0;
-    s_whist[2 * kRadix + d] = c0 + c1;
-    s_whist[3 * kRadix + d] = c0 + c1 + c2;
-
-    // decoupled look-back over earlier tiles for digit d
-    uint32_t excl = 0;
-    uint32_t* mine = lookback + (size_t)tile * kRadix + d;
-    if (tile == 0) {
-        __hip_atomic_store(mine, kFlagIncl | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        __hip_atomic_store(mine, kFlagAgg | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // walk back over the earlier tiles four at a time (four loads in flight per round trip);
-        // tile 0 always holds an inclusive prefix, so the walk ends at or above it
-        constexpr int kLookWindow = 4;
-        int64_t j = (int64_t)tile - 1;
-        while (true) {
-            uint32_t x[kLookWindow];
-#pragma unroll
-            for (int q = 0; q < kLookWindow; ++q)
-                x[q] = j - q >= 0 ? __hip_atomic_load(lookback + (size_t)(j - q) * kRadix + d, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT)
-                                  : kFlagIncl;
-            int used = kLookWindow;
-            bool done = false;
-#pragma unroll
-            for (int q = 0; q < kLookWindow; ++q) {
-                if (done || used < kLookWindow) continue;
-                const uint32_t f = x[q] & ~kCountMask;
-                if (f == 0) {
-                    used = q;          // not yet published: take what came before, poll again
-                } else {
-                    excl += x[q] & kCountMask;
-                    done = f == kFlagIncl;
-                }
-            }
-            if (done) break;
-            j -= used;
-            if (used < kLookWindow) __builtin_amdgcn_s_sleep(1);
-        }
-        __hip_atomic_store(mine, kFlagIncl | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const uint32_t hexcl = block_excl_scan256(hist[d], s_scan);
-    const uint32_t dexcl = block_excl_scan256(cnt, s_scan + 4);
-    s_gbase[d] = hexcl + excl;
-    s_dexcl[d] = dexcl;
+    const uint32_t dexcl = block_excl_scan256(c0 + c1 + c2 + c3, s_scan);
+    const uint32_t gbase = block_excl_scan256(gtot, s_scan + 4) + gofs;
+    s_whist[d] = dexcl;
+    s_whist[kRadix + d] = dexcl + c0;
+    s_whist[2 * kRadix + d] = dexcl + c0 + c1;
+    s_whist[3 * kRadix + d] = dexcl + c0 + c1 + c2;
+    s_gofs[d] = gbase - dexcl;
     __syncthreads();
 
 #pragma unroll
     for (uint32_t i = 0; i < kItems; ++i) {
         if (base + i * 64u < n) {
             const uint32_t dd = (uint32_t)(k[i] >> shift) & mask;
-            const uint32_t pos = s_dexcl[dd] + wh[dd] + r[i];
-            s_keys[pos] = k[i];
-            s_vals[pos] = v[i];
+            s_tile.put(wh[dd] + r[i], k[i], v[i]);
         }
     }
     __syncthreads();
     const uint32_t count = min(kTile, n - tile * kTile);
-    for (uint32_t j = t; j < count; j += kBlock) {
-        const K key = s_keys[j];
-        const uint32_t dd = (uint32_t)(key >> shift) & mask;
-        const uint32_t g = s_gbase[dd] + (j - s_dexcl[dd]);
-        if (kWriteKeys) kout[g] = key;
-        vout[g] = s_vals[j];
+#pragma unroll
+    for (uint32_t i = 0; i < kItems; ++i) {
+        const uint32_t j = t + i * kBlock;
+        if (j < count) {
+            K key;
+            uint32_t val;
+            s_tile.get(j, key, val);
+            const uint32_t g = s_gofs[(uint32_t)(key >> shift) & mask] + j;
+            if (kWriteKeys) kout[g] = key;
+            vout[g] = val;
+        }
     }
 }
 
@@ -335,21 +365,22 @@ __global__ __launch_bounds__(kBlock) void k_tile_sort(const K* __restrict__ kin,
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t keys_a, keys_b, vals, hist, counters, lookback, total;
+    size_t keys_a, keys_b, vals, counts, tot, total;
 };
 
+// Workspace of a global sort: two key buffers, one value buffer, the digit-major tile counts
+// of one pass (reused by every pass) and the digit totals.  Nothing in it needs clearing.
 constexpr Layout layout(uint32_t n, uint32_t key_bits, uint32_t skip = 0) {
     const size_t ks = key_bits <= 32 ? 4 : 8;
-    const uint32_t passes = (key_bits - skip + 7) / 8;
     const size_t tiles = ((size_t)n + kTile - 1) / kTile;
+    (void)skip;
     Layout L{};
     size_t off = 0;
     L.keys_a = off; off += align256((size_t)n * ks);
     L.keys_b = off; off += align256((size_t)n * ks);
     L.vals = off; off += align256((size_t)n * 4);
-    L.hist = off; off += align256((size_t)kMaxPasses * kRadix * 4);
-    L.counters = off; off += align256(kMaxPasses * 4);
-    L.lookback = off; off += align256((size_t)passes * tiles * kRadix * 4);
+    L.counts = off; off += align256(tiles * kRadix * 4);
+    L.tot = off; off += align256(kRadix * 4);
     L.total = off;
     return L;
 }
@@ -360,21 +391,14 @@ hcc_status run_sort(const K* keys, uint32_t key_bits, uint32_t skip, uint32_t n,
     const uint32_t passes = (key_bits - skip + 7) / 8;
     const Layout L = layout(n, key_bits, skip);
     const uint32_t tiles = (n + kTile - 1) / kTile;
-    uint32_t* hist = (uint32_t*)(ws + L.hist);
-    uint32_t* counters = (uint32_t*)(ws + L.counters);
-    uint32_t* lookback = (uint32_t*)(ws + L.lookback);
-    // zero histogram, counters and look-back state (hist, counters and lookback are contiguous)
-    const size_t zero_words = (L.total - L.hist) / 4;
-    k_fill_u32<<<dim3((unsigned)std::min<size_t>(1024, (zero_words + 255) / 256)), dim3(256), 0, stream>>>(
-        hist, zero_words, 0u);
-    const uint32_t hist_blocks = std::min<uint32_t>(2048u, ((n + 3) / 4 + kBlock - 1) / kBlock);
-    k_hist<K><<<dim3(hist_blocks), dim3(kBlock), 0, stream>>>(keys, n, key_bits, skip, passes, hist);
-
+    uint32_t* counts = (uint32_t*)(ws + L.counts);
+    uint32_t* tot = (uint32_t*)(ws + L.tot);
     K* final_keys = sorted_keys ? sorted_keys : (K*)(ws + L.keys_a);
     K* other_keys = (K*)(ws + L.keys_b);
     uint32_t* vals_tmp = (uint32_t*)(ws + L.vals);
     const K* kin = keys;
     const uint32_t* vin = nullptr;
+    const dim3 grid(tiles), block(kBlock);
     for (uint32_t p = 0; p < passes; ++p) {
         const bool to_final = ((passes - 1 - p) % 2) == 0;
         K* kout = to_final ? final_keys : other_keys;
@@ -382,20 +406,18 @@ hcc_status run_sort(const K* keys, uint32_t key_bits, uint32_t skip, uint32_t n,
         const bool last = p + 1 == passes;
         const uint32_t shift = skip + 8u * p;
         const uint32_t nb = std::min<uint32_t>(8u, key_bits - shift);
-        const uint32_t* h = hist + p * kRadix;
-        uint32_t* lb = lookback + (size_t)p * tiles * kRadix;
-        uint32_t* ctr = counters + p;
-        dim3 grid(tiles), block(kBlock);
+        k_count<K><<<grid, block, 0, stream>>>(kin, n, shift, nb, counts);
+        k_scan<<<dim3(kRadix), block, 0, stream>>>(counts, tiles, tot);
         if (p == 0) {
             if (last && !sorted_keys)
-                k_scatter<K, true, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, h, lb, ctr);
+                k_scatter<K, true, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, counts, tot);
             else
-                k_scatter<K, true, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, h, lb, ctr);
+                k_scatter<K, true, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, counts, tot);
         } else {
             if (last && !sorted_keys)
-                k_scatter<K, false, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, h, lb, ctr);
+                k_scatter<K, false, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, counts, tot);
             else
-                k_scatter<K, false, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, h, lb, ctr);
+                k_scatter<K, false, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, counts, tot);
         }
         kin = kout;
         vin = vout;
