@@ -399,6 +399,15 @@ def compact_line(full: dict, args, workload: str) -> dict:
     sh = full.get("shadow")
     if sh:
         line["shadow_mrays_s"] = {m: sh[m]["mrays_s"] for m in res if m in sh}
+        for base in ("nosort", "twopoint"):
+            if head in sh and base in sh and head != base:
+                line[f"shadow_speedup_vs_{base}"] = round(sh[head]["mrays_s"] / sh[base]["mrays_s"], 3)
+    pe = res.get("hcc_paper_exact")
+    if pe and pe.get("key_bits") == 32 and pe.get("skip_bits") == 0 and pe["sort_ms"] > 0:
+        # the full 32-bit sort of the frame's keys against its algorithmic bytes (68 B per key)
+        achieved = 68.0 * full["rays"] / (pe["sort_ms"] * 1e-3) / 1e9
+        line["sort32"] = dict(ms=round(pe["sort_ms"], 4), bytes_per_key=68, achieved_gbs=round(achieved, 1),
+                              frac=round(achieved / HBM_PEAK_GBS, 4))
     fm = (full.get("fetches") or {}).get("model")
     if fm:
         line["model_fetches_per_ray"] = {m: [v["node_fetches_per_ray"], v["tri_fetches_per_ray"]] for m, v in fm.items()}

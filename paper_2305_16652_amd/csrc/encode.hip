@@ -1,9 +1,11 @@
 // Sorting-key kernels for gfx950.
 //
-// HCC (Algorithm 1, Section 4.2.1): the first min(C, K) cut boxes (HAD order) are
-// copied into LDS once per block; every ray of the block's share is tested against all
-// of them and bit K-1-i records cut node i.  All lanes of a wavefront read the same box
-// at the same time, so the LDS reads are broadcasts.
+// HCC (Algorithm 1, Section 4.2.1): every ray is tested against the first min(C, K) cut
+// boxes (HAD order) and bit K-1-i records cut node i.  All lanes of a wavefront test the same
+// box at the same time, so the boxes are read with scalar loads (one 32-byte load per box and
+// wavefront, through the scalar cache, into SGPRs that the slab test reads directly).  Staged
+// in LDS instead, each box cost two 16-byte reads per lane, and at 32 boxes per ray the LDS
+// bandwidth bound the kernel.
 //
 // TwoPoint (Section 3.2; fixed-length end point of Section 5): 6-D Morton code of
 // (origin, origin + 0.25 L * d/|d|), L the largest scene extent.
@@ -15,29 +17,36 @@ namespace hcc {
 namespace {
 
 constexpr uint32_t kBlock = 256;
-constexpr uint32_t kMaxCut = 64;
+
+// Bits of the boxes box[0 .. m) met by the ray, box 0 in bit m-1 (m <= 64).  The box index is
+// the same for every lane, so the boxes come through scalar loads.
+template <typename K>
+__device__ __forceinline__ K box_bits(const CutBox* __restrict__ box, uint32_t m, float ox, float oy, float oz,
+                                      float ix, float iy, float iz, float tmin, float tmax, int* first_hit) {
+    K bits = 0;
+    int first = -1;
+#pragma unroll 4
+    for (uint32_t i = 0; i < m; ++i) {
+        const CutBox c = box[i];
+        float tn;
+        const bool hit = slab(ox, oy, oz, ix, iy, iz, tmin, tmax, c.lo.x, c.lo.y, c.lo.z, c.hi.x, c.hi.y, c.hi.z, tn);
+        bits = (bits << 1) | (K)hit;
+        if (first_hit && hit && first < 0) first = (int)i;
+    }
+    if (first_hit) *first_hit = first;
+    return bits;
+}
 
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_encode_hcc(const float4* __restrict__ rays, uint32_t n,
                                                        const CutBox* __restrict__ cut, uint32_t m,
                                                        uint32_t key_bits, K* __restrict__ keys) {
-    __shared__ CutBox s_cut[kMaxCut];
-    for (uint32_t i = threadIdx.x; i < m; i += kBlock) s_cut[i] = cut[i];
-    __syncthreads();
     for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
         const float4 a = rays[2 * (size_t)r];
         const float4 b = rays[2 * (size_t)r + 1];
         const float ix = 1.0f / b.x, iy = 1.0f / b.y, iz = 1.0f / b.z;
-        K key = 0;
-        const uint32_t top = key_bits - 1;
-        for (uint32_t i = 0; i < m; ++i) {
-            const CutBox c = s_cut[i];
-            float tn;
-            const bool hit = slab(a.x, a.y, a.z, ix, iy, iz, a.w, b.w, c.lo.x, c.lo.y, c.lo.z, c.hi.x, c.hi.y,
-                                  c.hi.z, tn);
-            key |= (K)hit << (top - i);
-        }
-        keys[r] = key;
+        // 1 <= m <= key_bits: the m box bits go to the top of the key
+        keys[r] = box_bits<K>(cut, m, a.x, a.y, a.z, ix, iy, iz, a.w, b.w, nullptr) << (key_bits - m);
     }
 }
 
@@ -88,34 +97,26 @@ __global__ __launch_bounds__(kBlock) void k_encode_twopoint(const float4* __rest
     }
 }
 
-// MLHCC (Section 4.3): the top-level boxes and every top node's low-level boxes are staged in
-// LDS (top x low <= 2048 boxes, 64 KB).  Top bits as in HCC; the first top node met is the
-// representative, whose low-level boxes give the low bits.
+// MLHCC (Section 4.3): the top-level boxes are read like HCC's cut boxes (scalar loads); every
+// top node's low-level boxes are staged in LDS (top x low <= 2048 boxes, 64 KB), since lanes
+// whose rays meet different top nodes first read different rows.  Top bits as in HCC; the
+// first top node met is the representative, whose low-level boxes give the low bits.
 constexpr uint32_t kMaxLowBoxes = 2048;
 
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_encode_mlhcc(const float4* __restrict__ rays, uint32_t n,
                                                          const CutBox* __restrict__ boxes, uint32_t t_eff,
                                                          uint32_t low, uint32_t key_bits, K* __restrict__ keys) {
-    __shared__ CutBox s_top[kMaxCut];
     __shared__ CutBox s_low[kMaxLowBoxes];
-    for (uint32_t i = threadIdx.x; i < t_eff; i += kBlock) s_top[i] = boxes[i];
     for (uint32_t i = threadIdx.x; i < t_eff * low; i += kBlock) s_low[i] = boxes[t_eff + i];
     __syncthreads();
     for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
         const float4 a = rays[2 * (size_t)r];
         const float4 b = rays[2 * (size_t)r + 1];
         const float ix = 1.0f / b.x, iy = 1.0f / b.y, iz = 1.0f / b.z;
-        K key = 0;
         int rep = -1;
-        for (uint32_t i = 0; i < t_eff; ++i) {
-            const CutBox c = s_top[i];
-            float tn;
-            const bool hit = slab(a.x, a.y, a.z, ix, iy, iz, a.w, b.w, c.lo.x, c.lo.y, c.lo.z, c.hi.x, c.hi.y,
-                                  c.hi.z, tn);
-            key |= (K)hit << (key_bits - 1 - i);
-            if (hit && rep < 0) rep = (int)i;
-        }
+        // 1 <= t_eff and t_eff + low <= key_bits
+        K key = box_bits<K>(boxes, t_eff, a.x, a.y, a.z, ix, iy, iz, a.w, b.w, &rep) << (key_bits - t_eff);
         if (rep >= 0) {
             const CutBox* lb = s_low + (uint32_t)rep * low;
             for (uint32_t j = 0; j < low; ++j) {

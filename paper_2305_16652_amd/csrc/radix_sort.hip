@@ -2,8 +2,8 @@
 //
 // Sorting the ray keys as unsigned integers and handing the trace kernel the sorted
 // ray indices is the reorder step of the method (Sections 4.2.3 and 5).  Each pass over one
-// 8-bit digit is a reduce-then-scan over tiles of kTile consecutive keys, three launches with
-// no waiting between workgroups:
+// 8-bit digit is a reduce-then-scan over tiles of consecutive keys (4,096 of 32 bits or 2,048
+// of 64 bits), three launches with no waiting between workgroups:
 //   1. k_count: each tile's digit counts (one read of the keys, every load of a thread issued
 //      at once; runs of equal digits added to LDS with one atomic), stored digit-major;
 //   2. k_scan: per digit, the exclusive scan of its counts over the tiles (in place) and the
@@ -24,8 +24,13 @@ namespace hcc {
 namespace {
 
 constexpr uint32_t kBlock = 256;          // 4 wavefronts
-constexpr uint32_t kItems = 16;           // keys per thread and tile
-constexpr uint32_t kTile = kBlock * kItems;
+// Keys per thread and tile: 16 (4,096-key tiles) for 32-bit keys; 8 (2,048-key tiles) for
+// 64-bit keys, whose LDS staging of a 4,096-key tile (48 KB) would leave room for only two
+// workgroups per CU.
+template <typename K>
+constexpr uint32_t items_of() { return sizeof(K) == 4 ? 16u : 8u; }
+template <typename K>
+constexpr uint32_t tile_of() { return kBlock * items_of<K>(); }
 constexpr uint32_t kRadix = 256;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
@@ -81,6 +86,7 @@ template <typename K>
 __global__ __launch_bounds__(kBlock) void k_count(const K* __restrict__ keys, uint32_t n, uint32_t shift,
                                                   uint32_t nbits, uint32_t* __restrict__ counts) {
     constexpr uint32_t kPerLoad = 16 / sizeof(K);
+    constexpr uint32_t kItems = items_of<K>(), kTile = tile_of<K>();
     __shared__ uint32_t s_h[4 * kRadix];
     const uint32_t t = threadIdx.x, w = t >> 6;
     const uint32_t T = gridDim.x;
@@ -108,16 +114,26 @@ __global__ __launch_bounds__(kBlock) void k_count(const K* __restrict__ keys, ui
     __syncthreads();
     uint32_t* h = s_h + w * kRadix;
     uint32_t cur = (uint32_t)(k[0] >> shift) & mask, run = nv ? 1u : 0u;
+    // a wavefront whose 64 x kItems keys all share one digit (common for coherent rays' keys)
+    // adds them with one atomic instead of 64 on the same LDS word
+    bool uniform = nv == kItems && cur == __builtin_amdgcn_readfirstlane(cur);
 #pragma unroll
-    for (uint32_t i = 1; i < kItems; ++i) {
-        if (i < nv) {
-            const uint32_t d = (uint32_t)(k[i] >> shift) & mask;
-            if (d == cur) {
-                ++run;
-            } else {
-                atomicAdd(&h[cur], run);
-                cur = d;
-                run = 1u;
+    for (uint32_t i = 1; i < kItems; ++i) uniform = uniform && ((uint32_t)(k[i] >> shift) & mask) == cur;
+    if (__ballot(uniform) == ~0ull) {
+        if ((t & 63u) == 0) atomicAdd(&h[cur], 64u * kItems);
+        run = 0;
+    } else {
+#pragma unroll
+        for (uint32_t i = 1; i < kItems; ++i) {
+            if (i < nv) {
+                const uint32_t d = (uint32_t)(k[i] >> shift) & mask;
+                if (d == cur) {
+                    ++run;
+                } else {
+                    atomicAdd(&h[cur], run);
+                    cur = d;
+                    run = 1u;
+                }
             }
         }
     }
@@ -174,14 +190,14 @@ __global__ __launch_bounds__(kBlock) void k_scan(uint32_t* __restrict__ counts, 
 // separate key and value arrays for 64-bit keys.
 template <typename K>
 struct TileStage {
-    K key[kTile];
-    uint32_t val[kTile];
+    K key[tile_of<K>()];
+    uint32_t val[tile_of<K>()];
     __device__ void put(uint32_t i, K k, uint32_t v) { key[i] = k; val[i] = v; }
     __device__ void get(uint32_t i, K& k, uint32_t& v) const { k = key[i]; v = val[i]; }
 };
 template <>
 struct TileStage<uint32_t> {
-    uint2 kv[kTile];
+    uint2 kv[tile_of<uint32_t>()];
     __device__ void put(uint32_t i, uint32_t k, uint32_t v) { kv[i] = make_uint2(k, v); }
     __device__ void get(uint32_t i, uint32_t& k, uint32_t& v) const {
         const uint2 p = kv[i];
@@ -195,6 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ kin, c
                                                     K* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
                                                     uint32_t shift, uint32_t nbits, const uint32_t* __restrict__ offs,
                                                     const uint32_t* __restrict__ tot) {
+    constexpr uint32_t kItems = items_of<K>(), kTile = tile_of<K>();
     __shared__ uint32_t s_whist[4 * kRadix];
     __shared__ uint32_t s_gofs[kRadix];
     __shared__ uint32_t s_scan[8];
@@ -372,7 +389,8 @@ struct Layout {
 // of one pass (reused by every pass) and the digit totals.  Nothing in it needs clearing.
 constexpr Layout layout(uint32_t n, uint32_t key_bits, uint32_t skip = 0) {
     const size_t ks = key_bits <= 32 ? 4 : 8;
-    const size_t tiles = ((size_t)n + kTile - 1) / kTile;
+    const size_t tile = key_bits <= 32 ? tile_of<uint32_t>() : tile_of<uint64_t>();
+    const size_t tiles = ((size_t)n + tile - 1) / tile;
     (void)skip;
     Layout L{};
     size_t off = 0;
@@ -390,7 +408,7 @@ hcc_status run_sort(const K* keys, uint32_t key_bits, uint32_t skip, uint32_t n,
                     char* ws, hipStream_t stream) {
     const uint32_t passes = (key_bits - skip + 7) / 8;
     const Layout L = layout(n, key_bits, skip);
-    const uint32_t tiles = (n + kTile - 1) / kTile;
+    const uint32_t tiles = (n + tile_of<K>() - 1) / tile_of<K>();
     uint32_t* counts = (uint32_t*)(ws + L.counts);
     uint32_t* tot = (uint32_t*)(ws + L.tot);
     K* final_keys = sorted_keys ? sorted_keys : (K*)(ws + L.keys_a);

@@ -20,6 +20,7 @@ def _method(k=32, c=32):
 
 def _full():
     methods = {m: _method() for m in ("nosort", "twopoint", "hcc", "hcc_paper_exact")}
+    methods["hcc_paper_exact"]["skip_bits"] = 0
     rows = [dict(method=f"variant number {i} with a long name", mrays_s=2500.5 + i) for i in range(8)]
     fetch = dict(node_fetches_per_ray=26.712, tri_fetches_per_ray=3.123, bytes_per_ray=1859.3, waves_modelled=32400,
                  wave_stride=8, anc64=1.234, anc32=1.111)
@@ -56,6 +57,8 @@ def test_compact_line_fields_and_size():
     assert set(line["roofline"]) >= {"bound", "achieved", "peak", "unit", "frac", "traffic"}
     assert set(line["cpu_baseline"]) >= {"value", "unit", "cores", "kind", "sample"}
     assert "hcc_paper_exact" in line["methods"] and line["paper_exact_vs_nosort"] == 1.0
+    assert line["sort32"]["bytes_per_key"] == 68 and 0 < line["sort32"]["frac"] < 1
+    assert line["shadow_speedup_vs_nosort"] == 1.0
     assert json.loads(text) == line
 
 
