@@ -146,17 +146,26 @@ __device__ __forceinline__ void signal(uint32_t* p) {
     if (__lane_id() == 0) atomicAdd(p, 1u);
 }
 
+// HCC key of one ray.  The cut's boxes stay unchanged while the engine runs and every lane of
+// the wavefront reads the same box, so they are read through the constant address space:
+// scalar loads into SGPRs (a wavefront-uniform 32-byte load per box) instead of a copy in LDS
+// that every lane reads.
+typedef const __attribute__((address_space(4))) float* ConstFloats;
+
 template <typename K>
-__device__ K hcc_key(const CutBox* s_cut, uint32_t m, uint32_t key_bits, float4 a, float4 b) {
+__device__ K hcc_key(const CutBox* cut, uint32_t m, uint32_t key_bits, float4 a, float4 b) {
+    const ConstFloats box = (ConstFloats)cut;   // CutBox i: lo.xyz at 8i, hi.xyz at 8i + 4
     const float ix = 1.0f / b.x, iy = 1.0f / b.y, iz = 1.0f / b.z;
-    K key = 0;
+    K bits = 0;
+#pragma unroll 4
     for (uint32_t i = 0; i < m; ++i) {
-        const CutBox c = s_cut[i];
+        const ConstFloats c = box + 8 * i;
         float tn;
-        const bool hit = slab(a.x, a.y, a.z, ix, iy, iz, a.w, b.w, c.lo.x, c.lo.y, c.lo.z, c.hi.x, c.hi.y, c.hi.z, tn);
-        key |= (K)hit << (key_bits - 1 - i);
+        const bool hit = slab(a.x, a.y, a.z, ix, iy, iz, a.w, b.w, c[0], c[1], c[2], c[4], c[5], c[6], tn);
+        bits = (bits << 1) | (K)hit;
     }
-    return key;
+    // 1 <= m <= key_bits: the m box bits go to the top of the key
+    return bits << (key_bits - m);
 }
 
 template <typename K>
@@ -195,11 +204,9 @@ __device__ K twopoint_key(const EngScene& sc, uint32_t key_bits, float4 a, float
 // group of equal digits.
 template <typename K>
 __device__ void encode_tile(const EngScene& sc, const EngBatch& bt, uint32_t tile, uint32_t mode, uint32_t key_bits,
-                            uint32_t passes, CutBox* s_cut, uint32_t* s_h0) {
+                            uint32_t passes, uint32_t* s_h0) {
     const uint32_t lane = __lane_id();
     for (uint32_t j = 0; j < 4; ++j) s_h0[lane * 4 + j] = 0;
-    if (mode == HCC_KEY_HCC)
-        for (uint32_t i = lane; i < sc.m; i += 64) s_cut[i] = sc.cut[i];
     __syncthreads();
     const uint64_t lt = below_mask();
     K* keys = (K*)bt.keys_a;
@@ -209,7 +216,7 @@ __device__ void encode_tile(const EngScene& sc, const EngBatch& bt, uint32_t til
         K key = 0;
         if (valid) {
             const float4 a = bt.rays[2 * (size_t)idx], b = bt.rays[2 * (size_t)idx + 1];
-            key = mode == HCC_KEY_HCC ? hcc_key<K>(s_cut, sc.m, key_bits, a, b) : twopoint_key<K>(sc, key_bits, a, b);
+            key = mode == HCC_KEY_HCC ? hcc_key<K>(sc.cut, sc.m, key_bits, a, b) : twopoint_key<K>(sc, key_bits, a, b);
             st_dev(keys + idx, key);
         }
         for (uint32_t p = 0; p < passes; ++p) {
@@ -615,7 +622,6 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
                                             uint32_t nb, uint32_t total_items, uint32_t total_tiles, uint32_t* queue,
                                             uint32_t mode, uint32_t key_bits, uint32_t passes, uint32_t refill,
                                             uint32_t slab) {
-    __shared__ CutBox s_cut[64];
     __shared__ uint32_t s_whist[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
     // the scatter's ranks and the 4-wide trace's short stacks are never live at the same time
@@ -661,7 +667,7 @@ __device__ __forceinline__ void engine_loop(const EngScene* __restrict__ scenes,
         }
         const uint32_t tile = r - bt.tile0;
         if (phase == 0) {
-            encode_tile<K>(sc, bt, tile, mode, key_bits, passes, s_cut, s_whist);
+            encode_tile<K>(sc, bt, tile, mode, key_bits, passes, s_whist);
             signal(bt.done);
         } else {
             const uint32_t p = phase - 1;
