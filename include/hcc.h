@@ -104,7 +104,7 @@ typedef struct hcc_trace_opts {
                                  w + waves, w + 2 waves, ... instead.  Results are the same
                                  either way. */
     uint32_t waves;           /* persistent: wavefronts launched (0 = 8192) */
-    uint32_t flags;           /* HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB */
+    uint32_t flags;           /* HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB | HCC_TRACE_SPREAD */
 } hcc_trace_opts;
 
 /* hcc_trace_opts.flags */
@@ -118,6 +118,10 @@ typedef struct hcc_trace_opts {
                                    direction instead (the same hit / miss decisions and distances,
                                    fewer instructions; measured faster where the nodes stay in the
                                    caches, slower on scenes far larger than them) */
+#define HCC_TRACE_SPREAD 8u     /* persistent launches taking chunks from the stream's counter: the counter
+                                   deals the chunks in 64 interleaved streams (take t -> chunk
+                                   (t mod 64) * ceil(chunks / 64) + t / 64), so the wavefronts running
+                                   together work on 64 parts of the order; same results */
 
 /* ---------------------------------------------------------------------------------------
  * hcc_build_bvh -- linear BVH over n_tris triangles (Section 3.1: the acceleration structure

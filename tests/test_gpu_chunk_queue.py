@@ -18,6 +18,8 @@ pytestmark = pytest.mark.gpu
 # (block, stack, xcd_remap, persistent, refill, chunk, waves, flags)
 WIDE = (64, 2, 0, 1, 32, 64, 0, 2)
 BVH2 = (64, 0, 0, 1, 32, 64, 0, 0)
+WIDE_SPREAD = (64, 2, 0, 1, 32, 64, 0, 2 | 8)     # chunks dealt spread over the order
+BVH2_SPREAD = (64, 0, 0, 1, 32, 64, 0, 8)
 
 
 def _say(msg):
@@ -49,7 +51,8 @@ def _opts(H, base, chunk, waves):
     return H.TraceOpts(*base[:5], chunk, waves, base[7])
 
 
-@pytest.mark.parametrize("base", [WIDE, BVH2], ids=["wide", "bvh2"])
+@pytest.mark.parametrize("base", [WIDE, BVH2, WIDE_SPREAD, BVH2_SPREAD], ids=["wide", "bvh2", "wide-spread",
+                                                                            "bvh2-spread"])
 def test_back_to_back_launches_of_changing_shape(H, tiny, base):
     sec, shd = torch.from_numpy(tiny["sec"]).cuda(), torch.from_numpy(tiny["shd"]).cuda()
     n = sec.shape[0]
@@ -66,6 +69,21 @@ def test_back_to_back_launches_of_changing_shape(H, tiny, base):
         idx = np.arange(m)      # the launch traced the first m rays
         assert_closest(hits.cpu().numpy(), tiny["ref_sec"], tiny["sec"], tiny["spec"].tris, idx=idx)
         assert_any(occ.cpu().numpy(), tiny["ref_shd"], idx=idx)
+
+
+def test_spread_and_ordered_dealing_alternate_on_one_stream(H, tiny):
+    """Spread and in-order dealing share the stream's counter: alternating them back to back
+    (chunk counts that do and do not fill the 64 interleaved streams) gives the same hits."""
+    sec = torch.from_numpy(np.tile(tiny["sec"], (3, 1))).cuda()
+    n = sec.shape[0]
+    want = H.trace(tiny["bvh"], sec, opts=H.TraceOpts(*WIDE)).cpu().numpy()
+    outs = []
+    for i, (m, chunk) in enumerate([(n, 64), (n, 64), (4096, 64), (n - 1, 128), (200, 64), (n, 256)]):
+        base = WIDE_SPREAD if i % 2 == 0 else WIDE
+        outs.append((m, H.trace(tiny["bvh"], sec[:m], opts=_opts(H, base, chunk, 0))))
+    torch.cuda.synchronize()
+    for m, out in outs:
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), want[:m].view(np.uint32)), m
 
 
 def test_overlapping_launches_on_two_streams(H, tiny):

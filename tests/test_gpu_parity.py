@@ -189,7 +189,9 @@ OPTS = [(128, 1, 0, 0, 0, 0, 0), (64, 1, 1, 0, 0, 0, 0), (256, 1, 0, 0, 0, 0, 0)
         # XCD-contiguous chunk order for the persistent and 4-wide kernels
         (0, 2, 1, 1, 32, 64, 0, 2), (0, 0, 1, 1, 16, 256, 13, 1),
         # 4-wide with every child box through the slab test (flags bit 2)
-        (0, 2, 0, 1, 32, 64, 0, 6), (0, 0, 1, 1, 16, 256, 9, 6), (0, 1, 0, 1, 1, 64, 3, 6)]
+        (0, 2, 0, 1, 32, 64, 0, 6), (0, 0, 1, 1, 16, 256, 9, 6), (0, 1, 0, 1, 1, 64, 3, 6),
+        # chunks dealt spread over the order (flags bit 3), BVH2 and 4-wide
+        (0, 2, 0, 1, 32, 64, 0, 8 | 2), (0, 0, 0, 1, 16, 256, 5, 8 | 1)]
 WIDE = (0, 0, 0, 1, 32, 64, 0, 2)
 
 
@@ -348,7 +350,7 @@ def test_invalid_arguments(H, gpu_bvh):
     with pytest.raises(H.HCCError):
         H.trace(gpu_bvh, rays, opts=H.TraceOpts(64, 7, 0, 0, 0, 0, 0, 0))
     with pytest.raises(H.HCCError):
-        H.trace(gpu_bvh, rays, opts=H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 8))      # unknown flag bit
+        H.trace(gpu_bvh, rays, opts=H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 16))     # unknown flag bit
     other = H.build_bvh(torch.tensor([[0, 0, 0, 1, 0, 0, 0, 1, 0]], dtype=torch.float32, device="cuda"))
     with pytest.raises(H.HCCError):
         H.encode(gpu_bvh, H.select_cut(other, 1), H.KEY_HCC, 32, rays)   # cut from another BVH
