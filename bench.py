@@ -784,11 +784,12 @@ def run_method_grid(H, bvh, rays, opts, reps):
 
 def run_bounces(H, args, bvh, tris_h, sec, rays):
     """Bounces 2 and 3 of the frame workload: diffuse rays spawned at the previous bounce's
-    closest hits (origins now scattered over the scene, directions random).  Per bounce: trace
-    options tuned on its NoSort order; NoSort; TwoPoint and HCC (C = K) with key length and
-    skipped bits tuned on the bounce's own rays (at least half of the key sorted); and the
-    untuned rows HCC C = K = 32 and 64, MLHCC16 (8+8) and MLHCC32 (16+16), TwoPoint K = 32,
-    each with a full sort.  Node / triangle fetches per ray are the one-ray-per-lane kernel's
+    closest hits (origins now scattered over the scene, directions random).  Per bounce: NoSort
+    with trace options tuned on its own order; TwoPoint and HCC (C = K) with key length, skipped
+    bits and trace options tuned on the bounce's own rays in their own orders (at least half of
+    the key sorted); and the untuned rows HCC C = K = 32 and 64, MLHCC16 (8+8) and MLHCC32
+    (16+16), TwoPoint K = 32, each with a full sort and the trace options of its method's tuned
+    row.  Node / triangle fetches per ray are the one-ray-per-lane kernel's
     wavefront counts (equal to the oracle's wave model, see the tests)."""
     import torch
     import workloads as W
@@ -803,10 +804,11 @@ def run_bounces(H, args, bvh, tris_h, sec, rays):
                                  bounce=bounce - 1)
         rd = torch.from_numpy(nxt).to(rays.device)
         opts = AT.tune_trace(bvh, rd, None, candidates=AT.WIDE)[0]
-        tw, _ = AT.tune_reorder(bvh, rd, "twopoint", key_bits=(16, 32), skips=sk, candidates=[opts],
+        tw, _ = AT.tune_reorder(bvh, rd, "twopoint", key_bits=(16, 32), skips=sk, candidates=AT.WIDE,
                                 min_sorted_frac=args.min_sorted_frac)
         hc, _ = AT.tune_reorder(bvh, rd, "hcc", cuts=(16, 32), key_bits=(16, 32), skips=sk, paper_exact=True,
-                                candidates=[opts], min_sorted_frac=args.min_sorted_frac)
+                                candidates=AT.WIDE, min_sorted_frac=args.min_sorted_frac)
+        method_opts = {"nosort": opts, "twopoint": tw.opts, "hcc": hc.opts, "mlhcc": hc.opts}
         variants = [dict(mode="nosort"), dict(mode="twopoint", K=tw.key_bits, skip=tw.skip),
                     dict(mode="hcc", C=hc.cut, K=hc.key_bits, skip=hc.skip),
                     dict(mode="hcc", C=32, K=32), dict(mode="hcc", C=64, K=64),
@@ -818,8 +820,9 @@ def run_bounces(H, args, bvh, tris_h, sec, rays):
             if name in seen:
                 continue
             seen.add(name)
-            rows.append(measure_variant(H, bvh, rd, v, opts, args.grid_reps))
-        out[str(bounce)] = dict(rays=int(rd.shape[0]), trace_opts=AT.opts_dict(opts), rows=rows)
+            rows.append(measure_variant(H, bvh, rd, v, method_opts[v["mode"]], args.grid_reps))
+        out[str(bounce)] = dict(rays=int(rd.shape[0]), trace_opts={m: AT.opts_dict(o) for m, o in method_opts.items()},
+                                rows=rows)
         log(f"frame bounce {bounce} ({rd.shape[0]} rays, {time.time() - t0:.1f}s): " +
             "; ".join(f"{r['method']} {r['mrays_s']:.0f} Mrays/s (trace {r['trace_ms']:.2f} ms, "
                       f"{r['node_fetches_per_ray']:.1f} nf/ray)" for r in rows))
@@ -854,13 +857,18 @@ def run_drift(H, args):
         t, prim = h[:, 0].copy(), h[:, 1].copy().view(np.uint32)
         rays, _ = W.spawn_diffuse(rays, t, prim, spec.tris, seed=92, bounce=bounce - 1)
         rd = torch.from_numpy(rays).to(dev)
-        # one set of 4-wide trace options per bounce, tuned on the unsorted rays
+        # 4-wide trace options per bounce: tuned on the unsorted rays for NoSort, and on one
+        # sorted order (TwoPoint, K = 32, full sort) for every reordered row
         opts = AT.tune_trace(bvh, rd, None, candidates=AT.WIDE)[0]
+        tkeys = H.encode(bvh, None, H.KEY_TWOPOINT, 32, rd)
+        sorted_opts = AT.tune_trace(bvh, rd, H.sort(tkeys, 32), candidates=AT.WIDE)[0]
+        del tkeys
         rows = [measure_variant(H, bvh, rd, dict(mode="nosort"), opts, args.drift_reps)]
         for k in ks:
             for v in (dict(mode="twopoint", K=k), dict(mode="hcc", C=k, K=k), dict(mode="grid", K=k)):
-                rows.append(measure_variant(H, bvh, rd, v, opts, args.drift_reps))
-        out["bounces"][str(bounce)] = dict(rays=int(rd.shape[0]), rows=rows, trace_opts=AT.opts_dict(opts))
+                rows.append(measure_variant(H, bvh, rd, v, sorted_opts, args.drift_reps))
+        out["bounces"][str(bounce)] = dict(rays=int(rd.shape[0]), rows=rows, trace_opts=AT.opts_dict(opts),
+                                           sorted_trace_opts=AT.opts_dict(sorted_opts))
         log(f"drift bounce {bounce} ({rd.shape[0]} rays): " +
             "; ".join(f"{r['method']} {r['mrays_s']:.0f} Mrays/s {r['node_fetches_per_ray']:.1f} nf/ray "
                       f"anc32 {r.get('anc32', 0):.2f}" for r in rows))
