@@ -42,7 +42,10 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    # roctx ranges of the entry points (ROCm's rocprofiler-sdk-roctx)
+    rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, f"-L{rocm_lib}",
+           "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{rocm_lib}"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

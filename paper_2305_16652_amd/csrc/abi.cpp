@@ -248,6 +248,7 @@ __attribute__((visibility("default"))) const char* hcc_version(void) { return "h
 
 __attribute__((visibility("default"))) hcc_status hcc_build_bvh(const float* d_tris, uint32_t n_tris,
                                                                 hcc_stream stream, hcc_bvh* out) {
+    hcc::Range range("hcc_build_bvh");
     if (!d_tris || !out) return fail(HCC_ERR_INVALID, "hcc_build_bvh: null pointer");
     if (n_tris == 0 || n_tris > (1u << 28)) return fail(HCC_ERR_INVALID, "hcc_build_bvh: n_tris must be in [1, 2^28]");
     hcc_bvh_s* b = nullptr;
@@ -285,6 +286,7 @@ __attribute__((visibility("default"))) void hcc_bvh_destroy(hcc_bvh bvh) {
 
 __attribute__((visibility("default"))) hcc_status hcc_select_cut(hcc_bvh bvh, uint32_t cut_size, double lambda,
                                                                  hcc_stream stream, hcc_cut* out) {
+    hcc::Range range("hcc_select_cut");
     if (!valid_bvh(bvh) || !out) return fail(HCC_ERR_INVALID, "hcc_select_cut: invalid handle or null out");
     if (cut_size == 0 || cut_size > (1u << 20)) return fail(HCC_ERR_INVALID, "hcc_select_cut: cut_size must be in [1, 2^20]");
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(HCC_ERR_INVALID, "hcc_select_cut: lambda must be finite and >= 0");
@@ -337,6 +339,7 @@ __attribute__((visibility("default"))) void hcc_cut_destroy(hcc_cut cut) {
 __attribute__((visibility("default"))) hcc_status hcc_encode(hcc_bvh bvh, hcc_cut cut, hcc_key_mode mode,
                                                              uint32_t key_bits, const hcc_ray* d_rays, uint32_t n,
                                                              void* d_keys, hcc_stream stream) {
+    hcc::Range range("hcc_encode");
     if (!valid_bvh(bvh)) return fail(HCC_ERR_INVALID, "hcc_encode: invalid bvh handle");
     if (key_bits < 1 || key_bits > 64) return fail(HCC_ERR_INVALID, "hcc_encode: key_bits must be in [1, 64]");
     if (n == 0) return HCC_OK;
@@ -373,6 +376,7 @@ __attribute__((visibility("default"))) hcc_status hcc_sort_workspace(uint32_t n,
 __attribute__((visibility("default"))) hcc_status hcc_sort(const void* d_keys, uint32_t key_bits, uint32_t n,
                                                            uint32_t* d_perm, void* d_sorted_keys, void* d_ws,
                                                            size_t ws_bytes, hcc_stream stream) {
+    hcc::Range range("hcc_sort");
     return radix_sort(d_keys, key_bits, n, d_perm, d_sorted_keys, nullptr, d_ws, ws_bytes, S(stream));
 }
 
@@ -392,6 +396,7 @@ __attribute__((visibility("default"))) hcc_status hcc_sort_ex(const void* d_keys
                                                               uint32_t skip_bits, uint32_t tile, uint32_t n,
                                                               uint32_t* d_perm, void* d_sorted_keys, void* d_ws,
                                                               size_t ws_bytes, hcc_stream stream) {
+    hcc::Range range("hcc_sort_ex");
     return radix_sort_ex(d_keys, key_bits, skip_bits, tile, n, d_perm, d_sorted_keys, d_ws, ws_bytes, S(stream));
 }
 
@@ -410,6 +415,7 @@ __attribute__((visibility("default"))) hcc_status hcc_trace_ex(hcc_bvh bvh, cons
                                                                const uint32_t* d_perm, uint32_t n, hcc_trace_mode mode,
                                                                hcc_hit* d_hits, uint8_t* d_occluded,
                                                                const hcc_trace_opts* opts, hcc_stream stream) {
+    hcc::Range range("hcc_trace_ex");
     hcc_status st = check_trace(bvh, d_rays, n, mode, d_hits, d_occluded);
     if (st != HCC_OK || n == 0) return st;
     hcc_trace_opts o{};
@@ -424,6 +430,7 @@ __attribute__((visibility("default"))) hcc_status hcc_trace_count(hcc_bvh bvh, c
                                                                   hcc_trace_mode mode, hcc_hit* d_hits,
                                                                   uint8_t* d_occluded, const hcc_trace_opts* opts,
                                                                   uint64_t* d_counts, hcc_stream stream) {
+    hcc::Range range("hcc_trace_count");
     hcc_status st = check_trace(bvh, d_rays, n, mode, d_hits, d_occluded);
     if (st != HCC_OK || n == 0) return st;
     if (!d_counts) return fail(HCC_ERR_INVALID, "hcc_trace_count: null d_counts");
@@ -438,6 +445,7 @@ __attribute__((visibility("default"))) hcc_status hcc_trace_count(hcc_bvh bvh, c
 __attribute__((visibility("default"))) hcc_status hcc_trace(hcc_bvh bvh, const hcc_ray* d_rays, const uint32_t* d_perm,
                                                             uint32_t n, hcc_trace_mode mode, hcc_hit* d_hits,
                                                             uint8_t* d_occluded, hcc_stream stream) {
+    hcc::Range range("hcc_trace");
     return hcc_trace_ex(bvh, d_rays, d_perm, n, mode, d_hits, d_occluded, nullptr, stream);
 }
 
@@ -447,6 +455,7 @@ __attribute__((visibility("default"))) hcc_status hcc_trace_stats(hcc_bvh bvh, c
                                                                   uint8_t* d_occluded, uint32_t* d_nodes,
                                                                   uint32_t* d_tris, uint32_t* d_wave_nodes,
                                                                   uint32_t* d_wave_tris, hcc_stream stream) {
+    hcc::Range range("hcc_trace_stats");
     hcc_status st = check_trace(bvh, d_rays, n, mode, d_hits, d_occluded);
     if (st != HCC_OK || n == 0) return st;
     if (!d_wave_nodes || !d_wave_tris)
@@ -497,6 +506,7 @@ __attribute__((visibility("default"))) hcc_status hcc_batch_run(const hcc_batch_
                                                                 hcc_key_mode mode, uint32_t key_bits,
                                                                 const hcc_batch_opts* opts, void* d_ws,
                                                                 size_t ws_bytes, hcc_stream stream) {
+    hcc::Range range("hcc_batch_run");
     hcc_status st = check_batches(batches, nb, mode, key_bits);
     if (st != HCC_OK) return st;
     if (!d_ws || ((uintptr_t)d_ws & 255u)) return fail(HCC_ERR_INVALID, "hcc_batch_run: workspace must be 256-byte aligned");
@@ -536,6 +546,7 @@ __attribute__((visibility("default"))) hcc_status hcc_batch_check(const void* d_
 __attribute__((visibility("default"))) hcc_status hcc_select_mlhcc_cut(hcc_bvh bvh, uint32_t top, uint32_t low,
                                                                        double lambda, hcc_stream stream,
                                                                        hcc_cut* out) {
+    hcc::Range range("hcc_select_mlhcc_cut");
     if (!valid_bvh(bvh) || !out) return fail(HCC_ERR_INVALID, "hcc_select_mlhcc_cut: invalid handle or null out");
     if (top == 0 || low == 0 || top > 64 || low > 64 || top * low > 2048)
         return fail(HCC_ERR_INVALID, "hcc_select_mlhcc_cut: need 1 <= top, low <= 64 and top * low <= 2048");
@@ -572,6 +583,7 @@ __attribute__((visibility("default"))) hcc_status hcc_select_mlhcc_cut(hcc_bvh b
 
 __attribute__((visibility("default"))) hcc_status hcc_grid_cut(hcc_bvh bvh, uint32_t gx, uint32_t gy, uint32_t gz,
                                                                hcc_stream stream, hcc_cut* out) {
+    hcc::Range range("hcc_grid_cut");
     if (!valid_bvh(bvh) || !out) return fail(HCC_ERR_INVALID, "hcc_grid_cut: invalid handle or null out");
     if (gx == 0 || gy == 0 || gz == 0 || (uint64_t)gx * gy * gz > 64)
         return fail(HCC_ERR_INVALID, "hcc_grid_cut: need 1 <= gx*gy*gz <= 64");

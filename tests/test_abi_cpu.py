@@ -72,3 +72,12 @@ def test_set_allocator_validation(H):
         H.set_allocator(alloc=lambda n, s: 0)
     H.set_allocator(lambda n, s: 0, lambda p, s: None)
     H.set_allocator()
+
+
+def test_entry_points_open_roctx_ranges(H):
+    """The library imports ROCm's roctx range calls (rocprofv3 --marker-trace shows each entry
+    point's host call) and its entry points still run their argument checks without a device."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", H.LIB_PATH], capture_output=True, text=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out
+    assert H.lib.hcc_encode(C.c_void_p(0), C.c_void_p(0), 1, 32, None, 10, None, None) == 1
