@@ -414,6 +414,23 @@ def compact_line(full: dict, args, workload: str) -> dict:
     b = full.get("frame_bounces")
     if b:
         line["bounces_mrays_s"] = {k: {r["method"]: r["mrays_s"] for r in v["rows"]} for k, v in b.items()}
+        # the frame's three diffuse bounces together (the paper-shaped frame traces three), each
+        # method in its tuned configuration of each bounce: all secondary rays / all step time
+        agg = {}
+        for m in ("nosort", "twopoint", "hcc"):
+            if m not in res:
+                continue
+            rays, ms = float(full["rays"]), res[m]["ms_per_step"]
+            for v in b.values():
+                tuned = [r for r in v["rows"] if r.get("tuned") and r["method"].split(" ")[0] == m]
+                if not tuned:
+                    break
+                rays += v["rays"]
+                ms += tuned[0]["ms"]
+            else:
+                agg[m] = round(rays / (ms * 1e-3) / 1e6, 1)
+        if agg:
+            line["frame_3_bounces_mrays_s"] = agg
     bt = full.get("batched")
     if bt:
         line["batched_mrays_s"] = {k.replace("_mrays_s", ""): bt[k] for k in (
@@ -820,7 +837,10 @@ def run_bounces(H, args, bvh, tris_h, sec, rays):
             if name in seen:
                 continue
             seen.add(name)
-            rows.append(measure_variant(H, bvh, rd, v, method_opts[v["mode"]], args.grid_reps))
+            row = measure_variant(H, bvh, rd, v, method_opts[v["mode"]], args.grid_reps)
+            # the tuned configuration of each method (NoSort, and the first TwoPoint and HCC rows)
+            row["tuned"] = v is variants[0] or v is variants[1] or v is variants[2]
+            rows.append(row)
         out[str(bounce)] = dict(rays=int(rd.shape[0]), trace_opts={m: AT.opts_dict(o) for m, o in method_opts.items()},
                                 rows=rows)
         log(f"frame bounce {bounce} ({rd.shape[0]} rays, {time.time() - t0:.1f}s): " +

@@ -22,6 +22,9 @@ def _full():
     methods = {m: _method() for m in ("nosort", "twopoint", "hcc", "hcc_paper_exact")}
     methods["hcc_paper_exact"]["skip_bits"] = 0
     rows = [dict(method=f"variant number {i} with a long name", mrays_s=2500.5 + i) for i in range(8)]
+    brows = ([dict(method="nosort", mrays_s=2500.0, ms=6.4, tuned=True),
+              dict(method="twopoint K=32", mrays_s=2600.0, ms=6.2, tuned=True),
+              dict(method="hcc C=16 K=16 skip 8", mrays_s=2400.0, ms=6.7, tuned=True)] + rows)
     fetch = dict(node_fetches_per_ray=26.712, tri_fetches_per_ray=3.123, bytes_per_ray=1859.3, waves_modelled=32400,
                  wave_stride=8, anc64=1.234, anc32=1.111)
     return {
@@ -30,7 +33,7 @@ def _full():
         "cut_composition": dict(sorted_nodes=32, leaves=3, distinct_boxes=30),
         "shadow": dict(rays=33177600, **{m: dict(ms=7.9, mrays_s=4158.12) for m in methods}),
         "fetches": dict(model={m: fetch for m in methods}, kernel_counted=None),
-        "frame_bounces": {b: dict(rows=rows) for b in ("2", "3")},
+        "frame_bounces": {b: dict(rays=16588000, rows=brows) for b in ("2", "3")},
         "batched": dict(engine_hcc_mrays_s=1122.5, plain_hcc_mrays_s=353.5, engine_nosort_mrays_s=1138.0,
                         plain_nosort_mrays_s=402.1, tuning=[dict(ms=1.0)] * 50),
         "serve": dict(loads={rho: dict(plain=dict(p50_ms=22.639, p99_ms=75.06, mrays_s=420.0),
@@ -59,6 +62,9 @@ def test_compact_line_fields_and_size():
     assert "hcc_paper_exact" in line["methods"] and line["paper_exact_vs_nosort"] == 1.0
     assert line["sort32"]["bytes_per_key"] == 68 and 0 < line["sort32"]["frac"] < 1
     assert line["shadow_speedup_vs_nosort"] == 1.0
+    # three bounces: (16588800 + 2 x 16588000) rays over 5.55555 + 6.4 + 6.4 ms for NoSort
+    assert abs(line["frame_3_bounces_mrays_s"]["nosort"] - 49764800 / 18.35555e-3 / 1e6) < 0.1
+    assert set(line["frame_3_bounces_mrays_s"]) == {"nosort", "twopoint", "hcc"}
     assert json.loads(text) == line
 
 
