@@ -375,8 +375,8 @@ def _np_slab(ray, box):
     """Independent float32 slab test in numpy (fmin/fmax ignore NaN like minNum/maxNum)."""
     f = np.float32
     o = ray[0:3].astype(f)
-    inv = (f(1.0) / ray[4:7].astype(f)).astype(f)
     with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+        inv = (f(1.0) / ray[4:7].astype(f)).astype(f)
         t0 = ((box[0:3].astype(f) - o) * inv).astype(f)
         t1 = ((box[3:6].astype(f) - o) * inv).astype(f)
     tn = np.fmin(t0, t1)

@@ -3,9 +3,13 @@ regular-grid control encoding (Section 5)."""
 import numpy as np
 import pytest
 
+import os
+
 import oracle as O
 import workloads as W
 from test_oracle import _four_triangles, leaves_under, random_rays
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def test_mlhcc_cut_hand_example():
@@ -38,6 +42,49 @@ def test_mlhcc_key_hand_example():
     keys = O.encode_mlhcc(rays, tb, lb, 2, 4)
     assert keys.tolist() == [0b1010, 0b0101, 0, 0b1000]
 
+
+def _golden_rows(name):
+    return [l.split() for l in open(os.path.join(GOLDEN, name)) if l[0] != "#"]
+
+
+def test_mlhcc_caption_codes():
+    """The codes printed for the MLHCC figure (Section 4.3), rebuilt from the cut nodes each ray
+    passes.  The figure itself is not in the text, so its geometry is laid out here: eight top
+    boxes side by side along x, each split into eight low boxes along x; a box is passed by a ray
+    running along x when its y range holds the ray's y.  The low boxes of the top nodes the rays
+    pass but that are not their representatives get other patterns, so a wrong choice of
+    representative (the last node passed, say), swapped halves or a reversed bit order all change
+    a code.  The caption names top node 3 as Ray1's representative while the text takes the
+    first top node passed in HAD order (node 1 here); nodes 1 and 3 share a pattern, so the
+    printed codes hold under either reading."""
+    rows = _golden_rows("mlhcc_caption_codes.txt")
+    assert len(rows) == 2
+    bands = [(0.0, 1.0), (1.2, 2.0)]               # y band of Ray1, of Ray2
+    nowhere = (5.0, 6.0)
+    band_of = {}
+    low_pattern = {t: "11111111" for t in range(8)}
+    for r, (name, code, tops, lows) in enumerate(rows):
+        met = [int(x) for x in tops.split(",")]
+        for t in met:
+            band_of[t] = bands[r]
+        rep = met[0]
+        low_pattern[rep] = "".join("1" if i in {int(x) for x in lows.split(",")} else "0" for i in range(8))
+    low_pattern[3] = low_pattern[1]                # the caption's representative for Ray1
+    low_pattern[4], low_pattern[5], low_pattern[7] = "10000001", "11110000", "11000000"
+    tb, lb = [], []
+    for t in range(8):
+        y0, y1 = band_of.get(t, nowhere)
+        tb.append([t, y0, 0, t + 1, y1, 1])
+        for k in range(8):
+            ly0, ly1 = (y0, y1) if low_pattern[t][k] == "1" and t in band_of else nowhere
+            lb.append([t + k / 8, ly0, 0, t + (k + 1) / 8, ly1, 1])
+    rays = np.array([[-1, 0.5, 0.5, 0, 1, 0, 0, np.inf],
+                     [-1, 1.5, 0.5, 0, 1, 0, 0, np.inf]], np.float32)
+    keys = O.encode_mlhcc(rays, np.asarray(tb, np.float32), np.asarray(lb, np.float32), 8, 16)
+    assert [format(int(k), "016b") for k in keys] == [row[1] for row in rows]
+    # the top half alone is the hierarchy cut code of the top boxes
+    top_only = O.encode_hcc(rays, np.asarray(tb, np.float32), 8)
+    assert [int(k) for k in top_only] == [int(row[1], 2) >> 8 for row in rows]
 
 @pytest.mark.parametrize("top,low", [(8, 8), (16, 16), (4, 32), (30, 2)])
 def test_mlhcc_cut_invariants(top, low):
@@ -151,6 +198,27 @@ def test_ppc_hand_example():
     one = O.build_bvh(_four_triangles()[:1])
     assert O.encode_ppc(one, rays[:3], 5).tolist() == [0b10000, 0, 0]
 
+
+
+def test_ppc_caption_code():
+    """The 4-bit prefix path code printed for the PPC figure (Section 4.1): tests true, true,
+    false, false give 1100.  Scene: the four corner triangles of the unit square, tilted so that
+    their boxes have depth; the root's children are the left column (triangles 0, 2) and the right
+    column (1, 3).  A ray along x at mid height passes both columns' boxes but neither triangle of
+    the left column, so the walk tests: left column (1), right column (1), then, expanding the left
+    column, its two triangles (0, 0).  Testing the root as well, a breadth-first walk past four
+    bits, or the bits reversed would each give another code."""
+    (bits, code, seq), = _golden_rows("ppc_caption_code.txt")
+    a = 0.125
+    tris = np.asarray([[x, y, 0, x + a, y, a, x, y + a, a]
+                       for (x, y) in [(0, 0), (0.875, 0), (0, 0.875), (0.875, 0.875)]], np.float32)
+    bvh = O.build_bvh(tris)
+    assert list(bvh.leaf_prim) == [0, 2, 1, 3] and bvh.child.tolist() == [[1, 2], [3, 4], [5, 6]]
+    ray = np.array([[-1, 0.5, a / 2, 0, 1, 0, 0, np.inf]], np.float32)
+    assert format(int(O.encode_ppc(bvh, ray, int(bits))[0]), "0%sb" % bits) == code
+    assert [int(x) for x in seq.split(",")] == [int(c) for c in code]
+    # the walk goes on into the right column, whose two triangles the ray also misses
+    assert format(int(O.encode_ppc(bvh, ray, 6)[0]), "06b") == "110000"
 
 @pytest.mark.parametrize("key_bits", [1, 7, 16, 32, 64])
 def test_ppc_matches_recursive_walk(key_bits):
