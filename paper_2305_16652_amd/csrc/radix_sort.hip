@@ -12,6 +12,9 @@
 //      digit are found from one ballot per digit bit; their count below a lane is its stable
 //      rank), reorders (key, value) pairs in LDS so that equal digits are consecutive, and
 //      writes them at (keys of smaller digits) + (this digit in earlier tiles) + rank.
+// Once the key bits still to be ordered fit beside the element index in 32 bits, a pass writes
+// packed words ((remaining key bits) << index bits | index) and the passes after it move those
+// 4-byte words instead of a key and a value (when the sorted keys are not asked for).
 // Tiles are dealt to the eight XCDs in contiguous ranges (the hardware deals workgroups round
 // robin): the runs that consecutive tiles write for one digit are adjacent, and when the
 // tiles sit on one XCD its L2 merges them into whole lines before they reach HBM.
@@ -186,9 +189,16 @@ __global__ __launch_bounds__(kBlock) void k_scan(uint32_t* __restrict__ counts, 
     if (t == 0) tot[d] = carry;
 }
 
-// LDS staging of a tile's reordered pairs: one 8-byte record per pair for 32-bit keys,
-// separate key and value arrays for 64-bit keys.
-template <typename K>
+// What a pass reads besides its keys, and what it writes.  Once the key bits a sort still has
+// to order fit beside the ray index in 32 bits, a pass writes one packed word per element,
+// (key >> consumed bits) << index bits | index, and the later passes read and move that word
+// alone: 4 bytes per element instead of a key and a value.
+enum : int { kInIota = 0, kInVals = 1, kInPacked = 2 };
+enum : int { kOutKeysVals = 0, kOutVals = 1, kOutPacked = 2 };
+
+// LDS staging of a tile's reordered elements: one 8-byte record per (32-bit key, value) pair,
+// separate key and value arrays for 64-bit keys, the word alone for packed words.
+template <typename K, bool kWordOnly>
 struct TileStage {
     K key[tile_of<K>()];
     uint32_t val[tile_of<K>()];
@@ -196,7 +206,7 @@ struct TileStage {
     __device__ void get(uint32_t i, K& k, uint32_t& v) const { k = key[i]; v = val[i]; }
 };
 template <>
-struct TileStage<uint32_t> {
+struct TileStage<uint32_t, false> {
     uint2 kv[tile_of<uint32_t>()];
     __device__ void put(uint32_t i, uint32_t k, uint32_t v) { kv[i] = make_uint2(k, v); }
     __device__ void get(uint32_t i, uint32_t& k, uint32_t& v) const {
@@ -205,21 +215,34 @@ struct TileStage<uint32_t> {
         v = p.y;
     }
 };
+template <>
+struct TileStage<uint32_t, true> {
+    uint32_t w[tile_of<uint32_t>()];
+    __device__ void put(uint32_t i, uint32_t k, uint32_t) { w[i] = k; }
+    __device__ void get(uint32_t i, uint32_t& k, uint32_t& v) const { k = w[i]; v = 0u; }
+};
 
-template <typename K, bool kIota, bool kWriteKeys>
+// One pass: digit (kin >> shift) & (2^nbits - 1).  Packed input: the value is the word's low
+// ib bits.  Packed output: (key part >> pshift) << ib | value, where the key part is the key
+// or, for packed input, the word without its index bits.
+template <typename K, int kIn, int kOut>
 __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                    K* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
-                                                    uint32_t shift, uint32_t nbits, const uint32_t* __restrict__ offs,
+                                                    void* __restrict__ kout_, uint32_t* __restrict__ vout, uint32_t n,
+                                                    uint32_t shift, uint32_t nbits, uint32_t ib, uint32_t pshift,
+                                                    const uint32_t* __restrict__ offs,
                                                     const uint32_t* __restrict__ tot) {
     constexpr uint32_t kItems = items_of<K>(), kTile = tile_of<K>();
+    constexpr bool kPackedIn = kIn == kInPacked;
+    static_assert(!kPackedIn || sizeof(K) == 4, "packed words are 32-bit");
     __shared__ uint32_t s_whist[4 * kRadix];
     __shared__ uint32_t s_gofs[kRadix];
     __shared__ uint32_t s_scan[8];
-    __shared__ TileStage<K> s_tile;
+    __shared__ TileStage<K, kPackedIn> s_tile;
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
     const uint32_t T = gridDim.x;
     const uint32_t tile = xcd_block(blockIdx.x, T);
     const uint32_t mask = (1u << nbits) - 1u;
+    const uint32_t imask = ib >= 32 ? ~0u : (1u << ib) - 1u;
     for (uint32_t i = t; i < 4 * kRadix; i += kBlock) s_whist[i] = 0;
     const uint32_t base = tile * kTile + w * (64u * kItems) + lane;
     const uint64_t lt = lanemask_lt();
@@ -233,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ kin, c
         for (uint32_t i = 0; i < kItems; ++i) {
             const uint32_t idx = base + i * 64u;
             k[i] = kin[idx];
-            v[i] = kIota ? idx : vin[idx];
+            v[i] = kIn == kInIota ? idx : (kIn == kInVals ? vin[idx] : 0u);
         }
     } else {
 #pragma unroll
@@ -241,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ kin, c
             const uint32_t idx = base + i * 64u;
             const bool valid = idx < n;
             k[i] = valid ? kin[idx] : K(0);
-            v[i] = kIota ? idx : (valid ? vin[idx] : 0u);
+            v[i] = kIn == kInIota ? idx : ((kIn == kInVals && valid) ? vin[idx] : 0u);
         }
     }
     // the tile's global offsets do not depend on its keys: read them while the keys load
@@ -294,9 +317,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ kin, c
             K key;
             uint32_t val;
             s_tile.get(j, key, val);
+            if (kPackedIn) val = (uint32_t)key & imask;
             const uint32_t g = s_gofs[(uint32_t)(key >> shift) & mask] + j;
-            if (kWriteKeys) kout[g] = key;
-            vout[g] = val;
+            if (kOut == kOutKeysVals) ((K*)kout_)[g] = key;
+            if (kOut == kOutPacked) {
+                const K part = kPackedIn ? (K)(key >> ib) : key;
+                ((uint32_t*)kout_)[g] = ((uint32_t)(part >> pshift) << ib) | val;
+            }
+            if (kOut != kOutPacked) vout[g] = val;
         }
     }
 }
@@ -403,39 +431,84 @@ constexpr Layout layout(uint32_t n, uint32_t key_bits, uint32_t skip = 0) {
     return L;
 }
 
+// Launches one pass's scatter for the input / output forms chosen by run_sort.
+template <typename K>
+void scatter_pass(int in, int out, uint32_t tiles, const K* kin, const uint32_t* vin, void* kout, uint32_t* vout,
+                  uint32_t n, uint32_t shift, uint32_t nb, uint32_t ib, uint32_t pshift, const uint32_t* counts,
+                  const uint32_t* tot, hipStream_t stream) {
+    const dim3 grid(tiles), block(kBlock);
+#define HCC_SCATTER(I, O) \
+    k_scatter<K, I, O><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, ib, pshift, counts, tot)
+    if (in == kInIota) {
+        if (out == kOutKeysVals) HCC_SCATTER(kInIota, kOutKeysVals);
+        else if (out == kOutVals) HCC_SCATTER(kInIota, kOutVals);
+        else HCC_SCATTER(kInIota, kOutPacked);
+    } else {
+        if (out == kOutKeysVals) HCC_SCATTER(kInVals, kOutKeysVals);
+        else if (out == kOutVals) HCC_SCATTER(kInVals, kOutVals);
+        else HCC_SCATTER(kInVals, kOutPacked);
+    }
+#undef HCC_SCATTER
+}
+
+void scatter_packed(int out, uint32_t tiles, const uint32_t* kin, void* kout, uint32_t* vout, uint32_t n,
+                    uint32_t shift, uint32_t nb, uint32_t ib, const uint32_t* counts, const uint32_t* tot,
+                    hipStream_t stream) {
+    const dim3 grid(tiles), block(kBlock);
+    if (out == kOutVals)
+        k_scatter<uint32_t, kInPacked, kOutVals><<<grid, block, 0, stream>>>(kin, nullptr, kout, vout, n, shift, nb,
+                                                                          ib, 0u, counts, tot);
+    else
+        k_scatter<uint32_t, kInPacked, kOutPacked><<<grid, block, 0, stream>>>(kin, nullptr, kout, vout, n, shift,
+                                                                            nb, ib, 0u, counts, tot);
+}
+
+// Passes over the digits [skip, key_bits), lowest first.  Without sorted keys out, the first
+// pass whose remaining key bits fit beside the index in 32 bits writes packed words, and the
+// passes after it sort those words (the digit then sits above the index bits).
 template <typename K>
 hcc_status run_sort(const K* keys, uint32_t key_bits, uint32_t skip, uint32_t n, uint32_t* perm, K* sorted_keys,
                     char* ws, hipStream_t stream) {
     const uint32_t passes = (key_bits - skip + 7) / 8;
     const Layout L = layout(n, key_bits, skip);
-    const uint32_t tiles = (n + tile_of<K>() - 1) / tile_of<K>();
+    const uint32_t tiles_k = (n + tile_of<K>() - 1) / tile_of<K>();
+    const uint32_t tiles_w = (n + tile_of<uint32_t>() - 1) / tile_of<uint32_t>();
+    uint32_t ib = 0;
+    while (ib < 32 && (1ull << ib) < n) ++ib;
     uint32_t* counts = (uint32_t*)(ws + L.counts);
     uint32_t* tot = (uint32_t*)(ws + L.tot);
-    K* final_keys = sorted_keys ? sorted_keys : (K*)(ws + L.keys_a);
-    K* other_keys = (K*)(ws + L.keys_b);
+    void* final_keys = sorted_keys ? (void*)sorted_keys : (void*)(ws + L.keys_a);
+    void* other_keys = ws + L.keys_b;
     uint32_t* vals_tmp = (uint32_t*)(ws + L.vals);
-    const K* kin = keys;
+    const void* kin = keys;
     const uint32_t* vin = nullptr;
-    const dim3 grid(tiles), block(kBlock);
+    bool packed = false;       // kin holds packed words
+    uint32_t dropped = 0;      // key bits below the packed words' key part
     for (uint32_t p = 0; p < passes; ++p) {
         const bool to_final = ((passes - 1 - p) % 2) == 0;
-        K* kout = to_final ? final_keys : other_keys;
+        void* kout = to_final ? final_keys : other_keys;
         uint32_t* vout = to_final ? perm : vals_tmp;
         const bool last = p + 1 == passes;
-        const uint32_t shift = skip + 8u * p;
-        const uint32_t nb = std::min<uint32_t>(8u, key_bits - shift);
-        k_count<K><<<grid, block, 0, stream>>>(kin, n, shift, nb, counts);
-        k_scan<<<dim3(kRadix), block, 0, stream>>>(counts, tiles, tot);
-        if (p == 0) {
-            if (last && !sorted_keys)
-                k_scatter<K, true, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, counts, tot);
-            else
-                k_scatter<K, true, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, counts, tot);
+        const uint32_t at = skip + 8u * p;
+        const uint32_t nb = std::min<uint32_t>(8u, key_bits - at);
+        const uint32_t left = key_bits - (at + nb);
+        int out = kOutKeysVals;
+        if (last) out = sorted_keys ? kOutKeysVals : kOutVals;
+        else if (packed || (!sorted_keys && left + ib <= 32)) out = kOutPacked;
+        if (packed) {
+            const uint32_t shift = ib + (at - dropped);
+            k_count<uint32_t><<<dim3(tiles_w), dim3(kBlock), 0, stream>>>((const uint32_t*)kin, n, shift, nb, counts);
+            k_scan<<<dim3(kRadix), dim3(kBlock), 0, stream>>>(counts, tiles_w, tot);
+            scatter_packed(out, tiles_w, (const uint32_t*)kin, kout, vout, n, shift, nb, ib, counts, tot, stream);
         } else {
-            if (last && !sorted_keys)
-                k_scatter<K, false, false><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, counts, tot);
-            else
-                k_scatter<K, false, true><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, counts, tot);
+            k_count<K><<<dim3(tiles_k), dim3(kBlock), 0, stream>>>((const K*)kin, n, at, nb, counts);
+            k_scan<<<dim3(kRadix), dim3(kBlock), 0, stream>>>(counts, tiles_k, tot);
+            scatter_pass<K>(p == 0 ? kInIota : kInVals, out, tiles_k, (const K*)kin, vin, kout, vout, n, at, nb, ib,
+                            at + nb, counts, tot, stream);
+            if (out == kOutPacked) {
+                packed = true;
+                dropped = at + nb;
+            }
         }
         kin = kout;
         vin = vout;
@@ -496,8 +569,8 @@ size_t sort_workspace_bytes(uint32_t n, uint32_t key_bits) { return layout(n, ke
 size_t sort_static_bytes() { return kStaticBytes; }
 
 // hcc_sort with the library's static workspace: the same kernels as radix_sort_ex over the
-// whole key range; the zero-initialised parts of the workspace (histograms, tile counters,
-// look-back state) are cleared by a kernel on every call, as in every sort.
+// whole key range.  Every part of the workspace a pass reads was written earlier in the same
+// call, so nothing carries over between calls and nothing needs clearing.
 hcc_status radix_sort_static(const void* d_keys, uint32_t key_bits, uint32_t n, uint32_t* d_perm,
                              void* d_sorted_keys, hipStream_t stream) {
     if (key_bits < 1 || key_bits > 64) return fail(HCC_ERR_INVALID, "hcc_sort_static: key_bits must be in [1, 64]");

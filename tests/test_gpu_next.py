@@ -122,6 +122,8 @@ def test_prefix_sort_bit_exact(H, n, key_bits, skip):
     ref = O.sort_prefix(raw, key_bits, skip)
     assert np.array_equal(perm.cpu().numpy().view(np.uint32), ref)
     assert np.array_equal(_keys(sk, key_bits), raw[ref].astype(np.uint32 if key_bits <= 32 else np.uint64))
+    # without sorted keys out (packed late passes)
+    assert np.array_equal(H.sort_ex(keys, key_bits, skip_bits=skip).cpu().numpy().view(np.uint32), ref)
 
 
 @pytest.mark.parametrize("tile", [256, 512, 1024, 2048, 4096])

@@ -147,6 +147,8 @@ def test_sort_bit_exact(H, n, key_bits, kind):
     p = perm.cpu().numpy().view(np.uint32)
     assert np.array_equal(p, O.sort(keys))
     assert np.array_equal(_keys_np(sk, key_bits), keys[p.astype(np.int64)])
+    # without sorted keys out, the late passes move packed (key bits, index) words
+    assert np.array_equal(H.sort(dt, key_bits).cpu().numpy().view(np.uint32), p)
 
 
 @pytest.mark.parametrize("kind", ["few", "uniform"])
