@@ -2,8 +2,8 @@
 //
 // Sorting the ray keys as unsigned integers and handing the trace kernel the sorted
 // ray indices is the reorder step of the method (Sections 4.2.3 and 5).  Each pass over one
-// 8-bit digit is a reduce-then-scan over tiles of consecutive keys (8,192 32-bit words or 2,048
-// 64-bit keys), three launches with no waiting between workgroups:
+// 8-bit digit is a reduce-then-scan over tiles of consecutive keys (4,096 of 32 bits or 2,048
+// of 64 bits), three launches with no waiting between workgroups:
 //   1. k_count: each tile's digit counts (one read of the keys, every load of a thread issued
 //      at once; runs of equal digits added to LDS with one atomic), stored digit-major;
 //   2. k_scan: per digit, the exclusive scan of its counts over the tiles (in place) and the
@@ -26,18 +26,14 @@
 namespace hcc {
 namespace {
 
-constexpr uint32_t kBlock = 256;          // 4 wavefronts (scan and tile-local sort)
-// Keys per thread: 16 for 32-bit words (512-thread workgroups, 8,192-word tiles); 8 for 64-bit
-// keys (256 threads, 2,048-key tiles), whose LDS staging of a larger tile would leave room for
-// fewer workgroups per CU.
+constexpr uint32_t kBlock = 256;          // 4 wavefronts
+// Keys per thread and tile: 16 (4,096-key tiles) for 32-bit keys; 8 (2,048-key tiles) for
+// 64-bit keys, whose LDS staging of a 4,096-key tile (48 KB) would leave room for only two
+// workgroups per CU.
 template <typename K>
 constexpr uint32_t items_of() { return sizeof(K) == 4 ? 16u : 8u; }
-// Threads of the count and scatter workgroups: 512 (eight wavefronts, 8,192-key tiles) for
-// 32-bit words, 256 for 64-bit keys.
 template <typename K>
-constexpr uint32_t block_of() { return sizeof(K) == 4 ? 512u : 256u; }
-template <typename K>
-constexpr uint32_t tile_of() { return block_of<K>() * items_of<K>(); }
+constexpr uint32_t tile_of() { return kBlock * items_of<K>(); }
 constexpr uint32_t kRadix = 256;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
@@ -50,20 +46,18 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
-// Exclusive scan of one value per thread over a block of kB threads.  s must hold kB / 64
-// words not used by any other concurrent scan.
-template <uint32_t kB>
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s) {
+// Exclusive scan of one value per thread over a 256-thread block.  s must hold 4 words
+// not used by any other concurrent scan.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s) {
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
     uint32_t incl = wave_incl_scan(x);
     if (lane == 63) s[w] = incl;
     __syncthreads();
     uint32_t pre = 0;
 #pragma unroll
-    for (uint32_t j = 0; j < kB / 64; ++j) pre += (j < w) ? s[j] : 0u;
+    for (uint32_t j = 0; j < 4; ++j) pre += (j < w) ? s[j] : 0u;
     return pre + incl - x;
 }
-__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s) { return block_excl_scan<256>(x, s); }
 
 // Lanes of the wavefront (among 'alive') whose low 'nbits' bits of d equal this lane's.
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint32_t nbits, bool alive) {
@@ -92,16 +86,15 @@ __global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
 // together, and adds each run of equal digits among them to its wavefront's LDS histogram
 // with one atomic (keys of coherent rays repeat: few atomics, little contention).
 template <typename K>
-__global__ __launch_bounds__(block_of<K>()) void k_count(const K* __restrict__ keys, uint32_t n, uint32_t shift,
-                                                         uint32_t nbits, uint32_t* __restrict__ counts) {
+__global__ __launch_bounds__(kBlock) void k_count(const K* __restrict__ keys, uint32_t n, uint32_t shift,
+                                                  uint32_t nbits, uint32_t* __restrict__ counts) {
     constexpr uint32_t kPerLoad = 16 / sizeof(K);
     constexpr uint32_t kItems = items_of<K>(), kTile = tile_of<K>();
-    constexpr uint32_t kB = block_of<K>(), kW = kB / 64;
-    __shared__ uint32_t s_h[kW * kRadix];
+    __shared__ uint32_t s_h[4 * kRadix];
     const uint32_t t = threadIdx.x, w = t >> 6;
     const uint32_t T = gridDim.x;
     const uint32_t tile = xcd_block(blockIdx.x, T);
-    for (uint32_t i = t; i < kW * kRadix; i += kB) s_h[i] = 0;
+    for (uint32_t i = t; i < 4 * kRadix; i += kBlock) s_h[i] = 0;
     const uint32_t mask = (1u << nbits) - 1u;
     const size_t first = (size_t)tile * kTile + (size_t)t * kItems;
     const uint32_t nv = first >= n ? 0u : ((size_t)n - first >= kItems ? kItems : (uint32_t)((size_t)n - first));
@@ -149,12 +142,7 @@ __global__ __launch_bounds__(block_of<K>()) void k_count(const K* __restrict__ k
     }
     if (run) atomicAdd(&h[cur], run);
     __syncthreads();
-    if (t < kRadix) {
-        uint32_t c = 0;
-#pragma unroll
-        for (uint32_t j = 0; j < kW; ++j) c += s_h[j * kRadix + t];
-        counts[(size_t)t * T + tile] = c;
-    }
+    counts[(size_t)t * T + tile] = s_h[t] + s_h[kRadix + t] + s_h[2 * kRadix + t] + s_h[3 * kRadix + t];
 }
 
 // Block d: exclusive scan of digit d's tile counts (row d of counts, T entries, in place),
@@ -238,25 +226,24 @@ struct TileStage<uint32_t, true> {
 // ib bits.  Packed output: (key part >> pshift) << ib | value, where the key part is the key
 // or, for packed input, the word without its index bits.
 template <typename K, int kIn, int kOut>
-__global__ __launch_bounds__(block_of<K>()) void k_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                           void* __restrict__ kout_, uint32_t* __restrict__ vout,
-                                                           uint32_t n, uint32_t shift, uint32_t nbits, uint32_t ib,
-                                                           uint32_t pshift, const uint32_t* __restrict__ offs,
-                                                           const uint32_t* __restrict__ tot) {
+__global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                    void* __restrict__ kout_, uint32_t* __restrict__ vout, uint32_t n,
+                                                    uint32_t shift, uint32_t nbits, uint32_t ib, uint32_t pshift,
+                                                    const uint32_t* __restrict__ offs,
+                                                    const uint32_t* __restrict__ tot) {
     constexpr uint32_t kItems = items_of<K>(), kTile = tile_of<K>();
-    constexpr uint32_t kB = block_of<K>(), kW = kB / 64;
     constexpr bool kPackedIn = kIn == kInPacked;
     static_assert(!kPackedIn || sizeof(K) == 4, "packed words are 32-bit");
-    __shared__ uint32_t s_whist[kW * kRadix];
+    __shared__ uint32_t s_whist[4 * kRadix];
     __shared__ uint32_t s_gofs[kRadix];
-    __shared__ uint32_t s_scan[2 * kW];
+    __shared__ uint32_t s_scan[8];
     __shared__ TileStage<K, kPackedIn> s_tile;
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
     const uint32_t T = gridDim.x;
     const uint32_t tile = xcd_block(blockIdx.x, T);
     const uint32_t mask = (1u << nbits) - 1u;
     const uint32_t imask = ib >= 32 ? ~0u : (1u << ib) - 1u;
-    for (uint32_t i = t; i < kW * kRadix; i += kB) s_whist[i] = 0;
+    for (uint32_t i = t; i < 4 * kRadix; i += kBlock) s_whist[i] = 0;
     const uint32_t base = tile * kTile + w * (64u * kItems) + lane;
     const uint64_t lt = lanemask_lt();
     uint32_t* wh = s_whist + w * kRadix;
@@ -281,8 +268,8 @@ __global__ __launch_bounds__(block_of<K>()) void k_scatter(const K* __restrict__
         }
     }
     // the tile's global offsets do not depend on its keys: read them while the keys load
-    const uint32_t gtot = t < kRadix ? tot[t] : 0u;
-    const uint32_t gofs = t < kRadix ? offs[(size_t)t * T + tile] : 0u;
+    const uint32_t gtot = tot[t];
+    const uint32_t gofs = offs[(size_t)t * T + tile];
     __syncthreads();
 
     // stable rank of every key among the keys of its wavefront with the same digit
@@ -300,26 +287,18 @@ __global__ __launch_bounds__(block_of<K>()) void k_scatter(const K* __restrict__
     }
     __syncthreads();
 
-    // thread t < 256 owns digit t: where each wavefront's keys of digit t start in the tile, and
-    // the distance from a position in the tile to its position in the output
+    // thread t owns digit t: where each wavefront's keys of digit t start in the tile, and the
+    // distance from a position in the tile to its position in the output
     const uint32_t d = t;
-    uint32_t c[kW], all = 0;
-#pragma unroll
-    for (uint32_t j = 0; j < kW; ++j) {
-        c[j] = d < kRadix ? s_whist[j * kRadix + d] : 0u;
-        all += c[j];
-    }
-    const uint32_t dexcl = block_excl_scan<kB>(all, s_scan);
-    const uint32_t gbase = block_excl_scan<kB>(gtot, s_scan + kW) + gofs;
-    if (d < kRadix) {
-        uint32_t at = dexcl;
-#pragma unroll
-        for (uint32_t j = 0; j < kW; ++j) {
-            s_whist[j * kRadix + d] = at;
-            at += c[j];
-        }
-        s_gofs[d] = gbase - dexcl;
-    }
+    const uint32_t c0 = s_whist[d], c1 = s_whist[kRadix + d], c2 = s_whist[2 * kRadix + d],
+                   c3 = s_whist[3 * kRadix + d];
+    const uint32_t dexcl = block_excl_scan256(c0 + c1 + c2 + c3, s_scan);
+    const uint32_t gbase = block_excl_scan256(gtot, s_scan + 4) + gofs;
+    s_whist[d] = dexcl;
+    s_whist[kRadix + d] = dexcl + c0;
+    s_whist[2 * kRadix + d] = dexcl + c0 + c1;
+    s_whist[3 * kRadix + d] = dexcl + c0 + c1 + c2;
+    s_gofs[d] = gbase - dexcl;
     __syncthreads();
 
 #pragma unroll
@@ -333,7 +312,7 @@ __global__ __launch_bounds__(block_of<K>()) void k_scatter(const K* __restrict__
     const uint32_t count = min(kTile, n - tile * kTile);
 #pragma unroll
     for (uint32_t i = 0; i < kItems; ++i) {
-        const uint32_t j = t + i * kB;
+        const uint32_t j = t + i * kBlock;
         if (j < count) {
             K key;
             uint32_t val;
@@ -457,7 +436,7 @@ template <typename K>
 void scatter_pass(int in, int out, uint32_t tiles, const K* kin, const uint32_t* vin, void* kout, uint32_t* vout,
                   uint32_t n, uint32_t shift, uint32_t nb, uint32_t ib, uint32_t pshift, const uint32_t* counts,
                   const uint32_t* tot, hipStream_t stream) {
-    const dim3 grid(tiles), block(block_of<K>());
+    const dim3 grid(tiles), block(kBlock);
 #define HCC_SCATTER(I, O) \
     k_scatter<K, I, O><<<grid, block, 0, stream>>>(kin, vin, kout, vout, n, shift, nb, ib, pshift, counts, tot)
     if (in == kInIota) {
@@ -475,7 +454,7 @@ void scatter_pass(int in, int out, uint32_t tiles, const K* kin, const uint32_t*
 void scatter_packed(int out, uint32_t tiles, const uint32_t* kin, void* kout, uint32_t* vout, uint32_t n,
                     uint32_t shift, uint32_t nb, uint32_t ib, const uint32_t* counts, const uint32_t* tot,
                     hipStream_t stream) {
-    const dim3 grid(tiles), block(block_of<uint32_t>());
+    const dim3 grid(tiles), block(kBlock);
     if (out == kOutVals)
         k_scatter<uint32_t, kInPacked, kOutVals><<<grid, block, 0, stream>>>(kin, nullptr, kout, vout, n, shift, nb,
                                                                           ib, 0u, counts, tot);
@@ -518,11 +497,11 @@ hcc_status run_sort(const K* keys, uint32_t key_bits, uint32_t skip, uint32_t n,
         else if (packed || (!sorted_keys && left + ib <= 32)) out = kOutPacked;
         if (packed) {
             const uint32_t shift = ib + (at - dropped);
-            k_count<uint32_t><<<dim3(tiles_w), dim3(block_of<uint32_t>()), 0, stream>>>((const uint32_t*)kin, n, shift, nb, counts);
+            k_count<uint32_t><<<dim3(tiles_w), dim3(kBlock), 0, stream>>>((const uint32_t*)kin, n, shift, nb, counts);
             k_scan<<<dim3(kRadix), dim3(kBlock), 0, stream>>>(counts, tiles_w, tot);
             scatter_packed(out, tiles_w, (const uint32_t*)kin, kout, vout, n, shift, nb, ib, counts, tot, stream);
         } else {
-            k_count<K><<<dim3(tiles_k), dim3(block_of<K>()), 0, stream>>>((const K*)kin, n, at, nb, counts);
+            k_count<K><<<dim3(tiles_k), dim3(kBlock), 0, stream>>>((const K*)kin, n, at, nb, counts);
             k_scan<<<dim3(kRadix), dim3(kBlock), 0, stream>>>(counts, tiles_k, tot);
             scatter_pass<K>(p == 0 ? kInIota : kInVals, out, tiles_k, (const K*)kin, vin, kout, vout, n, at, nb, ib,
                             at + nb, counts, tot, stream);
