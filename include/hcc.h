@@ -104,7 +104,8 @@ typedef struct hcc_trace_opts {
                                  w + waves, w + 2 waves, ... instead.  Results are the same
                                  either way. */
     uint32_t waves;           /* persistent: wavefronts launched (0 = 8192) */
-    uint32_t flags;           /* HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB | HCC_TRACE_SPREAD */
+    uint32_t flags;           /* HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB | HCC_TRACE_SPREAD |
+                                 HCC_TRACE_QUANT */
 } hcc_trace_opts;
 
 /* hcc_trace_opts.flags */
@@ -122,6 +123,14 @@ typedef struct hcc_trace_opts {
                                    deals the chunks in 64 interleaved streams (take t -> chunk
                                    (t mod 64) * ceil(chunks / 64) + t / 64), so the wavefronts running
                                    together work on 64 parts of the order; same results */
+#define HCC_TRACE_QUANT 16u     /* with HCC_TRACE_WIDE: traverse the quantised copy of the 4-wide nodes that
+                                   hcc_build_bvh also builds (64 bytes per node instead of 128: each slot's
+                                   box as 8-bit steps from the node's corner, rounded outwards, so every
+                                   decoded box contains the exact one; the node step reads four 16-byte
+                                   words instead of seven).  The traversal then tests a superset of the
+                                   boxes the exact nodes pass and finds the same closest or any hit.
+                                   HCC_ERR_UNSUPPORTED without HCC_TRACE_WIDE, or for a BVH with a
+                                   non-finite box */
 
 /* ---------------------------------------------------------------------------------------
  * hcc_build_bvh -- linear BVH over n_tris triangles (Section 3.1: the acceleration structure

@@ -364,7 +364,7 @@ def trace(bvh: BVH, rays: torch.Tensor, perm=None, closest: bool = True, out=Non
     return out
 
 
-TRACE_SPECULATE, TRACE_WIDE, TRACE_SLAB, TRACE_SPREAD = 1, 2, 4, 8
+TRACE_SPECULATE, TRACE_WIDE, TRACE_SLAB, TRACE_SPREAD, TRACE_QUANT = 1, 2, 4, 8, 16
 BATCH_STACK_SCRATCH = 3
 lib.hcc_trace_count.argtypes = [_H, _P, _P, _U32, C.c_int, _P, _P, C.POINTER(TraceOpts), _P, _P]
 lib.hcc_trace_count.restype = C.c_int

@@ -5,8 +5,8 @@ the fastest.  The search space covers what the trace kernels expose: one-ray-per
 (64/128/256 lanes) vs persistent wavefronts, the stack placement (scratch, LDS, split), the
 persistent refill threshold, chunk size and speculative descent, and for the 4-wide traversal
 the wavefront count, the child-box test (selected planes or slab, whichever suits the
-scene's size against the caches) and whether the chunk counter deals chunks in order or spread
-over the order; for HCC additionally the cut size C and key length K (the
+scene's size against the caches), exact or quantised nodes, and whether the chunk counter deals
+chunks in order or spread over the order; for HCC additionally the cut size C and key length K (the
 paper's configuration is C = K).
 """
 from __future__ import annotations
@@ -22,10 +22,10 @@ from . import (KEY_HCC, KEY_TWOPOINT, TraceOpts, encode, select_cut, sort_ex, so
 PLAIN = [TraceOpts(b, s, 0, 0, 0, 0, 0, 0) for b in (64, 128) for s in (0, 2)]
 PERSISTENT = [TraceOpts(64, s, 0, 1, r, c, 8192, f)
               for s in (0,) for r in (24, 32) for c in (64, 128, 256) for f in (0, 1)]
-# 4-wide: LDS short stack, both child-box tests (selected planes / slab, flags 2 / 6), chunks dealt
-# in order or spread over the order (flag 8)
-WIDE = [TraceOpts(64, 2, 0, 1, r, c, 8192, f | sp) for f in (2, 6) for sp in (0, 8) for r in (24, 32)
-        for c in (64, 128, 256)]
+# 4-wide: LDS short stack, both child-box tests (selected planes / slab, flags 2 / 6) on the exact
+# or the quantised nodes (flag 16), chunks dealt in order or spread over the order (flag 8)
+WIDE = [TraceOpts(64, 2, 0, 1, r, c, 8192, f | q | sp) for f in (2, 6) for q in (0, 16) for sp in (0, 8)
+        for r in (24, 32) for c in (64, 128, 256)]
 DEFAULT_CANDIDATES = PLAIN + PERSISTENT + WIDE
 
 

@@ -331,6 +331,82 @@ __global__ __launch_bounds__(256) void k_wide_level(const uint32_t* __restrict__
     wide[level_base + i] = w;
 }
 
+// Quantised copy of wide node i (the Node4Q layout).  Axis a: corner p = the least lower plane
+// of the slots, scale s = the least power of two (at least 2^-126) whose step 255 decodes to at
+// least the node's upper plane; each slot's lower step is the largest decoding to at most its
+// lower plane, its upper step the smallest decoding to at least its upper plane, both found by
+// decoding exactly as the traversal does (fmaf(q, s, p)).  A node with a non-finite corner or
+// upper plane counts into *bad and keeps zero steps (the library then does not offer the
+// quantised traversal for this BVH).
+__device__ __forceinline__ float qdec(uint32_t q, float s, float p) { return fmaf((float)q, s, p); }
+
+__global__ __launch_bounds__(256) void k_quantize_wide(const Node4* __restrict__ wide, uint32_t count,
+                                                       Node4Q* __restrict__ qn, uint32_t* __restrict__ bad) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const Node4 w = wide[i];
+    const uint32_t refs[4] = {w.ref.x, w.ref.y, w.ref.z, w.ref.w};
+    const float lo[3][4] = {{w.lox.x, w.lox.y, w.lox.z, w.lox.w},
+                            {w.loy.x, w.loy.y, w.loy.z, w.loy.w},
+                            {w.loz.x, w.loz.y, w.loz.z, w.loz.w}};
+    const float hi[3][4] = {{w.hix.x, w.hix.y, w.hix.z, w.hix.w},
+                            {w.hiy.x, w.hiy.y, w.hiy.z, w.hiy.w},
+                            {w.hiz.x, w.hiz.y, w.hiz.z, w.hiz.w}};
+    float p[3], sc[3];
+    uint32_t lw[3] = {0, 0, 0}, hw[3] = {0, 0, 0};
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        float c = INFINITY, top = -INFINITY;
+        for (int j = 0; j < 4; ++j) {
+            if (refs[j] == kWideEmpty) continue;
+            c = fminf(c, lo[a][j]);
+            top = fmaxf(top, hi[a][j]);
+        }
+        p[a] = c;
+        sc[a] = 0.0f;
+        if (!(fabsf(c) < INFINITY) || !(fabsf(top) < INFINITY) || !(top >= c)) {
+            ok = false;
+            continue;
+        }
+        // the least power of two whose 255 steps reach top (start from the extent's estimate)
+        const double need = ((double)top - (double)c) / 255.0;
+        int e = need > 0.0 ? (int)ceil(log2(need)) : -126;
+        if (e < -126) e = -126;
+        float s = ldexpf(1.0f, e);
+        while (e > -126 && qdec(255u, ldexpf(1.0f, e - 1), c) >= top) s = ldexpf(1.0f, --e);
+        while (qdec(255u, s, c) < top && e < 127) s = ldexpf(1.0f, ++e);
+        if (!(qdec(255u, s, c) >= top) || !(fabsf(qdec(255u, s, c)) < INFINITY)) {
+            ok = false;
+            continue;
+        }
+        sc[a] = s;
+        for (int j = 0; j < 4; ++j) {
+            uint32_t ql = 255u, qh = 0u;   // empty slot: inverted
+            if (refs[j] != kWideEmpty) {
+                // lower: the largest step decoding to <= lo (step 0 decodes to c <= lo)
+                const double fl = floor(((double)lo[a][j] - (double)c) / (double)s);
+                ql = fl <= 0.0 ? 0u : (fl >= 255.0 ? 255u : (uint32_t)fl);
+                while (ql > 0u && qdec(ql, s, c) > lo[a][j]) --ql;
+                while (ql < 255u && qdec(ql + 1u, s, c) <= lo[a][j]) ++ql;
+                // upper: the smallest step decoding to >= hi (step 255 decodes to >= top >= hi)
+                const double fh = ceil(((double)hi[a][j] - (double)c) / (double)s);
+                qh = fh <= 0.0 ? 0u : (fh >= 255.0 ? 255u : (uint32_t)fh);
+                while (qh < 255u && qdec(qh, s, c) < hi[a][j]) ++qh;
+                while (qh > 0u && qdec(qh - 1u, s, c) >= hi[a][j]) --qh;
+            }
+            lw[a] |= ql << (8 * j);
+            hw[a] |= qh << (8 * j);
+        }
+    }
+    if (!ok) atomicAdd(bad, 1u);
+    Node4Q q;
+    q.a = make_float4(p[0], p[1], p[2], sc[0]);
+    q.b = make_float4(sc[1], sc[2], __uint_as_float(lw[0]), __uint_as_float(hw[0]));
+    q.c = make_uint4(lw[1], hw[1], lw[2], hw[2]);
+    q.ref = w.ref;
+    qn[i] = q;
+}
+
 __global__ void k_fill(uint32_t* p, size_t n, uint32_t v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -362,6 +438,7 @@ void free_bvh(hcc_bvh_s* b) {
     const Allocator& A = b->alloc;
     A.put(b->nodes, nullptr);
     A.put(b->wnodes, nullptr);
+    A.put(b->qnodes, nullptr);
     A.put(b->tris, nullptr);
     A.put(b->boxes, nullptr);
     A.put(b->had, nullptr);
@@ -473,6 +550,23 @@ hcc_status build_bvh(const float* d_tris, uint32_t n, hipStream_t stream, hcc_bv
             cleanup();
             free_bvh(b);
             return fail(HCC_ERR_DEVICE, "hcc_build_bvh: 4-wide collapse did not finish");
+        }
+        b->n_wide = level_base;
+        // quantised copy of the wide nodes (flags[0] counts nodes that cannot be quantised)
+        if (e == hipSuccess) {
+            const hcc_status qs = dalloc(A, stream, &b->qnodes, b->n_wide, b->bytes);
+            if (qs != HCC_OK) {
+                cleanup();
+                free_bvh(b);
+                return qs;
+            }
+            uint32_t nbad = 1;
+            k_fill<<<1, 256, 0, stream>>>(flags, 1, 0u);
+            k_quantize_wide<<<blocks_for(b->n_wide), 256, 0, stream>>>(b->wnodes, b->n_wide, b->qnodes, flags);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipMemcpyAsync(&nbad, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            b->quant_ok = e == hipSuccess && nbad == 0;
         }
     }
     if (e == hipSuccess) e = hipMemcpyAsync(b->scene_box, d_box, 6 * sizeof(float), hipMemcpyDeviceToHost, stream);

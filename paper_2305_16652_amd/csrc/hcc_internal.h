@@ -38,6 +38,28 @@ struct alignas(64) Node4 {
 };
 constexpr uint32_t kWideLeaf = 0x80000000u;
 constexpr uint32_t kWideEmpty = 0xFFFFFFFFu;
+
+// Quantised 4-wide node, 64 bytes (one cache line, four 16-byte loads instead of the seven a
+// Node4 step reads): the slot boxes of the Node4 with the same index as 8-bit steps from the
+// node's corner.  On axis a, step q decodes to the plane fmaf(q, s_a, p_a) (q * s_a is exact,
+// one rounding), with p the corner (the least lower plane over the slots) and s_a a power of
+// two for which step 255 reaches the node's upper plane.  A slot's lower steps are the largest
+// that decode to at most its lower planes and its upper steps the smallest that decode to at
+// least its upper planes, so every decoded box contains its slot's box and a ray that meets a
+// slot's box meets its decoded box.  An empty slot has lower steps 255, upper steps 0 and ref
+// kWideEmpty.
+//   a = (p.x, p.y, p.z, s.x)   b = (s.y, s.z, lower x steps, upper x steps)
+//   c = (lower y, upper y, lower z, upper z steps)   ref = the Node4's refs
+// Each steps word holds slot j in byte j.
+struct alignas(64) Node4Q {
+    float4 a, b;
+    uint4 c;
+    uint4 ref;
+};
+
+__device__ __forceinline__ float qplane(uint32_t steps, int j, float s, float p) {
+    return fmaf((float)((steps >> (8 * j)) & 255u), s, p);
+}
 constexpr int kWideStack = 192;   // <= 3 pushes per wide level, at most 63 levels (BVH2 depth over 62-bit keys)
 
 // Triangle in Morton order, 48 bytes: v0, e1 = v1 - v0, e2 = v2 - v0 (float32,
@@ -146,6 +168,46 @@ __device__ __forceinline__ void wide_test(const Node4* __restrict__ wn, uint32_t
     }
 }
 
+// The four child tests of quantised node `node`: the tests of wide_test on the decoded boxes
+// (kFast: the selected-plane form, for fast rays), plus the check of ref for empty slots, whose
+// decoded box is inverted but not by infinities.
+template <bool kFast>
+__device__ __forceinline__ void wide_test_q(const Node4Q* __restrict__ qn, uint32_t node, const WideRay& w, float ox,
+                                            float oy, float oz, float ix, float iy, float iz, float tmin, float lim,
+                                            uint4& ref, bool (&h)[4], float (&t)[4]) {
+    const Node4Q nd = qn[node];
+    ref = nd.ref;
+    const float px = nd.a.x, py = nd.a.y, pz = nd.a.z, sx = nd.a.w, sy = nd.b.x, sz = nd.b.y;
+    const uint32_t lox = __float_as_uint(nd.b.z), hix = __float_as_uint(nd.b.w);
+    const uint32_t loy = nd.c.x, hiy = nd.c.y, loz = nd.c.z, hiz = nd.c.w;
+    const uint32_t refs[4] = {ref.x, ref.y, ref.z, ref.w};
+    if constexpr (kFast) {
+        // entry steps: the lower ones where 1/d has its sign bit clear, else the upper ones
+        const uint32_t enx = w.ex ? hix : lox, exx = w.ex ? lox : hix;
+        const uint32_t eny = w.ey != 16u ? hiy : loy, exy = w.ey != 16u ? loy : hiy;
+        const uint32_t enz = w.ez != 32u ? hiz : loz, exz = w.ez != 32u ? loz : hiz;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float tn = fmaxf(fmaxf(fmaxf((qplane(enx, j, sx, px) - ox) * ix, (qplane(eny, j, sy, py) - oy) * iy),
+                                         (qplane(enz, j, sz, pz) - oz) * iz),
+                                   tmin);
+            const float tf = fminf(fminf(fminf((qplane(exx, j, sx, px) - ox) * ix, (qplane(exy, j, sy, py) - oy) * iy),
+                                         (qplane(exz, j, sz, pz) - oz) * iz) *
+                                       0x1.000006p+0f,
+                                   lim);
+            t[j] = tn;
+            h[j] = tn <= tf && refs[j] != kWideEmpty;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            h[j] = slab(ox, oy, oz, ix, iy, iz, tmin, lim, qplane(lox, j, sx, px), qplane(loy, j, sy, py),
+                        qplane(loz, j, sz, pz), qplane(hix, j, sx, px), qplane(hiy, j, sy, py), qplane(hiz, j, sz, pz),
+                        t[j]) &&
+                   refs[j] != kWideEmpty;
+    }
+}
+
 // Moller-Trumbore, double sided, float32, fixed operation order, no FMA contraction.
 __device__ __forceinline__ bool tri_test(const Tri& tr, float ox, float oy, float oz, float dx, float dy, float dz,
                                          float tmin, float tmax, float& t, float& u, float& v) {
@@ -240,6 +302,9 @@ struct hcc_bvh_s {
     uint32_t n_int = 0;             // internal nodes = n - 1
     hcc::Node* nodes = nullptr;     // n_int
     hcc::Node4* wnodes = nullptr;   // 4-wide nodes in level order from the root (at most n_int)
+    hcc::Node4Q* qnodes = nullptr;  // the same nodes quantised (n_wide), when quant_ok
+    uint32_t n_wide = 0;            // 4-wide nodes
+    bool quant_ok = false;          // every wide node's corner and extent are finite
     hcc::Tri* tris = nullptr;       // n (Morton order)
     float* boxes = nullptr;         // (2n-1) x 6
     double* had = nullptr;          // 2n-1

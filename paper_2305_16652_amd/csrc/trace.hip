@@ -503,7 +503,8 @@ struct WideStack<0> {
 };
 
 template <bool kClosest, bool kStats, int kLds>
-__global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn, const Tri* __restrict__ tris,
+__global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn, const Node4Q* __restrict__ qn,
+                                                   const Tri* __restrict__ tris,
                                                    uint32_t n_int, const float4* __restrict__ rays,
                                                    const uint32_t* __restrict__ perm, uint32_t n,
                                                    float4* __restrict__ hits, uint8_t* __restrict__ occ,
@@ -580,13 +581,17 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
         // ---- one 4-wide node step for lanes with a node and no pending leaves
         const bool step = has && node != kNone && pmask == 0;
         if (kStats) c_nodes += wave_distinct_on(node, step);
-        // the whole node step is specialised on the (wavefront-uniform) form of the child test
+        // the whole node step is specialised on the (wavefront-uniform) form of the child test:
+        // 0 slab test, 1 selected planes, 2 / 3 the same on the quantised nodes
         auto node_step = [&](auto kind) {
             uint4 r;
             bool hh[4];
             float tt[4];
-            wide_test<decltype(kind)::value>(wn, node, wr, ox, oy, oz, ix, iy, iz, tmin, kClosest ? best_t : tmax, r,
-                                             hh, tt);
+            constexpr int kKind = decltype(kind)::value;
+            if constexpr (kKind >= 2)
+                wide_test_q<kKind == 3>(qn, node, wr, ox, oy, oz, ix, iy, iz, tmin, kClosest ? best_t : tmax, r, hh, tt);
+            else
+                wide_test<kKind == 1>(wn, node, wr, ox, oy, oz, ix, iy, iz, tmin, kClosest ? best_t : tmax, r, hh, tt);
             s_leaf[__lane_id()] = r;   // read back only if this step leaves hit leaves pending
             const bool h0 = hh[0], h1 = hh[1], h2 = hh[2], h3 = hh[3];
             const float t0 = tt[0], t1 = tt[1], t2 = tt[2], t3 = tt[3];
@@ -632,10 +637,16 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
                 }
             }
         };
-        if (fast_nodes && __ballot(step && !wr.fast) == 0) {
-            if (step) node_step(std::true_type{});
+        if (qn) {
+            if (!slab && __ballot(step && !wr.fast) == 0) {
+                if (step) node_step(std::integral_constant<int, 3>{});
+            } else {
+                if (step) node_step(std::integral_constant<int, 2>{});
+            }
+        } else if (fast_nodes && __ballot(step && !wr.fast) == 0) {
+            if (step) node_step(std::integral_constant<int, 1>{});
         } else {
-            if (step) node_step(std::false_type{});
+            if (step) node_step(std::integral_constant<int, 0>{});
         }
 
         // ---- batched leaf tests
@@ -763,8 +774,10 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
         // stack: scratch (HCC_STACK_SCRATCH, and always when counting), the first 16 entries in
         // LDS (HCC_STACK_SHORT) or the first 24 (HCC_STACK_LDS)
         const int lds = kStats ? 0 : (o.stack == HCC_STACK_SHORT ? 16 : (o.stack == HCC_STACK_LDS ? 24 : 0));
-#define HCC_WIDE(CL, LD)                                                                                       \
-    k_trace_wide<CL, kStats, LD><<<waves, 64, 0, s>>>(b->wnodes, b->tris, b->n_int, r, perm, n, h, occ, refill, \
+        // quantised nodes (HCC_TRACE_QUANT): checked available by the caller
+        const Node4Q* qn = (o.flags & HCC_TRACE_QUANT) ? b->qnodes : nullptr;
+#define HCC_WIDE(CL, LD)                                                                                           \
+    k_trace_wide<CL, kStats, LD><<<waves, 64, 0, s>>>(b->wnodes, qn, b->tris, b->n_int, r, perm, n, h, occ, refill, \
                                                       chunk, deal, (o.flags & HCC_TRACE_SLAB) ? 1u : 0u, qslot, counts)
         if (closest) {
             if (lds == 16) HCC_WIDE(true, 16); else if (lds == 24) HCC_WIDE(true, 24); else HCC_WIDE(true, 0);
@@ -814,6 +827,9 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
 
 hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, bool closest,
                  hcc_hit* hits, uint8_t* occ, const hcc_trace_opts& o, hipStream_t s) {
+    if ((o.flags & HCC_TRACE_QUANT) && (!(o.flags & HCC_TRACE_WIDE) || (b->n_int > 0 && !b->quant_ok)))
+        return fail(HCC_ERR_UNSUPPORTED, "hcc_trace: HCC_TRACE_QUANT needs HCC_TRACE_WIDE and a BVH whose boxes are "
+                                         "finite");
     if ((o.persistent || (o.flags & HCC_TRACE_WIDE)) && b->n_int > 0)
         return trace_persistent<false>(b, rays, perm, n, closest, hits, occ, o, nullptr, s);
     const uint32_t block = o.block ? o.block : 64;
@@ -829,6 +845,9 @@ hcc_status trace_count(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* 
                        hipStream_t s) {
     if (!(o.persistent || (o.flags & HCC_TRACE_WIDE)) || b->n_int == 0)
         return fail(HCC_ERR_UNSUPPORTED, "hcc_trace_count: counts the persistent launches only");
+    if ((o.flags & HCC_TRACE_QUANT) && (!(o.flags & HCC_TRACE_WIDE) || !b->quant_ok))
+        return fail(HCC_ERR_UNSUPPORTED, "hcc_trace_count: HCC_TRACE_QUANT needs HCC_TRACE_WIDE and a BVH whose "
+                                         "boxes are finite");
     return trace_persistent<true>(b, rays, perm, n, closest, hits, occ, o, counts, s);
 }
 

@@ -3,7 +3,9 @@
 Bars: keys, permutations, BVH topology, boxes and HAD bit-exact; closest-hit t within
 1e-5 relative; triangle ids equal except at near-ties (|dt| < 1e-6, and the GPU's
 triangle really is hit at its t); at most 1e-5 of the rays may disagree; any-hit flags
-disagree on at most 1e-5 of the rays.
+disagree on at most 1e-5 of the rays.  Between two traversals of which one tests a superset
+of the other's triangles: the superset's hit is never farther, and where it differs it is a
+real hit of its triangle.
 """
 import numpy as np
 
@@ -65,6 +67,45 @@ def assert_any(gpu_occ: np.ndarray, ref_occ: np.ndarray, idx=None):
     assert set(np.unique(g).tolist()) <= {0, 1}
     nbad = int((g != r).sum())
     assert nbad <= MAX_RATE * g.size, f"{nbad} of {g.size} any-hit flags disagree"
+
+
+def _key(t, prim):
+    return (float("inf") if prim == MISS else float(t), int(prim))
+
+
+def assert_no_worse_closest(got: np.ndarray, base: np.ndarray, rays: np.ndarray, tris: np.ndarray, max_rate=MAX_RATE):
+    """`got` comes from a traversal that tests every triangle `base`'s traversal tests and maybe
+    more (quantised boxes contain the exact ones; 4-wide nodes skip intermediate boxes).  The
+    Moller-Trumbore test can accept a ray passing just outside a triangle (and outside its box)
+    by rounding, so such a traversal may find a hit the other one culled: on every ray got's
+    distance is at most base's, and where the hits differ got's triangle is really hit at got's
+    distance (the same test on that triangle alone).  At equal distances the triangles may differ:
+    which of two triangles hit at the same t survives depends on the visiting order (a box whose
+    entry distance rounds above the current hit's is culled).  max_rate bounds the share of rays
+    that differ (None: no bound, for rays aimed at vertices and edges on purpose)."""
+    g = np.ascontiguousarray(got, np.float32)
+    b = np.ascontiguousarray(base, np.float32)
+    diff = np.nonzero((g.view(np.uint32) != b.view(np.uint32)).any(1))[0]
+    if max_rate is not None:
+        assert diff.size <= max_rate * g.shape[0], f"{diff.size} of {g.shape[0]} hits differ, e.g. rays {diff[:10]}"
+    for r in diff:
+        gp, bp = int(g[r, 1:2].view(np.uint32)[0]), int(b[r, 1:2].view(np.uint32)[0])
+        assert _key(g[r, 0], gp)[0] <= _key(b[r, 0], bp)[0] and gp != MISS, f"ray {r}: {g[r]} is farther than {b[r]}"
+        h = O.brute_force(tris[gp][None], rays[r][None])
+        assert h.prim[0] == 0 and h.t[0] == g[r, 0] and h.u[0] == g[r, 2] and h.v[0] == g[r, 3], f"ray {r}"
+
+
+def assert_no_fewer_any(got: np.ndarray, base: np.ndarray, upper=None, max_rate=MAX_RATE):
+    """Any-hit flags of a traversal testing a superset of base's triangles: every ray base
+    finds occluded is occluded in got; got differs from base on at most max_rate of the rays
+    (None: no bound) and, given `upper` (brute force), never reports a ray no triangle hits."""
+    g = np.asarray(got, np.uint8)
+    b = np.asarray(base, np.uint8)
+    assert not (b & ~g).any(), "a ray occluded in the base traversal is not occluded"
+    if max_rate is not None:
+        assert int((g != b).sum()) <= max_rate * g.size
+    if upper is not None:
+        assert not (g & ~np.asarray(upper, np.uint8)).any(), "occluded without any triangle hit"
 
 
 def assert_stable_sort(keys: np.ndarray, perm: np.ndarray):

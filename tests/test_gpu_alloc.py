@@ -54,11 +54,11 @@ def test_hooked_allocations_balance_and_results_match(H):
     try:
         H.set_allocator(alloc, free)
         b1 = H.build_bvh(tris)
-        assert counts["alloc"] > 8 and len(live) == 8          # 8 BVH arrays kept, temporaries returned
+        assert counts["alloc"] > 9 and len(live) == 9          # 9 BVH arrays kept (with the quantised nodes), temporaries returned
         c1 = H.select_cut(b1, 32)
         m1 = H.select_mlhcc_cut(b1, 8, 8)
         g1 = H.grid_cut(b1, 4, 4, 2)
-        assert len(live) == 11
+        assert len(live) == 12
         out = _run(H, b1, c1, rays)
         for a, e in zip(out, ref):
             assert np.array_equal(a.view(np.uint32), e.view(np.uint32))
@@ -73,7 +73,7 @@ def test_hooked_allocations_balance_and_results_match(H):
         del batch
         srv.drain()
         srv.close()
-        assert counts["alloc"] > before and len(live) == 11
+        assert counts["alloc"] > before and len(live) == 12
         got = np.concatenate([b.out.cpu().numpy() for b in batches])
         assert np.array_equal(got.view(np.uint32), ref[2][:1600].view(np.uint32))
         del m1, g1, c1, b1, batches, srv

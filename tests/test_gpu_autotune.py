@@ -35,7 +35,8 @@ def test_every_trace_candidate_gives_the_oracle_hits(H, tiny):
     best, ms, table = AT.tune_trace(tiny["bvh"], tiny["rays"], None, reps=1)
     assert len(table) == len(AT.DEFAULT_CANDIDATES) and ms > 0
     # the 4-wide candidates cover both child-box tests, with chunks dealt in order and spread
-    assert {o.flags for o in AT.WIDE} == {H.TRACE_WIDE | s | sp for s in (0, H.TRACE_SLAB) for sp in (0, H.TRACE_SPREAD)}
+    assert {o.flags for o in AT.WIDE} == {H.TRACE_WIDE | s | q | sp for s in (0, H.TRACE_SLAB)
+                                          for q in (0, H.TRACE_QUANT) for sp in (0, H.TRACE_SPREAD)}
     for o in AT.DEFAULT_CANDIDATES + [best]:
         hits = H.trace(tiny["bvh"], tiny["rays"], opts=o).cpu().numpy()
         assert_closest(hits, tiny["ref"], tiny["sec"], tiny["spec"].tris)

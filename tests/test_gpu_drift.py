@@ -17,7 +17,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from parity_utils import assert_any, assert_closest
+from parity_utils import assert_any, assert_closest, assert_no_fewer_any, assert_no_worse_closest
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -87,9 +87,13 @@ def test_drift_keys_sort_trace(drift, mode, key_bits):
     sample = np.arange(0, sec.shape[0], 97)
     oh = O.trace(ob, sec, subset=sample, threads=THREADS)
     assert_closest(hits, oh, sec, drift["spec"].tris, idx=sample)
-    # the selected-plane child test returns the same hits on every ray
+    # the selected-plane child test and the quantised nodes return the same hits on every ray
     wide = H.trace(bvh, rays, perm, opts=H.TraceOpts(*DRIFT_OPTS[:7], H.TRACE_WIDE)).cpu().numpy()
     assert np.array_equal(wide.view(np.uint32), hits.view(np.uint32))
+    # the quantised nodes test a superset of the boxes: never a farther hit, every other hit real
+    for flags in (H.TRACE_WIDE | H.TRACE_QUANT, H.TRACE_WIDE | H.TRACE_QUANT | H.TRACE_SLAB):
+        quant = H.trace(bvh, rays, perm, opts=H.TraceOpts(*DRIFT_OPTS[:7], flags)).cpu().numpy()
+        assert_no_worse_closest(quant, hits, sec, drift["spec"].tris)
 
 
 def test_drift_shadow_any_hit(drift):
@@ -99,3 +103,5 @@ def test_drift_shadow_any_hit(drift):
     occ = H.trace(bvh, rays, perm, closest=False, opts=H.TraceOpts(*DRIFT_OPTS)).cpu().numpy()
     sample = np.arange(0, shd.shape[0], 199)
     assert_any(occ, O.trace(ob, shd, subset=sample, closest=False, threads=THREADS), idx=sample)
+    occ_q = H.trace(bvh, rays, perm, closest=False, opts=H.TraceOpts(*DRIFT_OPTS[:7], DRIFT_OPTS[7] | H.TRACE_QUANT))
+    assert_no_fewer_any(occ_q.cpu().numpy(), occ)

@@ -15,7 +15,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from parity_utils import assert_any, assert_closest, assert_stable_sort
+from parity_utils import assert_any, assert_closest, assert_no_fewer_any, assert_no_worse_closest, assert_stable_sort
 
 pytestmark = pytest.mark.gpu
 
@@ -24,6 +24,14 @@ THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
 # the autotuner picks among these and the one-ray-per-lane launch, which test_gpu_parity covers
 BENCH_OPTS = (64, 0, 0, 1, 32, 64, 8192, 1)
 WIDE_OPTS = (64, 2, 0, 1, 32, 64, 8192, 2)        # the 4-wide traversal, LDS short stack (bench's pick)
+
+
+def WIDE_FLAGS(H):
+    """4-wide variants checked against each other: child test, quantised nodes, spread dealing
+    (the exact nodes give the same hits bit for bit; the quantised ones test a superset of the
+    boxes, see assert_no_worse_closest)."""
+    w, q = H.TRACE_WIDE, H.TRACE_QUANT
+    return (w, w | H.TRACE_SLAB, w | q, w | q | H.TRACE_SLAB, w | q | H.TRACE_SPREAD)
 
 
 def _say(msg):
@@ -90,10 +98,14 @@ def test_fullsize_hcc_keys_sort_trace(frame, cut_size, key_bits):
     sample = np.arange(0, sec.shape[0], 997)
     oh = O.trace(ob, sec, subset=sample, threads=THREADS)
     assert_closest(hits, oh, sec, frame["spec"].tris, idx=sample)
-    # the 4-wide traversal returns the same closest hits on every ray, with either child test
-    for flags in (H.TRACE_WIDE, H.TRACE_WIDE | H.TRACE_SLAB):
+    # the 4-wide traversal returns the same closest hits on every ray, with either child test, on
+    # the exact and on the quantised nodes
+    for flags in WIDE_FLAGS(H):
         wide = H.trace(bvh, rays, perm, opts=H.TraceOpts(*WIDE_OPTS[:7], flags)).cpu().numpy()
-        assert np.array_equal(wide.view(np.uint32), hits.view(np.uint32))
+        if flags & H.TRACE_QUANT:
+            assert_no_worse_closest(wide, hits, sec, frame["spec"].tris)
+        else:
+            assert np.array_equal(wide.view(np.uint32), hits.view(np.uint32))
 
 
 def test_fullsize_twopoint_keys(frame):
@@ -112,6 +124,9 @@ def test_fullsize_shadow_any_hit(frame):
     sample = np.arange(0, shd.shape[0], 1999)
     ref = O.trace(ob, shd, subset=sample, closest=False, threads=THREADS)
     assert_any(occ, ref, idx=sample)
-    for flags in (H.TRACE_WIDE, H.TRACE_WIDE | H.TRACE_SLAB):
+    for flags in WIDE_FLAGS(H):
         wide = H.trace(bvh, rays, perm, closest=False, opts=H.TraceOpts(*WIDE_OPTS[:7], flags)).cpu().numpy()
-        assert np.array_equal(wide, occ)
+        if flags & H.TRACE_QUANT:
+            assert_no_fewer_any(wide, occ)
+        else:
+            assert np.array_equal(wide, occ)

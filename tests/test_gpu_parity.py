@@ -193,7 +193,10 @@ OPTS = [(128, 1, 0, 0, 0, 0, 0), (64, 1, 1, 0, 0, 0, 0), (256, 1, 0, 0, 0, 0, 0)
         # 4-wide with every child box through the slab test (flags bit 2)
         (0, 2, 0, 1, 32, 64, 0, 6), (0, 0, 1, 1, 16, 256, 9, 6), (0, 1, 0, 1, 1, 64, 3, 6),
         # chunks dealt spread over the order (flags bit 3), BVH2 and 4-wide
-        (0, 2, 0, 1, 32, 64, 0, 8 | 2), (0, 0, 0, 1, 16, 256, 5, 8 | 1)]
+        (0, 2, 0, 1, 32, 64, 0, 8 | 2), (0, 0, 0, 1, 16, 256, 5, 8 | 1),
+        # quantised 4-wide nodes (flags bit 4): selected planes, slab test, spread dealing, stacks
+        (0, 2, 0, 1, 32, 64, 0, 16 | 2), (0, 0, 0, 1, 16, 256, 5, 16 | 2), (0, 1, 0, 1, 1, 64, 3, 16 | 4 | 2),
+        (64, 2, 0, 1, 32, 64, 0, 16 | 8 | 2), (0, 2, 1, 1, 24, 128, 7, 16 | 2)]
 WIDE = (0, 0, 0, 1, 32, 64, 0, 2)
 
 
@@ -352,7 +355,9 @@ def test_invalid_arguments(H, gpu_bvh):
     with pytest.raises(H.HCCError):
         H.trace(gpu_bvh, rays, opts=H.TraceOpts(64, 7, 0, 0, 0, 0, 0, 0))
     with pytest.raises(H.HCCError):
-        H.trace(gpu_bvh, rays, opts=H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 16))     # unknown flag bit
+        H.trace(gpu_bvh, rays, opts=H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 32))     # unknown flag bit
+    with pytest.raises(H.HCCError):
+        H.trace(gpu_bvh, rays, opts=H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 16))     # quantised nodes without 4-wide
     other = H.build_bvh(torch.tensor([[0, 0, 0, 1, 0, 0, 0, 1, 0]], dtype=torch.float32, device="cuda"))
     with pytest.raises(H.HCCError):
         H.encode(gpu_bvh, H.select_cut(other, 1), H.KEY_HCC, 32, rays)   # cut from another BVH
