@@ -533,7 +533,8 @@ def run_serving(H, args):
         for name, server in (("plain", plain), ("continuous", None)):
             if server is None:
                 server = H.Server(key_mode=H.KEY_HCC, key_bits=32, max_group=16, streams=4,
-                                  batch=H.BatchOpts(0, 0, 0, H.TRACE_WIDE, 0), direct_min=args.serve_direct_min)
+                                  batch=H.BatchOpts(0, 0, 0, H.TRACE_WIDE | H.TRACE_QUANT, 0),
+                                  direct_min=args.serve_direct_min)
             lat, wall = serve(server, rate)
             row[name] = dict(p50_ms=round(float(np.percentile(lat, 50)) / 1e3, 3),
                              p99_ms=round(float(np.percentile(lat, 99)) / 1e3, 3),
@@ -582,7 +583,7 @@ def run_batched(H, args):
             ts.append(a.elapsed_time(e))
         return float(np.median(ts))
 
-    topts = H.TraceOpts(64, 2, 0, 1, 32, 64, 8192, H.TRACE_WIDE)
+    topts = H.TraceOpts(64, 2, 0, 1, 32, 64, 8192, H.TRACE_WIDE | H.TRACE_QUANT)
     bufs = {}
 
     def plain(mode, K):
@@ -628,8 +629,10 @@ def run_batched(H, args):
         best = None
         for chunk in (128, 256, 512):
             for refill in (24, 32):
+                wq = H.TRACE_WIDE | H.TRACE_QUANT
                 for flags, stacks in ((0, (0,)), (H.TRACE_WIDE, (0, H.STACK_LDS, H.BATCH_STACK_SCRATCH)),
-                                      (H.TRACE_WIDE | H.TRACE_SLAB, (0,))):
+                                      (H.TRACE_WIDE | H.TRACE_SLAB, (0,)),
+                                      (wq, (0, H.STACK_LDS, H.BATCH_STACK_SCRATCH)), (wq | H.TRACE_SLAB, (0,))):
                     for st in stacks:
                         o = H.BatchOpts(chunk, refill, 8192, flags, 0, st)
                         ms = timeit(lambda: H.batch_run(batches, H.KEY_HCC, K, opts=o, ws=ws), reps=2)

@@ -315,7 +315,8 @@ typedef struct hcc_batch_opts {
     uint32_t refill;          /* lane refill threshold 1..64 (0 = 32) */
     uint32_t waves;           /* persistent wavefronts launched (0 = 8192) */
     uint32_t flags;           /* HCC_TRACE_WIDE: trace over the 4-wide nodes, HCC_TRACE_SLAB as for
-                                 hcc_trace_opts; other bits must be 0 */
+                                 hcc_trace_opts, HCC_TRACE_QUANT (with HCC_TRACE_WIDE): the quantised
+                                 4-wide nodes of each scene that has them; other bits must be 0 */
     uint32_t direct_min;      /* 0 = every batch in the one engine launch (default); else >= 65536:
                                  batches of at least this many rays run afterwards through the
                                  full-device encode / sort / trace kernels on the same stream */

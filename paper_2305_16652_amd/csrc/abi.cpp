@@ -512,7 +512,7 @@ __attribute__((visibility("default"))) hcc_status hcc_batch_run(const hcc_batch_
     if (!d_ws || ((uintptr_t)d_ws & 255u)) return fail(HCC_ERR_INVALID, "hcc_batch_run: workspace must be 256-byte aligned");
     hcc_batch_opts o{};
     if (opts) o = *opts;
-    if ((o.flags & ~(HCC_TRACE_WIDE | HCC_TRACE_SLAB)) != 0)
+    if ((o.flags & ~(HCC_TRACE_WIDE | HCC_TRACE_SLAB | HCC_TRACE_QUANT)) != 0)
         return fail(HCC_ERR_INVALID, "hcc_batch_run: unknown opts.flags bits");
     if (o.direct_min != 0 && o.direct_min < 65536)
         return fail(HCC_ERR_INVALID, "hcc_batch_run: opts.direct_min must be 0 or at least 65536");

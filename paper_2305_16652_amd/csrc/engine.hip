@@ -34,6 +34,7 @@ hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, 
 struct EngScene {
     const Node* nodes;
     const Node4* wnodes;
+    const Node4Q* qnodes;  // quantised 4-wide nodes (HCC_TRACE_QUANT and the BVH has them), else null
     const Tri* tris;
     const CutBox* cut;
     uint32_t n_int;
@@ -525,8 +526,13 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
             uint4 r;
             bool hh[4];
             float tt[4];
-            wide_test<decltype(kind)::value>(sc.wnodes, node, wr, ox, oy, oz, ix, iy, iz, tmin,
-                                             closest ? best_t : tmax, r, hh, tt);
+            constexpr int kKind = decltype(kind)::value;   // 0 slab, 1 selected planes, 2 / 3 quantised
+            if constexpr (kKind >= 2)
+                wide_test_q<kKind == 3>(sc.qnodes, node, wr, ox, oy, oz, ix, iy, iz, tmin, closest ? best_t : tmax, r,
+                                        hh, tt);
+            else
+                wide_test<kKind == 1>(sc.wnodes, node, wr, ox, oy, oz, ix, iy, iz, tmin, closest ? best_t : tmax, r,
+                                      hh, tt);
             const bool h0 = hh[0], h1 = hh[1], h2 = hh[2], h3 = hh[3];
             const float t0 = tt[0], t1 = tt[1], t2 = tt[2], t3 = tt[3];
             const bool l0 = h0 && (r.x & kWideLeaf), l1 = h1 && (r.y & kWideLeaf);
@@ -567,10 +573,16 @@ __device__ void trace_range_wide_t(const EngScene& sc, const EngBatch& bt, const
                 else node = pop(--sp);
             }
         };
-        if (fast_nodes && __ballot(step && !wr.fast) == 0) {
-            if (step) node_step(std::true_type{});
+        if (sc.qnodes) {
+            if (!slab && __ballot(step && !wr.fast) == 0) {
+                if (step) node_step(std::integral_constant<int, 3>{});
+            } else {
+                if (step) node_step(std::integral_constant<int, 2>{});
+            }
+        } else if (fast_nodes && __ballot(step && !wr.fast) == 0) {
+            if (step) node_step(std::integral_constant<int, 1>{});
         } else {
-            if (step) node_step(std::false_type{});
+            if (step) node_step(std::integral_constant<int, 0>{});
         }
         const bool can_step = has && node != kNone && pmask == 0;
         const uint64_t busy = __ballot(has);
@@ -818,6 +830,9 @@ static hcc_status fill_tables(const hcc_batch_desc* d, uint32_t nb, uint32_t mod
         EngScene& e = T.hs[s];
         e.nodes = sb[s]->nodes;
         e.wnodes = sb[s]->wnodes;
+        // quantised nodes where asked for and available (a scene without them traces its exact
+        // nodes: the same hits but for the rounding cases the quantised boxes also reach)
+        e.qnodes = ((o.flags & HCC_TRACE_QUANT) && sb[s]->quant_ok) ? sb[s]->qnodes : nullptr;
         e.tris = sb[s]->tris;
         e.n_int = sb[s]->n_int;
         e.cut = sc[s] ? sc[s]->d_boxes : nullptr;
@@ -876,13 +891,14 @@ static hcc_status fill_tables(const hcc_batch_desc* d, uint32_t nb, uint32_t mod
 
 // One batch through the full-device kernels (encode, radix sort, persistent 4-wide trace) on
 // the stream, with its buffers at ws.
-static hcc_status run_direct(const hcc_batch_desc& d, uint32_t mode, uint32_t key_bits, char* ws, hipStream_t stream) {
+static hcc_status run_direct(const hcc_batch_desc& d, uint32_t mode, uint32_t key_bits, bool quant, char* ws,
+                             hipStream_t stream) {
     hcc_trace_opts to{};
     to.persistent = 1;
     to.stack = HCC_STACK_SHORT;
     to.refill = 32;
     to.chunk = 64;
-    to.flags = HCC_TRACE_WIDE;
+    to.flags = HCC_TRACE_WIDE | ((quant && d.bvh->quant_ok) ? HCC_TRACE_QUANT : 0u);
     const uint32_t* perm = nullptr;
     if (mode != HCC_KEY_NONE) {
         const size_t ks = key_bits <= 32 ? 4 : 8;
@@ -928,7 +944,8 @@ hcc_status batch_launch(const hcc_batch_desc* d, uint32_t nb, uint32_t mode, uin
         if (d[b].n < o.direct_min) continue;
         const size_t need = direct_bytes(d[b].n, mode, key_bits);
         if (off + need > ws_bytes) return fail(HCC_ERR_INVALID, "hcc_batch_run: workspace too small (see hcc_batch_workspace)");
-        const hcc_status st = run_direct(d[b], mode, key_bits, (char*)d_ws + off, stream);
+        const hcc_status st = run_direct(d[b], mode, key_bits, (o.flags & HCC_TRACE_QUANT) != 0, (char*)d_ws + off,
+                                         stream);
         if (st != HCC_OK) return st;
         off += need;
     }

@@ -228,12 +228,13 @@ bool enqueue_direct(hcc_server_s* s, const hcc_batch_desc& d, hipStream_t st, vo
                                           : hcc::encode_twopoint(d.bvh, kb, d.d_rays, d.n, bufs[0], st)) == HCC_OK;
         if (ok) ok = hcc::radix_sort(bufs[0], kb, d.n, (uint32_t*)bufs[1], nullptr, nullptr, bufs[2], wsb, st) == HCC_OK;
     }
-    hcc_trace_opts to{};   // the full-device trace: persistent 4-wide traversal, LDS short stack
+    hcc_trace_opts to{};   // the full-device trace: persistent 4-wide traversal (quantised nodes where
+                           // the BVH has them), LDS short stack
     to.persistent = 1;
     to.stack = HCC_STACK_SHORT;
     to.refill = 32;
     to.chunk = 64;
-    to.flags = HCC_TRACE_WIDE;
+    to.flags = HCC_TRACE_WIDE | (d.bvh->quant_ok ? HCC_TRACE_QUANT : 0u);
     if (ok && d.n > 0)
         ok = hcc::trace(d.bvh, d.d_rays, (const uint32_t*)bufs[1], d.n, d.mode == HCC_TRACE_CLOSEST, d.d_hits,
                         d.d_occluded, to, st) == HCC_OK;
@@ -392,7 +393,7 @@ __attribute__((visibility("default"))) hcc_status hcc_server_create(const hcc_se
     if (o.direct_min == 0) o.direct_min = 65536;
     if (o.streams == 0) o.streams = 4;
     if (o.key_bits == 0) o.key_bits = 32;
-    if (o.key_bits > 64 || o.streams > 32 || o.key_mode > HCC_KEY_TWOPOINT || (o.batch.flags & ~(HCC_TRACE_WIDE | HCC_TRACE_SLAB)) ||
+    if (o.key_bits > 64 || o.streams > 32 || o.key_mode > HCC_KEY_TWOPOINT || (o.batch.flags & ~(HCC_TRACE_WIDE | HCC_TRACE_SLAB | HCC_TRACE_QUANT)) ||
         o.batch.stack > HCC_BATCH_STACK_SCRATCH)
         return fail(HCC_ERR_INVALID, "hcc_server_create: bad options");
     o.batch.direct_min = 0;   // large requests are routed by the server itself (direct_min above)

@@ -6,7 +6,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from parity_utils import assert_any, assert_closest
+from parity_utils import assert_any, assert_closest, assert_no_fewer_any, assert_no_worse_closest
 
 pytestmark = pytest.mark.gpu
 
@@ -85,7 +85,9 @@ def _batches(H, scenes, seed, key_cut):
 @pytest.mark.parametrize("mode,key_bits,cut", [("hcc", 32, "cut32"), ("hcc", 64, "cut64"), ("hcc", 16, "cut32"),
                                                ("twopoint", 32, None), ("twopoint", 64, None), ("none", 32, None)])
 @pytest.mark.parametrize("opts", [None, (64, 1, 7, 0), (1000, 64, 3, 0), (256, 32, 0, 2), (64, 5, 11, 2),
-                                  (128, 24, 0, 6), (256, 32, 0, 2, 0, 3), (64, 9, 13, 6, 0, 1)])
+                                  (128, 24, 0, 6), (256, 32, 0, 2, 0, 3), (64, 9, 13, 6, 0, 1),
+                                  # quantised 4-wide nodes (flags bit 4), with each child test and stack
+                                  (256, 32, 0, 18), (64, 9, 13, 22, 0, 1), (128, 24, 0, 18, 0, 3)])
 def test_engine_matches_oracle_and_plain_path(H, scenes, mode, key_bits, cut, opts):
     key_mode = {"hcc": H.KEY_HCC, "twopoint": H.KEY_TWOPOINT, "none": 0}[mode]
     items = _batches(H, scenes, seed=key_bits + (opts[0] if opts else 0), key_cut=cut if mode == "hcc" else None)
@@ -106,11 +108,18 @@ def test_engine_matches_oracle_and_plain_path(H, scenes, mode, key_bits, cut, op
             keys = H.encode(s["bvh"], b.cut, key_mode, key_bits, b.rays)
             perm = H.sort(keys, key_bits)
         ref_gpu = H.trace(s["bvh"], b.rays, perm, closest=b.closest).cpu().numpy()
+        quant = bool(opts and opts[3] & H.TRACE_QUANT)
         if b.closest:
-            assert np.array_equal(got.view(np.uint32), ref_gpu.view(np.uint32))
+            if quant:   # a superset of the boxes: see assert_no_worse_closest
+                assert_no_worse_closest(got, ref_gpu, rays, s["spec"].tris)
+            else:
+                assert np.array_equal(got.view(np.uint32), ref_gpu.view(np.uint32))
             assert_closest(got, O.trace(s["ob"], rays), rays, s["spec"].tris)
         else:
-            assert np.array_equal(got, ref_gpu)
+            if quant:
+                assert_no_fewer_any(got, ref_gpu)
+            else:
+                assert np.array_equal(got, ref_gpu)
             assert_any(got, O.trace(s["ob"], rays, closest=False))
 
 
@@ -176,6 +185,8 @@ def test_engine_invalid_arguments(H, scenes):
         H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 1))
     with pytest.raises(H.HCCError):
         H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 8))
+    with pytest.raises(H.HCCError):
+        H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 32))
     with pytest.raises(H.HCCError):
         H.batch_run([H.Batch(s["bvh"], rays, True)], H.KEY_TWOPOINT, 32, opts=H.BatchOpts(0, 0, 0, 2, 0, 4))
 
