@@ -37,6 +37,7 @@ if ROOT not in sys.path:
 METRIC = "secondary Mrays/s incl. encode+sort vs NoSort; serve p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, WIDE_NODE_BYTES, TRI_BYTES = 64, 128, 48
+QUANT_NODE_BYTES = 64      # quantised 4-wide node
 RAY_BYTES, PERM_BYTES, HIT_BYTES = 32, 4, 16
 
 
@@ -899,20 +900,28 @@ def run_drift(H, args):
     return out
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per trace launch from the committed PMC summary, if it was taken for this
-    kernel and still describes the current trace kernel sources (else None)."""
+def measured_traffic(kernel: str, opts):
+    """HBM bytes per trace launch from the committed PMC summary: the entry taken for this
+    kernel with these launch options (flags, refill, chunk, wavefronts, stack), while the trace
+    kernel sources still hash to what they were then (else None)."""
     path = os.path.join(ROOT, "profiles", "trace_traffic.txt")
     if not os.path.exists(path):
         return None
-    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    lines = [l.strip() for l in open(path) if "=" in l and not l.startswith("#")]
+    kv = dict(l.split("=", 1) for l in lines if not l.startswith("launch="))
     if kv.get("kernel") != kernel:
         return None
     src = b"".join(open(os.path.join(ROOT, "paper_2305_16652_amd", "csrc", f), "rb").read()
                    for f in ("trace.hip", "hcc_internal.h"))
     if hashlib.sha256(src).hexdigest()[:16] != kv.get("kernel_sha256_16"):
         return None
-    return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+    want = [int(opts.flags), int(opts.refill), int(opts.chunk), int(opts.waves), int(opts.stack)]
+    for l in lines:
+        if l.startswith("launch="):
+            f = [int(x) for x in l.split("=", 1)[1].split()]
+            if f[:5] == want:
+                return f[5] + f[6]
+    return None
 
 
 def kernel_name(H, opts) -> str:
@@ -932,7 +941,7 @@ def kernel_counted_fetches(H, bvh, rays, perm, opts) -> dict:
     else:
         _, _, _, wn, wt = H.trace_stats(bvh, rays, perm)
         nodes, tris = int(wn.to(torch.int64).sum().item()), int(wt.to(torch.int64).sum().item())
-    node_bytes = WIDE_NODE_BYTES if wide else NODE_BYTES
+    node_bytes = (QUANT_NODE_BYTES if opts.flags & H.TRACE_QUANT else WIDE_NODE_BYTES) if wide else NODE_BYTES
     return dict(node_fetches_per_ray=round(nodes / R, 3), tri_fetches_per_ray=round(tris / R, 3),
                 node_bytes=node_bytes, bytes_per_ray=round((node_bytes * nodes + TRI_BYTES * tris) / R, 1))
 
@@ -955,7 +964,7 @@ def roofline_of(H, R, trace_ms_mean, opts, model, counted):
     achieved = bytes_per_launch / (trace_ms_mean * 1e-3) / 1e9
     kernel = kernel_name(H, opts)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kernel),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kernel, opts),
                     kernel=kernel + "<closest>", launch_ms=round(trace_ms_mean, 4), bytes_per_ray=round(per_ray + io, 1),
                     numerator=numerator)
     if counted is not None:
