@@ -220,7 +220,7 @@ def main(argv=None):
                        perm=torch.empty(R, dtype=torch.int32, device=dev),
                        ws=torch.empty(H.sort_workspace_bytes(R, k), dtype=torch.uint8, device=dev))
 
-    def run(method: str, evs=None, rr=None, closest=True, out=None, b=None):
+    def run(method: str, evs=None, rr=None, closest=True, out=None, b=None, opts=None):
         rr = rays if rr is None else rr
         out = hits if out is None else out
         b = bufs.get(method) if b is None else b
@@ -242,7 +242,7 @@ def main(argv=None):
             evs[1].record()
         if evs:
             evs[2].record()
-        H.trace(bvh, rr, perm, closest=closest, out=out, opts=c["opts"])
+        H.trace(bvh, rr, perm, closest=closest, out=out, opts=c["opts"] if opts is None else opts)
         if evs:
             evs[3].record()
 
@@ -277,7 +277,8 @@ def main(argv=None):
     composition = (cut_composition(H, cuts[head], tris_h.shape[0], conf[head]["key_bits"] - conf[head]["skip"])
                    if head in cuts else None)
 
-    # any-hit (shadow) rays, each method in its secondary-ray configuration
+    # any-hit (shadow) rays, each method with its secondary-ray key (cut, key length, skipped bits)
+    # and its trace options tuned on the shadow rays in its own order
     shadow_res = None
     if shadow is not None:
         S = shadow.shape[0]
@@ -290,17 +291,23 @@ def main(argv=None):
                 sb = dict(keys=torch.empty(S, dtype=torch.int32 if k <= 32 else torch.int64, device=dev),
                           perm=torch.empty(S, dtype=torch.int32, device=dev),
                           ws=torch.empty(H.sort_workspace_bytes(S, k), dtype=torch.uint8, device=dev))
+            s_opts = conf[m]["opts"]
+            if args.tune:
+                run(m, rr=shadow, closest=False, out=occ, b=sb)     # leaves the order in sb["perm"]
+                s_opts = AT.tune_trace(bvh, shadow, sb["perm"] if sb else None, closest=False,
+                                       candidates=AT.WIDE)[0]
             times = []
             for s in range(args.warmup + args.steps):
                 a, b = ev(), ev()
                 a.record()
-                run(m, rr=shadow, closest=False, out=occ, b=sb)
+                run(m, rr=shadow, closest=False, out=occ, b=sb, opts=s_opts)
                 b.record()
                 torch.cuda.synchronize()
                 if s >= args.warmup:
                     times.append(a.elapsed_time(b))
             ms = float(np.median(times))
-            shadow_res[m] = dict(ms=round(ms, 4), mrays_s=round(S / (ms * 1e-3) / 1e6, 2))
+            shadow_res[m] = dict(ms=round(ms, 4), mrays_s=round(S / (ms * 1e-3) / 1e6, 2),
+                                 trace_opts=AT.opts_dict(s_opts))
             del sb
         log("shadow Mrays/s: " + ", ".join(f"{m} {shadow_res[m]['mrays_s']:.0f}" for m in conf))
 
@@ -969,6 +976,11 @@ def roofline_of(H, R, trace_ms_mean, opts, model, counted):
                     numerator=numerator)
     if counted is not None:
         roofline["kernel_counted_bytes_per_ray"] = round(counted["bytes_per_ray"] + io, 1)
+    if roofline["traffic"]:
+        # where the launch sits against HBM by the bytes it actually moves (PMC): far below, because
+        # the modelled fetch stream is served by L2 and the Infinity Cache; the kernel is bound by
+        # vector-memory instruction issue instead
+        roofline["traffic_frac"] = round(roofline["traffic"] / (trace_ms_mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     log(f"roofline: {achieved:.0f} GB/s of algorithmic traffic ({roofline['frac']:.3f} of HBM peak) from the "
         f"{numerator}; {per_ray + io:.0f} B/ray" +
         (f" (kernel-counted {counted['bytes_per_ray'] + io:.0f} B/ray)" if counted else ""))
