@@ -453,6 +453,16 @@ def compact_line(full: dict, args, workload: str) -> dict:
     if d:
         line["drift_best_mrays_s"] = {bn: list(max((r["mrays_s"], r["method"]) for r in v["rows"]))
                                       for bn, v in d["bounces"].items()}
+        # the best HCC row (C = K, encode + sort included) against NoSort on the scene that does
+        # not fit the caches
+        ratio = {}
+        for bn, v in d["bounces"].items():
+            hcc = [r["mrays_s"] for r in v["rows"] if r["method"].startswith("hcc")]
+            base = [r["mrays_s"] for r in v["rows"] if r["method"] == "nosort"]
+            if hcc and base:
+                ratio[bn] = round(max(hcc) / base[0], 3)
+        if ratio:
+            line["drift_hcc_vs_nosort"] = ratio
     line["roofline"] = full.get("roofline")
     line["cpu_baseline"] = full.get("cpu_baseline")
     line["full_record"] = args.full_out
@@ -898,6 +908,9 @@ def run_drift(H, args):
         for k in ks:
             for v in (dict(mode="twopoint", K=k), dict(mode="hcc", C=k, K=k), dict(mode="grid", K=k)):
                 rows.append(measure_variant(H, bvh, rd, v, sorted_opts, args.drift_reps))
+        # the paper's two-level code (a 16- and a 32-bit key from 8 + 8 and 16 + 16 cut nodes)
+        for v in (dict(mode="mlhcc", top=8, low=8, K=16), dict(mode="mlhcc", top=16, low=16, K=32)):
+            rows.append(measure_variant(H, bvh, rd, v, sorted_opts, args.drift_reps))
         out["bounces"][str(bounce)] = dict(rays=int(rd.shape[0]), rows=rows, trace_opts=AT.opts_dict(opts),
                                            sorted_trace_opts=AT.opts_dict(sorted_opts))
         log(f"drift bounce {bounce} ({rd.shape[0]} rays): " +

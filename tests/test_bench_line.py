@@ -39,7 +39,9 @@ def _full():
         "serve": dict(loads={rho: dict(plain=dict(p50_ms=22.639, p99_ms=75.06, mrays_s=420.0),
                                        continuous=dict(p50_ms=1.806, p99_ms=10.04, mrays_s=425.5))
                              for rho in ("0.5", "0.8", "0.95")}),
-        "drift": dict(bounces={b: dict(rows=rows) for b in ("1", "2")}),
+        "drift": dict(bounces={b: dict(rows=rows + [dict(method="nosort", mrays_s=500.0),
+                                                    dict(method="hcc C=16 K=16", mrays_s=535.0)])
+                               for b in ("1", "2")}),
         "roofline": dict(bound="hbm", achieved=6924.4, peak=8000.0, unit="GB/s", frac=0.8656, traffic=10334608383,
                          kernel="k_trace_wide<closest>", launch_ms=5.3101, bytes_per_ray=2222.7,
                          numerator="oracle wave model (BVH2 nodes, 64-lane waves)", kernel_counted_bytes_per_ray=2300.1),
