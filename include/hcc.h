@@ -154,6 +154,19 @@ hcc_status hcc_bvh_info(hcc_bvh bvh, uint32_t* n_tris, uint32_t* n_nodes, float*
  * lambda of the most recent hcc_select_cut (0.125 before the first). */
 hcc_status hcc_bvh_export(hcc_bvh bvh, uint32_t* h_child, uint32_t* h_leaf_prim, float* h_boxes, double* h_had);
 
+/* Copy the 4-wide traversal nodes to host memory (parity checks, inspection; the BVH2 collapsed
+ * top down, see HCC_TRACE_WIDE and HCC_TRACE_QUANT).  Blocking.  Any pointer may be NULL; call
+ * with null buffers first to learn *n_wide (0 for a one-triangle BVH).
+ * h_wide: n_wide x 128 bytes, wide node i in level order (the root first): 6 x 4 float32 planes
+ *   (lower x of slots 0..3, lower y, lower z, upper x, upper y, upper z), 4 uint32 refs (an
+ *   internal member's wide node index; 0x80000000 | leaf index for a triangle, the leaf index as
+ *   in h_leaf_prim; 0xFFFFFFFF for an empty slot), 4 uint32 zero.
+ * h_quant: n_wide x 64 bytes, the quantised copy: float32 p.x p.y p.z s.x s.y s.z (corner and
+ *   power-of-two step per axis), then uint32 step words lower x, upper x, lower y, upper y, lower
+ *   z, upper z (slot j in byte j; plane = fmaf(step, s, p) rounded once), then the 4 refs.
+ * *quant_ok: 1 when the quantised nodes exist and the quantised traversal is offered. */
+hcc_status hcc_bvh_export_wide(hcc_bvh bvh, uint32_t* n_wide, void* h_wide, void* h_quant, uint32_t* quant_ok);
+
 void hcc_bvh_destroy(hcc_bvh bvh);
 
 /* ---------------------------------------------------------------------------------------

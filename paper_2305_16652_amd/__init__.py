@@ -59,6 +59,7 @@ _SIGS = {
     "hcc_build_bvh": [_P, _U32, _P, C.POINTER(_H)],
     "hcc_bvh_info": [_H, C.POINTER(_U32), C.POINTER(_U32), _P, C.POINTER(C.c_size_t)],
     "hcc_bvh_export": [_H, _P, _P, _P, _P],
+    "hcc_bvh_export_wide": [_H, C.POINTER(_U32), _P, _P, C.POINTER(_U32)],
     "hcc_select_cut": [_H, _U32, C.c_double, _P, C.POINTER(_H)],
     "hcc_cut_info": [_H, C.POINTER(_U32)],
     "hcc_cut_export": [_H, _P, _P, _P],
@@ -175,6 +176,25 @@ class BVH:
         _check(lib.hcc_bvh_export(self._h, child.ctypes.data_as(_P), leaf.ctypes.data_as(_P),
                                   boxes.ctypes.data_as(_P), had.ctypes.data_as(_P)))
         return child, leaf, boxes, had
+
+    def export_wide(self):
+        """The 4-wide traversal nodes as numpy: (planes (w,6,4) f32, refs (w,4) u32) of the exact
+        nodes, (corner_step (w,6) f32, steps (w,6) u32, refs (w,4) u32) of the quantised ones, and
+        whether the quantised traversal is offered."""
+        import numpy as np
+        nw, ok = _U32(), _U32()
+        _check(lib.hcc_bvh_export_wide(self._h, C.byref(nw), None, None, C.byref(ok)))
+        w = nw.value
+        wide = np.zeros((w, 32), np.uint32)
+        quant = np.zeros((w, 16), np.uint32)
+        _check(lib.hcc_bvh_export_wide(self._h, C.byref(nw), wide.ctypes.data_as(_P), quant.ctypes.data_as(_P),
+                                       C.byref(ok)))
+        planes = wide[:, :24].copy().view(np.float32).reshape(w, 6, 4)
+        exact_refs = wide[:, 24:28].copy()
+        corner_step = quant[:, :6].copy().view(np.float32)
+        steps = quant[:, 6:12].copy()
+        quant_refs = quant[:, 12:16].copy()
+        return (planes, exact_refs), (corner_step, steps, quant_refs), bool(ok.value)
 
     def __del__(self):
         h = getattr(self, "_h", None)

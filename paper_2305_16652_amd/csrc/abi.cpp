@@ -280,6 +280,22 @@ __attribute__((visibility("default"))) hcc_status hcc_bvh_export(hcc_bvh bvh, ui
     return HCC_OK;
 }
 
+__attribute__((visibility("default"))) hcc_status hcc_bvh_export_wide(hcc_bvh bvh, uint32_t* n_wide, void* h_wide,
+                                                                      void* h_quant, uint32_t* quant_ok) {
+    if (!valid_bvh(bvh)) return fail(HCC_ERR_INVALID, "hcc_bvh_export_wide: invalid handle");
+    if (n_wide) *n_wide = bvh->n_wide;
+    if (quant_ok) *quant_ok = bvh->quant_ok ? 1u : 0u;
+    if (h_wide && bvh->n_wide)
+        HCC_HIP(hipMemcpy(h_wide, bvh->wnodes, sizeof(hcc::Node4) * bvh->n_wide, hipMemcpyDeviceToHost));
+    if (h_quant && bvh->n_wide) {
+        if (bvh->qnodes)
+            HCC_HIP(hipMemcpy(h_quant, bvh->qnodes, sizeof(hcc::Node4Q) * bvh->n_wide, hipMemcpyDeviceToHost));
+        else
+            std::memset(h_quant, 0, sizeof(hcc::Node4Q) * bvh->n_wide);
+    }
+    return HCC_OK;
+}
+
 __attribute__((visibility("default"))) void hcc_bvh_destroy(hcc_bvh bvh) {
     if (valid_bvh(bvh)) free_bvh(bvh);
 }

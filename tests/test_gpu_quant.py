@@ -149,3 +149,73 @@ def test_quantised_nodes_need_the_wide_traversal(H):
         H.trace(bvh, rd, opts=H.TraceOpts(0, 0, 0, 1, 32, 64, 0, H.TRACE_QUANT))
     with pytest.raises(H.HCCError):
         H.trace(bvh, rd, opts=H.TraceOpts(64, 0, 0, 0, 0, 0, 0, H.TRACE_QUANT))
+
+
+def _decode(q, s, p):
+    """The traversal's decode, fmaf(q, s, p): q * s is exact in float32, so one float32 add."""
+    return (q.astype(np.float32) * s.astype(np.float32)).astype(np.float32) + p.astype(np.float32)
+
+
+@pytest.mark.parametrize("kind", ["tiny", "cluster", "flat", "far", "scales", "negative"])
+def test_wide_and_quantised_nodes_structure(H, kind):
+    """The 4-wide nodes against the exported BVH2, and the quantised nodes against the 4-wide
+    ones, on the host: every triangle is the leaf slot of exactly one wide node, with its BVH2
+    leaf box bit for bit; an internal slot's box is the exact union of its wide node's slot boxes
+    and every wide node but the root is one slot's; the root's slots cover the BVH2 root box.
+    Quantised: the same refs; per axis the corner is the least lower plane and the step a power of
+    two whose step 255 reaches the node's upper plane; every slot's decoded lower plane is the
+    largest step at most its lower plane, its decoded upper plane the smallest step at least its
+    upper plane; empty slots hold steps 255 / 0."""
+    _say(f"wide node structure, scene {kind}")
+    if kind == "tiny":
+        tris = W.tiny_scene().tris
+    elif kind == "cluster":
+        tris = W.cluster_scene(50_000, seed=7).tris
+    else:
+        tris = scene(kind)
+    bvh = H.build_bvh(torch.from_numpy(np.ascontiguousarray(tris, np.float32)).cuda())
+    child, leaf_prim, boxes, had = bvh.export()
+    (planes, refs), (cs, steps, qrefs), ok = bvh.export_wide()
+    n = tris.shape[0]
+    ni = n - 1
+    EMPTY, LEAF = np.uint32(0xFFFFFFFF), np.uint32(0x80000000)
+    w = planes.shape[0]
+    assert ok and w > 0
+    full = refs != EMPTY
+    is_leaf = full & ((refs & LEAF) != 0)
+    is_int = full & ~is_leaf
+    # leaves: each triangle once, with its BVH2 leaf box
+    li = (refs[is_leaf] & ~LEAF).astype(np.int64)
+    assert np.array_equal(np.sort(li), np.arange(n))
+    wl, jl = np.nonzero(is_leaf)
+    got = planes[wl, :, jl]                           # (k, 6): lo.xyz, hi.xyz
+    assert np.array_equal(got.view(np.uint32), boxes[ni + li].view(np.uint32))
+    # internal slots: wide nodes 1..w-1 once each, box = union of that node's slot boxes
+    ci = refs[is_int].astype(np.int64)
+    assert np.array_equal(np.sort(ci), np.arange(1, w))
+    lo = np.where(full[:, None, :], planes[:, 0:3, :], np.float32(np.inf)).min(axis=2)
+    hi = np.where(full[:, None, :], planes[:, 3:6, :], np.float32(-np.inf)).max(axis=2)
+    wi, ji = np.nonzero(is_int)
+    assert np.array_equal(planes[wi, 0:3, ji], lo[ci]) and np.array_equal(planes[wi, 3:6, ji], hi[ci])
+    assert np.array_equal(np.concatenate([lo[0], hi[0]]), boxes[0])
+    # quantised copy
+    assert np.array_equal(qrefs, refs)
+    p, s = cs[:, 0:3], cs[:, 3:6]
+    assert np.array_equal(p, lo)
+    m, e = np.frexp(s.astype(np.float64))
+    assert (m == 0.5).all()                           # powers of two
+    assert (_decode(np.full_like(p, 255), s, p) >= hi).all()
+    for a in range(3):
+        for j in range(4):
+            ql = (steps[:, 2 * a] >> np.uint32(8 * j)) & np.uint32(255)
+            qh = (steps[:, 2 * a + 1] >> np.uint32(8 * j)) & np.uint32(255)
+            f = full[:, j]
+            assert (ql[~f] == 255).all() and (qh[~f] == 0).all()
+            L, U = planes[f, a, j], planes[f, 3 + a, j]
+            qlf, qhf, pf, sf = ql[f], qh[f], p[f, a], s[f, a]
+            dl, dh = _decode(qlf, sf, pf), _decode(qhf, sf, pf)
+            assert (dl <= L).all() and (dh >= U).all()
+            up = qlf < 255
+            assert (_decode(qlf[up] + 1, sf[up], pf[up]) > L[up]).all()
+            down = qhf > 0
+            assert (_decode(qhf[down] - 1, sf[down], pf[down]) < U[down]).all()
