@@ -105,7 +105,7 @@ typedef struct hcc_trace_opts {
                                  either way. */
     uint32_t waves;           /* persistent: wavefronts launched (0 = 8192) */
     uint32_t flags;           /* HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB | HCC_TRACE_SPREAD |
-                                 HCC_TRACE_QUANT */
+                                 HCC_TRACE_QUANT | HCC_TRACE_PACKET */
 } hcc_trace_opts;
 
 /* hcc_trace_opts.flags */
@@ -131,6 +131,19 @@ typedef struct hcc_trace_opts {
                                    boxes the exact nodes pass and finds the same closest or any hit.
                                    HCC_ERR_UNSUPPORTED without HCC_TRACE_WIDE, or for a BVH with a
                                    non-finite box */
+#define HCC_TRACE_PACKET 32u    /* with HCC_TRACE_WIDE: wavefront packets instead of one traversal per lane.
+                                   Each wavefront takes 64 consecutive rays of the trace order and walks
+                                   the 4-wide tree once for all of them: a node is visited when some
+                                   lane's child-box test passes, and its fetch is one load shared by the
+                                   wavefront.  Pays where the 64 rays are coherent (primary and shadow
+                                   rays, reordered rays: the per-warp coherence of Section 3.1); costs
+                                   many times more steps on incoherent rays.  The same hits as the
+                                   per-lane traversal, except that a lane also tests triangles whose
+                                   boxes only other lanes pass, so a ray passing within rounding of a
+                                   triangle's edge may report that triangle (as HCC_TRACE_QUANT).
+                                   HCC_TRACE_QUANT, HCC_TRACE_SLAB, HCC_TRACE_SPREAD, xcd_remap and
+                                   waves apply; chunk (64 rays per packet), refill and stack do not.
+                                   HCC_ERR_UNSUPPORTED without HCC_TRACE_WIDE and in hcc_trace_count */
 
 /* ---------------------------------------------------------------------------------------
  * hcc_build_bvh -- linear BVH over n_tris triangles (Section 3.1: the acceleration structure

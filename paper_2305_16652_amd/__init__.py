@@ -384,7 +384,7 @@ def trace(bvh: BVH, rays: torch.Tensor, perm=None, closest: bool = True, out=Non
     return out
 
 
-TRACE_SPECULATE, TRACE_WIDE, TRACE_SLAB, TRACE_SPREAD, TRACE_QUANT = 1, 2, 4, 8, 16
+TRACE_SPECULATE, TRACE_WIDE, TRACE_SLAB, TRACE_SPREAD, TRACE_QUANT, TRACE_PACKET = 1, 2, 4, 8, 16, 32
 BATCH_STACK_SCRATCH = 3
 lib.hcc_trace_count.argtypes = [_H, _P, _P, _U32, C.c_int, _P, _P, C.POINTER(TraceOpts), _P, _P]
 lib.hcc_trace_count.restype = C.c_int

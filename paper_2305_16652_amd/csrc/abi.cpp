@@ -436,7 +436,8 @@ __attribute__((visibility("default"))) hcc_status hcc_trace_ex(hcc_bvh bvh, cons
     if (st != HCC_OK || n == 0) return st;
     hcc_trace_opts o{};
     if (opts) o = *opts;
-    if (o.flags & ~(HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB | HCC_TRACE_SPREAD | HCC_TRACE_QUANT))
+    if (o.flags & ~(HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB | HCC_TRACE_SPREAD | HCC_TRACE_QUANT |
+                    HCC_TRACE_PACKET))
         return fail(HCC_ERR_INVALID, "hcc_trace: unknown opts.flags bits");
     return trace(bvh, d_rays, d_perm, n, mode == HCC_TRACE_CLOSEST, d_hits, d_occluded, o, S(stream));
 }
@@ -452,7 +453,8 @@ __attribute__((visibility("default"))) hcc_status hcc_trace_count(hcc_bvh bvh, c
     if (!d_counts) return fail(HCC_ERR_INVALID, "hcc_trace_count: null d_counts");
     hcc_trace_opts o{};
     if (opts) o = *opts;
-    if (o.flags & ~(HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB | HCC_TRACE_SPREAD | HCC_TRACE_QUANT))
+    if (o.flags & ~(HCC_TRACE_SPECULATE | HCC_TRACE_WIDE | HCC_TRACE_SLAB | HCC_TRACE_SPREAD | HCC_TRACE_QUANT |
+                    HCC_TRACE_PACKET))
         return fail(HCC_ERR_INVALID, "hcc_trace_count: unknown opts.flags bits");
     return trace_count(bvh, d_rays, d_perm, n, mode == HCC_TRACE_CLOSEST, d_hits, d_occluded, o,
                        (unsigned long long*)d_counts, S(stream));

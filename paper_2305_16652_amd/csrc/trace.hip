@@ -701,6 +701,177 @@ __global__ __launch_bounds__(64) void k_trace_wide(const Node4* __restrict__ wn,
     ch.finish();
 }
 
+// Wavefront packets over the 4-wide nodes.  A wavefront takes 64 consecutive rays of the trace
+// order (one chunk of 64 from the stream's counter) and walks the tree once for all of them: the
+// node of a step is the same on every lane, so it is fetched by one scalar load shared by the
+// wavefront, and the vector memory path (which bounds the per-lane traversal above) carries only
+// the rays and the results.  Each lane tests its own ray against the node's four child boxes
+// (culling with its own best distance); a child is visited when some lane's test passes, the
+// triangles of hit leaves are tested at once by the lanes that hit them, and the hit internal
+// children are taken in the entry order of the lowest lane that hits one of them (descend into
+// the first, push the others last first).  The stack is shared by the wavefront: entry e sits in
+// lane e mod 64 of register e / 64, so a push writes one lane and a pop reads one.  An any-hit
+// packet ends once every lane has found a hit.  A packet costs one step per node of the union of
+// its rays' traversals: close to one ray's for coherent rays, many times that for incoherent ones.
+struct PacketStack {
+    uint32_t r0 = 0, r1 = 0, r2 = 0;   // kWideStack = 3 x 64 entries
+    __device__ void push(uint32_t sp, uint32_t x) {
+        const bool here = __lane_id() == (sp & 63u);
+        const uint32_t g = sp >> 6;
+        if (g == 0) r0 = here ? x : r0;
+        else if (g == 1) r1 = here ? x : r1;
+        else r2 = here ? x : r2;
+    }
+    __device__ uint32_t pop(uint32_t sp) const {
+        const uint32_t l = sp & 63u, g = sp >> 6;
+        return __builtin_amdgcn_readlane(g == 0 ? r0 : (g == 1 ? r1 : r2), l);
+    }
+};
+static_assert(kWideStack == 3 * 64, "the packet stack holds three registers of 64 entries");
+
+// Order-preserving map of a float to an unsigned key (negative values flipped).
+__device__ __forceinline__ uint32_t ordered_bits(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ void cswap_u(uint32_t& ka, uint32_t& ia, uint32_t& kb, uint32_t& ib) {
+    const bool sw = kb < ka;
+    const uint32_t k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+    const uint32_t i0 = sw ? ib : ia, i1 = sw ? ia : ib;
+    ka = k0;
+    kb = k1;
+    ia = i0;
+    ib = i1;
+}
+
+template <bool kClosest>
+__global__ __launch_bounds__(64) void k_trace_packet(const Node4* __restrict__ wn, const Node4Q* __restrict__ qn,
+                                                     const Tri* __restrict__ tris, uint32_t n_int,
+                                                     const float4* __restrict__ rays, const uint32_t* __restrict__ perm,
+                                                     uint32_t n, float4* __restrict__ hits, uint8_t* __restrict__ occ,
+                                                     uint32_t deal, uint32_t slab, uint32_t qslot) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    Chunks ch;
+    ch.init(qslot, n, 64u, deal);
+    const uint32_t lane = __lane_id();
+    while (true) {
+        ch.advance();
+        if (ch.next >= ch.end) break;
+        const uint32_t k = ch.next + lane;
+        bool valid = k < ch.end;
+        ch.next = ch.end;
+        uint32_t rid = 0;
+        if (valid) {
+            rid = perm ? perm[k] : k;
+            valid = rid < n;
+        }
+        float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, tmin = 0, tmax = 0;
+        if (valid) {
+            const float4 ra = rays[2 * (size_t)rid];
+            const float4 rb = rays[2 * (size_t)rid + 1];
+            ox = ra.x; oy = ra.y; oz = ra.z; tmin = ra.w;
+            dx = rb.x; dy = rb.y; dz = rb.z; tmax = rb.w;
+        }
+        const float ix = 1.0f / dx, iy = 1.0f / dy, iz = 1.0f / dz;
+        const WideRay wr = wide_ray(ox, oy, oz, ix, iy, iz);
+        float best_t = tmax, best_u = 0.0f, best_v = 0.0f;
+        uint32_t best_prim = kMissPrim;
+        bool found = false;
+
+        auto test_tri = [&](const Tri& tr) {
+            const uint32_t prim = __float_as_uint(tr.r.y);
+            float t, u, v;
+            const bool hit = tri_test(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v);
+            if (!kClosest) {
+                found = found || hit;
+            } else {
+                const bool take = hit && (t < best_t || (t == best_t && prim < best_prim));
+                best_t = take ? t : best_t;
+                best_u = take ? u : best_u;
+                best_v = take ? v : best_v;
+                best_prim = take ? prim : best_prim;
+                found = found || take;
+            }
+        };
+
+        // the walk, specialised on the (packet-uniform) form of the child test: 0 slab test on the
+        // exact nodes, 2 slab test / 3 selected planes on the quantised nodes
+        auto walk = [&](auto kind) {
+            constexpr int kKind = decltype(kind)::value;
+            PacketStack st;
+            uint32_t sp = 0, node = 0;
+            while (true) {
+                node = __builtin_amdgcn_readfirstlane(node);
+                const bool alive = valid && (kClosest || !found);
+                if (!kClosest && __ballot(alive) == 0) break;
+                uint4 r;
+                bool hh[4];
+                float tt[4];
+                if constexpr (kKind >= 2)
+                    wide_test_q<kKind == 3>(qn, node, wr, ox, oy, oz, ix, iy, iz, tmin, kClosest ? best_t : tmax, r, hh,
+                                            tt);
+                else
+                    wide_test<false>(wn, node, wr, ox, oy, oz, ix, iy, iz, tmin, kClosest ? best_t : tmax, r, hh, tt);
+                const uint32_t refs[4] = {r.x, r.y, r.z, r.w};
+                // leaves first: the hits they give shrink every lane's segment before the descent
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bool hl = alive && hh[j] && (refs[j] & kWideLeaf);
+                    if (__ballot(hl) != 0) {
+                        const Tri tr = tris[refs[j] & ~kWideLeaf];
+                        if (hl && (kClosest || !found)) test_tri(tr);
+                    }
+                }
+                // internal children some lane hits, keyed by the entry distance of the lowest such
+                // lane (children that lane misses after those it hits, missed children last)
+                bool hi[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) hi[j] = alive && hh[j] && !(refs[j] & kWideLeaf);
+                const uint64_t any = __ballot(hi[0] || hi[1] || hi[2] || hi[3]);
+                if (any == 0) {
+                    if (sp == 0) break;
+                    node = st.pop(--sp);
+                    continue;
+                }
+                const uint32_t rep = (uint32_t)__ffsll((unsigned long long)any) - 1u;
+                uint32_t key[4], id[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bool some = __ballot(hi[j]) != 0;
+                    const uint32_t mine = __builtin_amdgcn_readlane(hi[j] ? ordered_bits(tt[j]) : 0xFFFFFFFEu, rep);
+                    key[j] = some ? mine : 0xFFFFFFFFu;
+                    id[j] = some ? refs[j] : kNone;
+                }
+                cswap_u(key[0], id[0], key[1], id[1]);
+                cswap_u(key[2], id[2], key[3], id[3]);
+                cswap_u(key[0], id[0], key[2], id[2]);
+                cswap_u(key[1], id[1], key[3], id[3]);
+                cswap_u(key[1], id[1], key[2], id[2]);
+                if (id[3] != kNone && sp < (uint32_t)kWideStack) st.push(sp++, id[3]);
+                if (id[2] != kNone && sp < (uint32_t)kWideStack) st.push(sp++, id[2]);
+                if (id[1] != kNone && sp < (uint32_t)kWideStack) st.push(sp++, id[1]);
+                node = id[0];
+            }
+        };
+        if (!qn) {
+            walk(std::integral_constant<int, 0>{});
+        } else if (!slab && __ballot(valid && !wr.fast) == 0) {
+            walk(std::integral_constant<int, 3>{});
+        } else {
+            walk(std::integral_constant<int, 2>{});
+        }
+        if (valid) {
+            if (kClosest)
+                hits[rid] = make_float4(found ? best_t : INFINITY, __uint_as_float(found ? best_prim : kMissPrim),
+                                        found ? best_u : 0.0f, found ? best_v : 0.0f);
+            else
+                occ[rid] = found ? 1 : 0;
+        }
+    }
+    ch.finish();
+}
+
 template <bool kClosest, int kStack, int kBlock, bool kStats>
 void launch(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, uint32_t n, hcc_hit* hits, uint8_t* occ,
             uint32_t remap, uint32_t* cn, uint32_t* ct, uint32_t* wn, uint32_t* wt, hipStream_t stream) {
@@ -770,6 +941,23 @@ hcc_status trace_persistent(const hcc_bvh_s* b, const hcc_ray* rays, const uint3
     const uint32_t deal = (o.xcd_remap ? 1u : 0u) | ((o.flags & HCC_TRACE_SPREAD) ? 2u : 0u);
     const float4* r = (const float4*)rays;
     float4* h = (float4*)hits;
+    if constexpr (!kStats) {
+        if (o.flags & HCC_TRACE_PACKET) {
+            // one chunk of 64 rays per packet; the wide flags (QUANT, SLAB, SPREAD) apply
+            const uint32_t packets = (uint32_t)(((uint64_t)n + 63) / 64);
+            const uint32_t pw = std::min<uint32_t>(packets, o.waves ? o.waves : 8192u);
+            const Node4Q* qn = (o.flags & HCC_TRACE_QUANT) ? b->qnodes : nullptr;
+            const uint32_t sl = (o.flags & HCC_TRACE_SLAB) ? 1u : 0u;
+            if (closest)
+                k_trace_packet<true><<<pw, 64, 0, s>>>(b->wnodes, qn, b->tris, b->n_int, r, perm, n, h, occ, deal, sl,
+                                                       qslot);
+            else
+                k_trace_packet<false><<<pw, 64, 0, s>>>(b->wnodes, qn, b->tris, b->n_int, r, perm, n, h, occ, deal, sl,
+                                                        qslot);
+            HCC_HIP(hipGetLastError());
+            return HCC_OK;
+        }
+    }
     if (o.flags & HCC_TRACE_WIDE) {
         // stack: scratch (HCC_STACK_SCRATCH, and always when counting), the first 16 entries in
         // LDS (HCC_STACK_SHORT) or the first 24 (HCC_STACK_LDS)
@@ -830,6 +1018,8 @@ hcc_status trace(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* perm, 
     if ((o.flags & HCC_TRACE_QUANT) && (!(o.flags & HCC_TRACE_WIDE) || (b->n_int > 0 && !b->quant_ok)))
         return fail(HCC_ERR_UNSUPPORTED, "hcc_trace: HCC_TRACE_QUANT needs HCC_TRACE_WIDE and a BVH whose boxes are "
                                          "finite");
+    if ((o.flags & HCC_TRACE_PACKET) && !(o.flags & HCC_TRACE_WIDE))
+        return fail(HCC_ERR_UNSUPPORTED, "hcc_trace: HCC_TRACE_PACKET needs HCC_TRACE_WIDE");
     if ((o.persistent || (o.flags & HCC_TRACE_WIDE)) && b->n_int > 0)
         return trace_persistent<false>(b, rays, perm, n, closest, hits, occ, o, nullptr, s);
     const uint32_t block = o.block ? o.block : 64;
@@ -845,6 +1035,8 @@ hcc_status trace_count(const hcc_bvh_s* b, const hcc_ray* rays, const uint32_t* 
                        hipStream_t s) {
     if (!(o.persistent || (o.flags & HCC_TRACE_WIDE)) || b->n_int == 0)
         return fail(HCC_ERR_UNSUPPORTED, "hcc_trace_count: counts the persistent launches only");
+    if (o.flags & HCC_TRACE_PACKET)
+        return fail(HCC_ERR_UNSUPPORTED, "hcc_trace_count: packet launches are not counted");
     if ((o.flags & HCC_TRACE_QUANT) && (!(o.flags & HCC_TRACE_WIDE) || !b->quant_ok))
         return fail(HCC_ERR_UNSUPPORTED, "hcc_trace_count: HCC_TRACE_QUANT needs HCC_TRACE_WIDE and a BVH whose "
                                          "boxes are finite");

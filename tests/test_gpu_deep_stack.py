@@ -108,6 +108,8 @@ DEEP_OPTS = [
     (64, 2, 0, 1, 32, 64, 0, 6 | 8),    # 4-wide, slab child test, spread dealing
     (64, 2, 0, 1, 32, 64, 0, 2 | 16),   # quantised 4-wide nodes, 16 LDS entries + scratch
     (64, 0, 0, 1, 32, 64, 0, 6 | 16),   # quantised 4-wide nodes, slab child test, scratch only
+    (0, 0, 0, 1, 0, 0, 0, 2 | 32),      # wavefront packets, shared register stack
+    (0, 0, 0, 1, 0, 0, 0, 2 | 16 | 32), # wavefront packets on the quantised nodes
 ]
 
 

@@ -196,8 +196,14 @@ OPTS = [(128, 1, 0, 0, 0, 0, 0), (64, 1, 1, 0, 0, 0, 0), (256, 1, 0, 0, 0, 0, 0)
         (0, 2, 0, 1, 32, 64, 0, 8 | 2), (0, 0, 0, 1, 16, 256, 5, 8 | 1),
         # quantised 4-wide nodes (flags bit 4): selected planes, slab test, spread dealing, stacks
         (0, 2, 0, 1, 32, 64, 0, 16 | 2), (0, 0, 0, 1, 16, 256, 5, 16 | 2), (0, 1, 0, 1, 1, 64, 3, 16 | 4 | 2),
-        (64, 2, 0, 1, 32, 64, 0, 16 | 8 | 2), (0, 2, 1, 1, 24, 128, 7, 16 | 2)]
+        (64, 2, 0, 1, 32, 64, 0, 16 | 8 | 2), (0, 2, 1, 1, 24, 128, 7, 16 | 2),
+        # wavefront packets (flags bit 5) on the exact and quantised nodes, slab test, spread and
+        # XCD-contiguous dealing, few wavefronts
+        (0, 0, 0, 1, 0, 0, 0, 32 | 2), (0, 0, 0, 1, 0, 0, 3, 32 | 16 | 2), (0, 0, 0, 1, 0, 0, 0, 32 | 16 | 4 | 2),
+        (0, 0, 1, 1, 0, 0, 5, 32 | 16 | 8 | 2), (0, 0, 0, 1, 0, 0, 1, 32 | 4 | 2)]
 WIDE = (0, 0, 0, 1, 32, 64, 0, 2)
+PACKET = (0, 0, 0, 1, 0, 0, 0, 32 | 2)
+PACKET_Q = (0, 0, 0, 1, 0, 0, 0, 32 | 16 | 2)
 
 
 @pytest.mark.parametrize("opt", OPTS)
@@ -280,7 +286,7 @@ def test_single_and_two_triangle_scenes(H):
             assert np.array_equal(H.select_cut(b, c).export()[0], O.select_cut(ob, O.had(ob), c))
         rays = np.array([[0.2, 0.2, 0, 0, 0, 0, 1, np.inf], [2, 2, 0, 0, 0, 0, 1, np.inf],
                          [0.2, 0.2, 0, 1.5, 0, 0, 1, np.inf], [0.2, 0.2, 0, 0, 0, 0, 1, 0.5]], np.float32)
-        for o in (None, H.TraceOpts(*WIDE)):
+        for o in (None, H.TraceOpts(*WIDE), H.TraceOpts(*PACKET), H.TraceOpts(*PACKET_Q)):
             hits = H.trace(b, _dev(rays), opts=o).cpu().numpy()
             assert_closest(hits, O.trace(ob, rays), rays, tris)
             assert_any(H.trace(b, _dev(rays), closest=False, opts=o).cpu().numpy(), O.trace(ob, rays, closest=False))
@@ -304,7 +310,7 @@ def test_degenerate_rays(H, gpu_bvh, tiny):
     rays[5::11, 4:7] = 0.0       # zero direction
     tris = tiny["spec"].tris
     for o in (None, H.TraceOpts(*WIDE), H.TraceOpts(*WIDE[:7], H.TRACE_WIDE | H.TRACE_SLAB),
-              H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 1)):
+              H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 1), H.TraceOpts(*PACKET), H.TraceOpts(*PACKET_Q)):
         assert_closest(H.trace(gpu_bvh, _dev(rays), opts=o).cpu().numpy(), O.trace(tiny["ob"], rays), rays, tris)
         assert_any(H.trace(gpu_bvh, _dev(rays), closest=False, opts=o).cpu().numpy(),
                    O.trace(tiny["ob"], rays, closest=False))
@@ -326,7 +332,7 @@ def test_nonfinite_origins(H, gpu_bvh, tiny):
     rays[21::64, 1] = np.inf
     rays[40::64, 2] = -np.inf
     tris = tiny["spec"].tris
-    for o in (None, H.TraceOpts(*WIDE), H.TraceOpts(64, 2, 0, 1, 32, 64, 0, H.TRACE_WIDE)):
+    for o in (None, H.TraceOpts(*WIDE), H.TraceOpts(64, 2, 0, 1, 32, 64, 0, H.TRACE_WIDE), H.TraceOpts(*PACKET_Q)):
         assert_closest(H.trace(gpu_bvh, _dev(rays), opts=o).cpu().numpy(), O.trace(tiny["ob"], rays), rays, tris)
         assert_any(H.trace(gpu_bvh, _dev(rays), closest=False, opts=o).cpu().numpy(),
                    O.trace(tiny["ob"], rays, closest=False))
@@ -355,7 +361,11 @@ def test_invalid_arguments(H, gpu_bvh):
     with pytest.raises(H.HCCError):
         H.trace(gpu_bvh, rays, opts=H.TraceOpts(64, 7, 0, 0, 0, 0, 0, 0))
     with pytest.raises(H.HCCError):
-        H.trace(gpu_bvh, rays, opts=H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 32))     # unknown flag bit
+        H.trace(gpu_bvh, rays, opts=H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 64))     # unknown flag bit
+    with pytest.raises(H.HCCError):
+        H.trace(gpu_bvh, rays, opts=H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 32))     # packets without 4-wide
+    with pytest.raises(H.HCCError):
+        H.trace_count(gpu_bvh, rays, opts=H.TraceOpts(*PACKET))                 # packets are not counted
     with pytest.raises(H.HCCError):
         H.trace(gpu_bvh, rays, opts=H.TraceOpts(0, 0, 0, 1, 32, 64, 0, 16))     # quantised nodes without 4-wide
     other = H.build_bvh(torch.tensor([[0, 0, 0, 1, 0, 0, 0, 1, 0]], dtype=torch.float32, device="cuda"))
