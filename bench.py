@@ -15,9 +15,10 @@ size C from 32 to 4,096 with C >= K -- the frame configuration's cut sizes -- or
 C = K pairs with --paper-exact; key lengths 16 / 32 / 64; low key bits left out of the sort).  Prints one JSON line on stdout; progress goes to stderr.
 
 Beside the headline the line carries: the roofline of the trace kernel, the CPU oracle's rate,
-a grid of reordering methods on the same batch, bounces 2 and 3 of the frame, the 10M-triangle
-boundary-drift workload, the uneven-batch engine workload and the request-server workload
-(each can be skipped with its --no-... flag).
+a grid of reordering methods on the same batch, wavefront packets against per-lane launches by ray
+order (primary and shadow rays), bounces 2 and 3 of the frame, the 10M-triangle boundary-drift
+workload, the uneven-batch engine workload and the request-server workload (each can be skipped
+with its --no-... flag).
 """
 from __future__ import annotations
 
@@ -84,6 +85,8 @@ def parse(argv=None):
     ap.add_argument("--model-wave-stride", type=int, default=8,
                     help="the oracle's wave model runs on every k-th wavefront of each trace order")
     ap.add_argument("--no-shadow", action="store_true")
+    ap.add_argument("--no-packets", action="store_true",
+                    help="skip the table of wavefront-packet against per-lane trace launches by ray order")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch engine workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server workload")
     ap.add_argument("--no-grid", action="store_true", help="skip the frame workload's method grid")
@@ -172,6 +175,9 @@ def main(argv=None):
         shd, _ = W.spawn_shadow(prim, p_t, p_prim, tris_h, spec.lights)
         shadow = torch.from_numpy(shd).to(dev)
         log(f"{shadow.shape[0]} shadow rays")
+    packets = None
+    if not args.no_packets and shadow is not None:
+        packets = run_packets(H, bvh, torch.from_numpy(prim).to(dev), shadow)
     del prim, ph
 
     # ------------------------------------------------------------------ configuration per method
@@ -278,7 +284,8 @@ def main(argv=None):
                    if head in cuts else None)
 
     # any-hit (shadow) rays, each method with its secondary-ray key (cut, key length, skipped bits)
-    # and its trace options tuned on the shadow rays in its own order
+    # and its trace options tuned on the shadow rays in its own order (per-lane 4-wide launches and
+    # wavefront packets, which pay on these more coherent rays)
     shadow_res = None
     if shadow is not None:
         S = shadow.shape[0]
@@ -295,7 +302,7 @@ def main(argv=None):
             if args.tune:
                 run(m, rr=shadow, closest=False, out=occ, b=sb)     # leaves the order in sb["perm"]
                 s_opts = AT.tune_trace(bvh, shadow, sb["perm"] if sb else None, closest=False,
-                                       candidates=AT.WIDE)[0]
+                                       candidates=AT.WIDE + AT.PACKET)[0]
             times = []
             for s in range(args.warmup + args.steps):
                 a, b = ev(), ev()
@@ -344,6 +351,7 @@ def main(argv=None):
                     for m, r in results.items()},
         "cut_composition": composition,
         "shadow": shadow_res,
+        "packets": packets,
         "build_ms": round(build_ms, 2),
         "select_cut_ms": round(cut_ms, 2),
         "fetches": dict(model=oracle_leg["model"] if oracle_leg else None, kernel_counted=counted),
@@ -404,6 +412,9 @@ def compact_line(full: dict, args, workload: str) -> dict:
         "paper_exact_vs_nosort": speed("hcc_paper_exact", "nosort"),
         "cut_composition": full.get("cut_composition"),
     }
+    pk = full.get("packets")
+    if pk:
+        line["packet_vs_lane_ms"] = {k: [v["lane_ms"], v["packet_ms"]] for k, v in pk.items()}
     sh = full.get("shadow")
     if sh:
         line["shadow_mrays_s"] = {m: sh[m]["mrays_s"] for m in res if m in sh}
@@ -871,6 +882,35 @@ def run_bounces(H, args, bvh, tris_h, sec, rays):
             del prev_d
         prev, prev_d = nxt, rd
     del prev_d
+    return out
+
+
+def run_packets(H, bvh, prim, shadow) -> dict:
+    """Wavefront packets against per-lane launches, by ray order: the frame's primary rays in
+    pixel order (closest hit) and its shadow rays (any hit) in pixel order, HCC order (C = K = 32,
+    full sort; C = K = 16 sorted on the top 8 bits) and TwoPoint order (K = 32, full sort).  Each
+    entry: the fastest per-lane 4-wide launch and the fastest packet launch for that order, each
+    tuned over its candidates (trace time only; the order's encode and sort are not included).
+    A packet walks the union of its 64 rays' traversals, so its time follows the coherence the
+    order gives each wavefront (Section 3.1), while the per-lane launch barely depends on it."""
+    out = {}
+
+    def row(name, rays, perm, closest):
+        lane = AT.tune_trace(bvh, rays, perm, closest=closest, candidates=AT.WIDE)
+        pack = AT.tune_trace(bvh, rays, perm, closest=closest, candidates=AT.PACKET)
+        out[name] = dict(lane_ms=round(lane[1], 4), packet_ms=round(pack[1], 4),
+                         lane_opts=AT.opts_dict(lane[0]), packet_opts=AT.opts_dict(pack[0]))
+        log(f"packets {name}: per-lane {lane[1]:.3f} ms, packets {pack[1]:.3f} ms")
+
+    row("primary nosort", prim, None, True)
+    row("shadow nosort", shadow, None, False)
+    for name, mode, cut, k, skip in (("shadow hcc C=32 K=32", H.KEY_HCC, 32, 32, 0),
+                                     ("shadow hcc C=16 K=16 skip 8", H.KEY_HCC, 16, 16, 8),
+                                     ("shadow twopoint K=32", H.KEY_TWOPOINT, 0, 32, 0)):
+        cut_h = H.select_cut(bvh, cut) if mode == H.KEY_HCC else None
+        perm = H.sort_ex(H.encode(bvh, cut_h, mode, k, shadow), k, skip)
+        row(name, shadow, perm, False)
+        del perm
     return out
 
 

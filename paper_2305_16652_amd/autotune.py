@@ -26,7 +26,12 @@ PERSISTENT = [TraceOpts(64, s, 0, 1, r, c, 8192, f)
 # or the quantised nodes (flag 16), chunks dealt in order or spread over the order (flag 8)
 WIDE = [TraceOpts(64, 2, 0, 1, r, c, 8192, f | q | sp) for f in (2, 6) for q in (0, 16) for sp in (0, 8)
         for r in (24, 32) for c in (64, 128, 256)]
-DEFAULT_CANDIDATES = PLAIN + PERSISTENT + WIDE
+# wavefront packets over the 4-wide nodes (flag 32): exact or quantised nodes, chunks in order or
+# spread.  A packet costs one step per node of the union of its 64 rays' traversals, so these pay
+# only on coherent rays (primary rays, shadow rays towards one light, well ordered rays); on
+# diffuse secondary rays they are several times slower than the per-lane launches
+PACKET = [TraceOpts(0, 0, 0, 1, 0, 0, 8192, 2 | q | sp | 32) for q in (0, 16) for sp in (0, 8)]
+DEFAULT_CANDIDATES = PLAIN + PERSISTENT + WIDE + PACKET
 
 
 def opts_dict(o: TraceOpts) -> dict:

@@ -745,6 +745,25 @@ __device__ __forceinline__ void cswap_u(uint32_t& ka, uint32_t& ia, uint32_t& kb
     ib = i1;
 }
 
+// tri_test without its early exits: every lane of a packet runs the whole test anyway, and the
+// exits cost scalar exec-mask work per triangle.  Same operations in the same order, so the same
+// (t, u, v) wherever a hit is reported.
+__device__ __forceinline__ bool tri_test_flat(const Tri& tr, float ox, float oy, float oz, float dx, float dy,
+                                              float dz, float tmin, float tmax, float& t, float& u, float& v) {
+    const float v0x = tr.p.x, v0y = tr.p.y, v0z = tr.p.z;
+    const float e1x = tr.p.w, e1y = tr.q.x, e1z = tr.q.y;
+    const float e2x = tr.q.z, e2y = tr.q.w, e2z = tr.r.x;
+    const float px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    const float det = (e1x * px + e1y * py) + e1z * pz;
+    const float sx = ox - v0x, sy = oy - v0y, sz = oz - v0z;
+    const float inv = 1.0f / det;
+    u = ((sx * px + sy * py) + sz * pz) * inv;
+    const float qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+    v = ((dx * qx + dy * qy) + dz * qz) * inv;
+    t = ((e2x * qx + e2y * qy) + e2z * qz) * inv;
+    return (det != 0.0f) & (u >= 0.0f) & (u <= 1.0f) & (v >= 0.0f) & (u + v <= 1.0f) & (t > tmin) & (t < tmax);
+}
+
 template <bool kClosest>
 __global__ __launch_bounds__(64) void k_trace_packet(const Node4* __restrict__ wn, const Node4Q* __restrict__ qn,
                                                      const Tri* __restrict__ tris, uint32_t n_int,
@@ -779,10 +798,11 @@ __global__ __launch_bounds__(64) void k_trace_packet(const Node4* __restrict__ w
         uint32_t best_prim = kMissPrim;
         bool found = false;
 
-        auto test_tri = [&](const Tri& tr) {
+        // on the lanes with `on` set (no branch: the whole wavefront runs the test)
+        auto test_tri = [&](const Tri& tr, bool on) {
             const uint32_t prim = __float_as_uint(tr.r.y);
             float t, u, v;
-            const bool hit = tri_test(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v);
+            const bool hit = on & tri_test_flat(tr, ox, oy, oz, dx, dy, dz, tmin, tmax, t, u, v);
             if (!kClosest) {
                 found = found || hit;
             } else {
@@ -795,9 +815,11 @@ __global__ __launch_bounds__(64) void k_trace_packet(const Node4* __restrict__ w
             }
         };
 
-        // the walk, specialised on the (packet-uniform) form of the child test: 0 slab test on the
-        // exact nodes, 2 slab test / 3 selected planes on the quantised nodes
-        auto walk = [&](auto kind) {
+        // the walk, specialised on the (packet-uniform) form of the child test: 0 slab test / 1
+        // selected planes on the exact nodes, 2 slab test / 3 selected planes on the quantised nodes.
+        // w: the lane's own plane choice, or one shared by the packet (every ray with the same
+        // direction signs), which makes the choice a scalar one and the exact planes scalar loads
+        auto walk = [&](auto kind, const WideRay& w) {
             constexpr int kKind = decltype(kind)::value;
             PacketStack st;
             uint32_t sp = 0, node = 0;
@@ -809,19 +831,16 @@ __global__ __launch_bounds__(64) void k_trace_packet(const Node4* __restrict__ w
                 bool hh[4];
                 float tt[4];
                 if constexpr (kKind >= 2)
-                    wide_test_q<kKind == 3>(qn, node, wr, ox, oy, oz, ix, iy, iz, tmin, kClosest ? best_t : tmax, r, hh,
+                    wide_test_q<kKind == 3>(qn, node, w, ox, oy, oz, ix, iy, iz, tmin, kClosest ? best_t : tmax, r, hh,
                                             tt);
                 else
-                    wide_test<false>(wn, node, wr, ox, oy, oz, ix, iy, iz, tmin, kClosest ? best_t : tmax, r, hh, tt);
+                    wide_test<kKind == 1>(wn, node, w, ox, oy, oz, ix, iy, iz, tmin, kClosest ? best_t : tmax, r, hh, tt);
                 const uint32_t refs[4] = {r.x, r.y, r.z, r.w};
                 // leaves first: the hits they give shrink every lane's segment before the descent
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const bool hl = alive && hh[j] && (refs[j] & kWideLeaf);
-                    if (__ballot(hl) != 0) {
-                        const Tri tr = tris[refs[j] & ~kWideLeaf];
-                        if (hl && (kClosest || !found)) test_tri(tr);
-                    }
+                    if (__ballot(hl) != 0) test_tri(tris[refs[j] & ~kWideLeaf], hl && (kClosest || !found));
                 }
                 // internal children some lane hits, keyed by the entry distance of the lowest such
                 // lane (children that lane misses after those it hits, missed children last)
@@ -854,12 +873,27 @@ __global__ __launch_bounds__(64) void k_trace_packet(const Node4* __restrict__ w
                 node = id[0];
             }
         };
+        const uint64_t live = __ballot(valid);
+        if (live == 0) continue;
+        const bool all_fast = !slab && __ballot(valid && !wr.fast) == 0;
+        // the first valid lane's plane choice, and whether every valid lane makes the same one
+        const int src = __ffsll((unsigned long long)live) - 1;
+        WideRay shared;
+        shared.ex = __builtin_amdgcn_readfirstlane(__shfl(wr.ex, src, 64));
+        shared.ey = __builtin_amdgcn_readfirstlane(__shfl(wr.ey, src, 64));
+        shared.ez = __builtin_amdgcn_readfirstlane(__shfl(wr.ez, src, 64));
+        shared.fast = true;
+        const bool same = all_fast && __ballot(valid && (wr.ex != shared.ex || wr.ey != shared.ey ||
+                                                         wr.ez != shared.ez)) == 0;
         if (!qn) {
-            walk(std::integral_constant<int, 0>{});
-        } else if (!slab && __ballot(valid && !wr.fast) == 0) {
-            walk(std::integral_constant<int, 3>{});
+            if (same && n_int <= kWideFastNodes) walk(std::integral_constant<int, 1>{}, shared);
+            else walk(std::integral_constant<int, 0>{}, wr);
+        } else if (same) {
+            walk(std::integral_constant<int, 3>{}, shared);
+        } else if (all_fast) {
+            walk(std::integral_constant<int, 3>{}, wr);
         } else {
-            walk(std::integral_constant<int, 2>{});
+            walk(std::integral_constant<int, 2>{}, wr);
         }
         if (valid) {
             if (kClosest)

@@ -37,6 +37,8 @@ def test_every_trace_candidate_gives_the_oracle_hits(H, tiny):
     # the 4-wide candidates cover both child-box tests, with chunks dealt in order and spread
     assert {o.flags for o in AT.WIDE} == {H.TRACE_WIDE | s | q | sp for s in (0, H.TRACE_SLAB)
                                           for q in (0, H.TRACE_QUANT) for sp in (0, H.TRACE_SPREAD)}
+    assert {o.flags for o in AT.PACKET} == {H.TRACE_WIDE | H.TRACE_PACKET | q | sp for q in (0, H.TRACE_QUANT)
+                                            for sp in (0, H.TRACE_SPREAD)}
     for o in AT.DEFAULT_CANDIDATES + [best]:
         hits = H.trace(tiny["bvh"], tiny["rays"], opts=o).cpu().numpy()
         assert_closest(hits, tiny["ref"], tiny["sec"], tiny["spec"].tris)
