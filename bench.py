@@ -893,6 +893,7 @@ def run_packets(H, bvh, prim, shadow) -> dict:
     tuned over its candidates (trace time only; the order's encode and sort are not included).
     A packet walks the union of its 64 rays' traversals, so its time follows the coherence the
     order gives each wavefront (Section 3.1), while the per-lane launch barely depends on it."""
+    from paper_2305_16652_amd import autotune as AT
     out = {}
 
     def row(name, rays, perm, closest):

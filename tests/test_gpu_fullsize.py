@@ -72,7 +72,11 @@ def test_fullsize_bvh_and_cut(frame):
         assert np.array_equal(H.select_cut(bvh, c).export()[0], O.select_cut(ob, had, c))
 
 
-@pytest.mark.parametrize("opts", [BENCH_OPTS, WIDE_OPTS])
+# wavefront packets on the exact and the quantised nodes (bench.py's packet candidates)
+PACKET_OPTS = [(0, 0, 0, 1, 0, 0, 8192, 2 | 32), (0, 0, 0, 1, 0, 0, 8192, 2 | 16 | 8 | 32)]
+
+
+@pytest.mark.parametrize("opts", [BENCH_OPTS, WIDE_OPTS] + PACKET_OPTS)
 def test_fullsize_primary_hits_all_rays(frame, opts):
     H = frame["H"]
     hits = H.trace(frame["bvh"], torch.from_numpy(frame["prim"]).cuda(), opts=H.TraceOpts(*opts)).cpu().numpy()
@@ -130,3 +134,10 @@ def test_fullsize_shadow_any_hit(frame):
             assert_no_fewer_any(wide, occ)
         else:
             assert np.array_equal(wide, occ)
+    # packets test a superset of each ray's triangles: never fewer occluded rays than the per-lane
+    # launch, in the HCC order and in pixel order
+    for o in PACKET_OPTS:
+        for p in (perm, None):
+            pk = H.trace(bvh, rays, p, closest=False, opts=H.TraceOpts(*o)).cpu().numpy()
+            assert_no_fewer_any(pk, occ)
+            assert_any(pk, ref, idx=sample)
