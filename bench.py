@@ -121,7 +121,7 @@ def cut_composition(H, cut, n_tris: int, sorted_bits: int) -> dict:
 def main(argv=None):
     args = parse(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(rays would be sharded by contiguous ranges with a BVH replica per GPU); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
