@@ -20,6 +20,8 @@ WIDE = (64, 2, 0, 1, 32, 64, 0, 2)
 BVH2 = (64, 0, 0, 1, 32, 64, 0, 0)
 WIDE_SPREAD = (64, 2, 0, 1, 32, 64, 0, 2 | 8)     # chunks dealt spread over the order
 BVH2_SPREAD = (64, 0, 0, 1, 32, 64, 0, 8)
+PACKET = (0, 0, 0, 1, 0, 0, 0, 2 | 32)           # wavefront packets (chunks of 64 rays)
+PACKET_SPREAD = (0, 0, 0, 1, 0, 0, 0, 2 | 16 | 8 | 32)
 
 
 def _say(msg):
@@ -51,8 +53,8 @@ def _opts(H, base, chunk, waves):
     return H.TraceOpts(*base[:5], chunk, waves, base[7])
 
 
-@pytest.mark.parametrize("base", [WIDE, BVH2, WIDE_SPREAD, BVH2_SPREAD], ids=["wide", "bvh2", "wide-spread",
-                                                                            "bvh2-spread"])
+@pytest.mark.parametrize("base", [WIDE, BVH2, WIDE_SPREAD, BVH2_SPREAD, PACKET, PACKET_SPREAD],
+                         ids=["wide", "bvh2", "wide-spread", "bvh2-spread", "packet", "packet-spread"])
 def test_back_to_back_launches_of_changing_shape(H, tiny, base):
     sec, shd = torch.from_numpy(tiny["sec"]).cuda(), torch.from_numpy(tiny["shd"]).cuda()
     n = sec.shape[0]
@@ -130,3 +132,44 @@ def test_graph_captured_launch_replays(H, tiny):
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy().view(np.uint32), eager.view(np.uint32)), f"replay {rep}"
         assert np.array_equal(other.cpu().numpy().view(np.uint32), eager.view(np.uint32))
+
+
+def test_packet_and_per_lane_launches_share_the_counter(H, tiny):
+    """Packet launches (chunks of 64 rays) and per-lane launches (chunks of 64-256) alternate back
+    to back on one stream, through the stream's one counter slot: each must start from zero."""
+    sec = torch.from_numpy(np.tile(tiny["sec"], (3, 1))).cuda()
+    n = sec.shape[0]
+    want = H.trace(tiny["bvh"], sec, opts=H.TraceOpts(*WIDE)).cpu().numpy()
+    plan = [(PACKET, n, 0), (WIDE, n, 0), (PACKET_SPREAD, 4096, 0), (WIDE_SPREAD, n - 1, 0), (PACKET, 65, 3),
+            (BVH2, n, 0), (PACKET, n, 1), (WIDE, 200, 0)]
+    outs = [(m, H.trace(tiny["bvh"], sec[:m], opts=_opts(H, base, base[5], waves))) for base, m, waves in plan]
+    torch.cuda.synchronize()
+    for (m, out), (base, _, _) in zip(outs, plan):
+        got = out.cpu().numpy()
+        if base[7] & 32:
+            # packets test a superset of each ray's triangles: the oracle's bar on every ray
+            assert_closest(got, O.Hits(np.tile(tiny["ref_sec"].raw, (3, 1))[:m]), np.tile(tiny["sec"], (3, 1))[:m],
+                           tiny["spec"].tris)
+        else:
+            assert np.array_equal(got.view(np.uint32), want[:m].view(np.uint32)), (base, m)
+
+
+def test_graph_captured_packet_launch_replays(H, tiny):
+    shd = torch.from_numpy(tiny["shd"]).cuda()
+    n = shd.shape[0]
+    o = H.TraceOpts(*PACKET)
+    eager = H.trace(tiny["bvh"], shd, closest=False, opts=o).cpu().numpy()
+    assert_any(eager, tiny["ref_shd"])
+    out = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+    H.trace(tiny["bvh"], shd, closest=False, out=out, opts=o)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        H.trace(tiny["bvh"], shd, closest=False, out=out, opts=o)
+    for rep in range(4):
+        out.fill_(7)
+        g.replay()
+        other = H.trace(tiny["bvh"], shd, closest=False, opts=o)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), f"replay {rep}"
+        assert np.array_equal(other.cpu().numpy(), eager)
