@@ -32,6 +32,10 @@ def _full():
         "rays": 16588800, "headline": "hcc", "methods": methods,
         "cut_composition": dict(sorted_nodes=32, leaves=3, distinct_boxes=30),
         "shadow": dict(rays=33177600, **{m: dict(ms=7.9, mrays_s=4158.12) for m in methods}),
+        "packets": {name: dict(lane_ms=6.5887, packet_ms=8.4635, lane_opts=methods["hcc"]["trace_opts"],
+                               packet_opts=methods["hcc"]["trace_opts"])
+                    for name in ("primary nosort", "shadow nosort", "shadow hcc C=32 K=32",
+                                 "shadow hcc C=16 K=16 skip 8", "shadow twopoint K=32")},
         "fetches": dict(model={m: fetch for m in methods}, kernel_counted=None),
         "frame_bounces": {b: dict(rays=16588000, rows=brows) for b in ("2", "3")},
         "batched": dict(engine_hcc_mrays_s=1122.5, plain_hcc_mrays_s=353.5, engine_nosort_mrays_s=1138.0,
@@ -64,6 +68,8 @@ def test_compact_line_fields_and_size():
     assert "hcc_paper_exact" in line["methods"] and line["paper_exact_vs_nosort"] == 1.0
     assert line["sort32"]["bytes_per_key"] == 68 and 0 < line["sort32"]["frac"] < 1
     assert line["shadow_speedup_vs_nosort"] == 1.0
+    assert line["packet_vs_lane_ms"]["shadow twopoint K=32"] == [6.5887, 8.4635]
+    assert len(line["packet_vs_lane_ms"]) == 5
     # three bounces: (16588800 + 2 x 16588000) rays over 5.55555 + 6.4 + 6.4 ms for NoSort
     assert abs(line["frame_3_bounces_mrays_s"]["nosort"] - 49764800 / 18.35555e-3 / 1e6) < 0.1
     assert set(line["frame_3_bounces_mrays_s"]) == {"nosort", "twopoint", "hcc"}
