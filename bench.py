@@ -474,6 +474,13 @@ def compact_line(full: dict, args, workload: str) -> dict:
                 ratio[bn] = round(max(hcc) / base[0], 3)
         if ratio:
             line["drift_hcc_vs_nosort"] = ratio
+        sh = d.get("shadow")
+        if sh:
+            base = [r["mrays_s"] for r in sh["rows"] if r["method"] == "nosort"]
+            line["drift_shadow_best_mrays_s"] = list(max((r["mrays_s"], r["method"]) for r in sh["rows"]))
+            hcc = [r["mrays_s"] for r in sh["rows"] if r["method"].startswith("hcc")]
+            if hcc and base:
+                line["drift_shadow_hcc_vs_nosort"] = round(max(hcc) / base[0], 3)
     line["roofline"] = full.get("roofline")
     line["cpu_baseline"] = full.get("cpu_baseline")
     line["full_record"] = args.full_out
@@ -915,10 +922,31 @@ def run_packets(H, bvh, prim, shadow) -> dict:
     return out
 
 
+def drift_shadow_rows(H, bvh, rd, args) -> dict:
+    """Any-hit rows of the drift scene's shadow rays: per-lane 4-wide trace options tuned on the
+    rays in pixel order (NoSort) and in TwoPoint order (every reordered row), as for the diffuse
+    rows; encode + sort included in each row's rate."""
+    from paper_2305_16652_amd import autotune as AT
+    opts = AT.tune_trace(bvh, rd, None, closest=False, candidates=AT.WIDE)[0]
+    tperm = H.sort(H.encode(bvh, None, H.KEY_TWOPOINT, 32, rd), 32)
+    sorted_opts = AT.tune_trace(bvh, rd, tperm, closest=False, candidates=AT.WIDE)[0]
+    del tperm
+    rows = [measure_variant(H, bvh, rd, dict(mode="nosort"), opts, args.drift_reps, closest=False)]
+    for v in (dict(mode="twopoint", K=32), dict(mode="hcc", C=16, K=16), dict(mode="hcc", C=32, K=32),
+              dict(mode="mlhcc", top=16, low=16, K=32)):
+        rows.append(measure_variant(H, bvh, rd, v, sorted_opts, args.drift_reps, closest=False))
+    log(f"drift shadow ({rd.shape[0]} rays): " +
+        "; ".join(f"{r['method']} {r['mrays_s']:.0f} Mrays/s (trace {r['trace_ms']:.2f} ms)" for r in rows))
+    return dict(rays=int(rd.shape[0]), rows=rows, trace_opts=AT.opts_dict(opts),
+                sorted_trace_opts=AT.opts_dict(sorted_opts))
+
+
 def run_drift(H, args):
     """Boundary-drift workload: 10M thin triangles in 64 Gaussian clusters inside the unit room,
     1920x1080x4 camera, two diffuse bounces.  For each bounce: NoSort, and TwoPoint, HCC (C = K)
-    and the regular grid at K in {16, 24, 32, 48, 64}, with node fetches/ray and ANC."""
+    and the regular grid at K in {16, 24, 32, 48, 64}, with node fetches/ray and ANC.  Also the
+    any-hit shadow rays of the camera rays' hits (two lights): NoSort, TwoPoint K = 32, HCC C = K
+    = 16 and 32, MLHCC32, each with encode + sort included."""
     import torch
     import workloads as W
     dev = torch.device("cuda:0")
@@ -937,6 +965,10 @@ def run_drift(H, args):
         h = H.trace(bvh, rd, opts=opts).cpu().numpy()
         del rd
         t, prim = h[:, 0].copy(), h[:, 1].copy().view(np.uint32)
+        if bounce == 1 and not args.no_shadow:
+            shd, _ = W.spawn_shadow(rays, t, prim, spec.tris, spec.lights)
+            out["shadow"] = drift_shadow_rows(H, bvh, torch.from_numpy(shd).to(dev), args)
+            del shd
         rays, _ = W.spawn_diffuse(rays, t, prim, spec.tris, seed=92, bounce=bounce - 1)
         rd = torch.from_numpy(rays).to(dev)
         # 4-wide trace options per bounce: tuned on the unsorted rays for NoSort, and on one

@@ -45,7 +45,11 @@ def _full():
                              for rho in ("0.5", "0.8", "0.95")}),
         "drift": dict(bounces={b: dict(rows=rows + [dict(method="nosort", mrays_s=500.0),
                                                     dict(method="hcc C=16 K=16", mrays_s=535.0)])
-                               for b in ("1", "2")}),
+                               for b in ("1", "2")},
+                      shadow=dict(rows=[dict(method="nosort", mrays_s=700.0), dict(method="twopoint K=32", mrays_s=820.0),
+                                        dict(method="hcc C=16 K=16", mrays_s=735.0),
+                                        dict(method="hcc C=32 K=32", mrays_s=742.0),
+                                        dict(method="mlhcc32 (16+16)", mrays_s=760.0)])),
         "roofline": dict(bound="hbm", achieved=6924.4, peak=8000.0, unit="GB/s", frac=0.8656, traffic=10334608383,
                          kernel="k_trace_wide<closest>", launch_ms=5.3101, bytes_per_ray=2222.7,
                          numerator="oracle wave model (BVH2 nodes, 64-lane waves)", kernel_counted_bytes_per_ray=2300.1),
@@ -70,6 +74,8 @@ def test_compact_line_fields_and_size():
     assert line["shadow_speedup_vs_nosort"] == 1.0
     assert line["packet_vs_lane_ms"]["shadow twopoint K=32"] == [6.5887, 8.4635]
     assert len(line["packet_vs_lane_ms"]) == 5
+    assert line["drift_shadow_hcc_vs_nosort"] == 1.06
+    assert line["drift_shadow_best_mrays_s"] == [820.0, "twopoint K=32"]
     # three bounces: (16588800 + 2 x 16588000) rays over 5.55555 + 6.4 + 6.4 ms for NoSort
     assert abs(line["frame_3_bounces_mrays_s"]["nosort"] - 49764800 / 18.35555e-3 / 1e6) < 0.1
     assert set(line["frame_3_bounces_mrays_s"]) == {"nosort", "twopoint", "hcc"}
